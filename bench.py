@@ -1,0 +1,166 @@
+"""Throughput of the GAP-LA hot path on one MI355X: nets layer-assigned per second.
+
+One step = the whole path over the 2,000,000-net workload (1024x1024 GCells, 12
+layers): I outer iterations of [Elmore forward -> timing weights -> la_assign
+with R negotiation rounds], then the Elmore timing of the final assignment.
+nets/s = nets x R x I / step time.  Inputs are resident in HBM before timing.
+
+The batched+adjoint form (persistent per-batch DP kernels in a hipGraph,
+weights from the Elmore reverse sweep) is the reported value; the plain
+per-level-launch form with Eq. 4/5 weights runs the same schedule beside it.
+The CPU oracle is timed on a bounded sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+R_ROUNDS, I_ITERS = 5, 3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--nets", type=int, default=None, help="truncate the workload (testing only)")
+    ap.add_argument("--forms", default="batched,plain")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true", help="per-kernel event timing (roofline)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2507_13375_amd as la
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    inst = gen.config(args.config, num_nets=args.nets)
+    log("generated c%d: %d nets %d input nodes in %.1fs" % (args.config, inst.num_nets, inst.num_nodes,
+                                                            time.time() - t0))
+    t0 = time.time()
+    b = la.la_build_batch(inst)
+    torch.cuda.synchronize()
+    log("la_build_batch: %d LA nodes, %d sinks, %d levels, %.1fs" % (b.nodes, b.sinks, b.levels, time.time() - t0))
+
+    dev = "cuda"
+    E = inst.X * inst.Y * inst.L
+    H = torch.zeros(E, dtype=torch.int32, device=dev)
+    layers = torch.zeros(b.nodes, dtype=torch.uint8, device=dev)
+    delay = torch.zeros(b.sinks, dtype=torch.float32, device=dev)
+    sw = torch.zeros(b.nodes, dtype=torch.uint16, device=dev)
+    pw = torch.zeros(b.sinks, dtype=torch.uint16, device=dev)
+    lam = torch.zeros(b.nodes, dtype=torch.int32, device=dev)
+    tier = torch.zeros(b.nets, dtype=torch.uint8, device=dev)
+
+    def step(form):
+        la.la_reset(b)
+        H.zero_()
+        mode = la.LA_WEIGHTS_ADJOINT if form == la.LA_FORM_BATCHED else la.LA_WEIGHTS_PLAIN
+        for _ in range(I_ITERS):
+            la.la_elmore(b, delay)
+            la.la_timing_weights(b, delay, mode, sw, pw, lam, tier)
+            la.la_assign(b, sw, pw, lam, H, layers, net_tier=tier, num_tiers=11, rounds=R_ROUNDS, form=form)
+        la.la_elmore(b, delay)
+
+    results = {}
+    for name in args.forms.split(","):
+        form = la.LA_FORM_BATCHED if name == "batched" else la.LA_FORM_PLAIN
+        try:
+            for _ in range(args.warmup):
+                step(form)
+            torch.cuda.synchronize()
+        except la.LAError as e:
+            log("form %s unavailable: %s" % (name, e))
+            continue
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(args.steps):
+            step(form)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        tns, wns = la.la_timing_summary(b, delay)
+        results[name] = dict(ms=ms, nets_per_s=inst.num_nets * R_ROUNDS * I_ITERS / (ms * 1e-3), tns=tns, wns=wns)
+        log("form %s: %.2f ms/step, %.3e nets/s, TNS %.1f ps, WNS %.2f ps" % (name, ms, results[name]["nets_per_s"],
+                                                                          tns, wns))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(inst)
+
+    main_form = "batched" if "batched" in results else "plain"
+    r = results[main_form]
+    out = {
+        "metric": "nets layer-assigned/sec (DP+Elmore) at 2M nets; batched vs plain, same GPU",
+        "value": r["nets_per_s"],
+        "unit": "nets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64+fp32",
+        "data": "synthetic",
+        "config": {"workload": "c%d: %d nets, %dx%d GCells x %d layers, %s form, R=%d rounds x I=%d iterations"
+                               % (args.config, inst.num_nets, inst.X, inst.Y, inst.L,
+                                  "batched+adjoint" if main_form == "batched" else "plain", R_ROUNDS, I_ITERS),
+                   "nets": inst.num_nets, "la_nodes": b.nodes, "rounds": R_ROUNDS, "iterations": I_ITERS,
+                   "form": main_form},
+        "forms": {k: {"nets_per_s": v["nets_per_s"], "ms_per_step": v["ms"], "tns_ps": v["tns"], "wns_ps": v["wns"]}
+                  for k, v in results.items()},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    if "batched" in results and "plain" in results:
+        out["batched_over_plain"] = results["batched"]["nets_per_s"] / results["plain"]["nets_per_s"]
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(inst):
+    """The oracle (as it stands) on a bounded sample: one round, one iteration of the plain
+    pipeline over the first nets of the same workload."""
+    import numpy as np
+
+    import gen
+    import oracle
+
+    n = min(inst.num_nets, 400000)
+    sub = gen.config(4, num_nets=n) if inst.name == "c4" or inst.name == "c3" else inst
+    t0 = time.time()
+    T = oracle.Tree(sub)
+    P0 = oracle.Params(T)
+    w = oracle.plain_weights(T, P0)
+    P = oracle.Params(T, seg_w=w["seg_w"], pin_w=w["pin_w"], lam=w["lam"])
+    st = oracle.State(T)
+    lay, _, _, _ = oracle.assign(T, P, st, w["tier"], rounds=1)
+    R, C = oracle.rc(T, P, lay)
+    oracle.elmore(T, R, C)
+    dt = time.time() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count()
+    log("cpu oracle: %d nets, 1 round x 1 iteration in %.1fs on %d threads" % (n, dt, cores))
+    return {"value": n / dt, "unit": "nets/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d nets of the workload, plain weights, 1 round x 1 iteration, then Elmore" % n}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,256 @@
+// C ABI entry points (include/gapla.h): argument checks, dispatch, state handling.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "la_internal.h"
+
+namespace gapla {
+
+static thread_local std::string g_last_error;
+
+la_status set_error(la_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+la_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? LA_ERR_OOM : LA_ERR_HIP;
+}
+
+la_status build_batch(const la_nets *, const la_grid *, const la_layer_rc *, const uint8_t *, void *, la_batch **);
+la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers);
+la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers);
+la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t *seg_w, uint16_t *pin_w,
+                         int32_t *lam, uint8_t *tier);
+la_status timing_summary(la_batch *b, const float *delay, double *tns, double *wns);
+la_status zero_i32(la_batch *b, int32_t *p, int64_t n);
+la_status interleave_vias(la_batch *b, uint8_t *out);
+
+static la_status set_device(const la_batch *b)
+{
+    int cur = -1;
+    LA_HIP(hipGetDevice(&cur));
+    if (cur != b->device) LA_HIP(hipSetDevice(b->device));
+    return LA_OK;
+}
+
+}  // namespace gapla
+
+using namespace gapla;
+
+extern "C" {
+
+const char *la_status_str(la_status s)
+{
+    switch (s) {
+    case LA_OK: return "LA_OK";
+    case LA_ERR_INVALID_ARG: return "LA_ERR_INVALID_ARG";
+    case LA_ERR_BAD_TREE: return "LA_ERR_BAD_TREE";
+    case LA_ERR_RANGE: return "LA_ERR_RANGE";
+    case LA_ERR_OOM: return "LA_ERR_OOM";
+    case LA_ERR_HIP: return "LA_ERR_HIP";
+    case LA_ERR_STATE: return "LA_ERR_STATE";
+    }
+    return "LA_ERR_UNKNOWN";
+}
+
+const char *la_last_error(void) { return g_last_error.c_str(); }
+
+la_status la_default_cong_lut(int32_t L, const double *ofw, int32_t *out)
+{
+    if (L < 1 || L > kMaxL || !out) return set_error(LA_ERR_INVALID_ARG, "la_default_cong_lut: bad L or out");
+    for (int l = 0; l < L; ++l) {
+        const double w = ofw ? ofw[l] : 1.0;
+        for (int z = 0; z < 2; ++z) {
+            const double s = z == 0 ? 0.5 : 1.5;
+            for (int i = 0; i < kNDelta; ++i) {
+                const double d = (double)(i + kDeltaMin);
+                const double v = 1024.0 * w * (std::exp(s * (d + 1.0)) - std::exp(s * d));
+                out[(l * 2 + z) * kNDelta + i] = v >= (double)kLutSat ? kLutSat : (int32_t)std::nearbyint(v);
+            }
+        }
+    }
+    return LA_OK;
+}
+
+la_status la_build_batch(const la_nets *nets, const la_grid *grid, const la_layer_rc *layer_rc,
+                         const uint8_t *edge_caps, void *stream, la_batch **out)
+{
+    return build_batch(nets, grid, layer_rc, edge_caps, stream, out);
+}
+
+la_status la_batch_info(const la_batch *b, la_info *o)
+{
+    if (!b || !o) return set_error(LA_ERR_INVALID_ARG, "la_batch_info: NULL argument");
+    o->nets = b->nets;
+    o->nodes = b->nodes;
+    o->sinks = b->sinks;
+    o->rc_edges = b->nodes + b->sinks;
+    o->grid_edges = b->E;
+    o->levels = b->levels;
+    o->max_net_nodes = b->max_net_nodes;
+    o->gcell_edges = b->gcell_edges;
+    o->node_parent = b->parent;
+    o->node_net = b->net;
+    o->sink_node = b->sink_node;
+    return LA_OK;
+}
+
+la_status la_assign(la_batch *b, const la_weights *w, int32_t *history, uint8_t *out_layers)
+{
+    if (!b || !w || !history) return set_error(LA_ERR_INVALID_ARG, "la_assign: NULL batch, weights or history");
+    if (!w->seg_w_q10 || !w->lambda_mohm || (b->sinks > 0 && !w->pin_w_q10))
+        return set_error(LA_ERR_INVALID_ARG, "la_assign: weight arrays must be given");
+    if (w->w_cong < 0 || w->w_cap < 0 || w->w_d < 0 || w->w_via < 0 || w->rounds < 1 || w->hist_inc < 0)
+        return set_error(LA_ERR_INVALID_ARG, "la_assign: weights must be >= 0 and rounds >= 1");
+    if (w->form != LA_FORM_PLAIN && w->form != LA_FORM_BATCHED)
+        return set_error(LA_ERR_INVALID_ARG, "la_assign: unknown form");
+    if (w->net_tier && (w->num_tiers < 1 || w->num_tiers > 256))
+        return set_error(LA_ERR_INVALID_ARG, "la_assign: num_tiers must be in 1..256");
+    const double bound = (double)w->w_cong * b->bnd_cong + (double)w->w_cap * b->bnd_cap +
+                         (double)w->w_via * b->bnd_via + (double)w->w_d * b->bnd_d;
+    if (!(bound < 4.0e18) || w->w_d >= (int64_t(1) << 20))
+        return set_error(LA_ERR_RANGE, "la_assign: weights could overflow a net's int64 cost");
+    la_status s = set_device(b);
+    if (s != LA_OK) return s;
+    const int32_t *lut = w->cong_lut ? w->cong_lut : b->lut;
+    if (b->nodes == 0) return LA_OK;
+    s = (w->form == LA_FORM_PLAIN) ? assign_plain(b, w, history, lut, out_layers)
+                                   : assign_batched(b, w, history, lut, out_layers);
+    if (s != LA_OK) return s;
+    return launch_rc_from_layers(b);
+}
+
+la_status la_vias(la_batch *b, uint8_t *out)
+{
+    if (!b || !out) return set_error(LA_ERR_INVALID_ARG, "la_vias: NULL argument");
+    return interleave_vias(b, out);
+}
+
+la_status la_demand(la_batch *b, int32_t *out)
+{
+    if (!b || !out) return set_error(LA_ERR_INVALID_ARG, "la_demand: NULL argument");
+    LA_HIP(hipMemcpyAsync(out, b->D, b->E * sizeof(int32_t), hipMemcpyDeviceToDevice, b->stream));
+    return LA_OK;
+}
+
+la_status la_reset(la_batch *b)
+{
+    if (!b) return set_error(LA_ERR_INVALID_ARG, "la_reset: NULL batch");
+    la_status s = zero_i32(b, b->D, b->E);
+    if (s != LA_OK) return s;
+    LA_HIP(hipMemsetAsync(b->cur_layer, 0, b->nodes, b->stream));
+    b->has_prev = false;
+    b->fwd_done = b->bwd_done = false;
+    return launch_rc_pre(b);
+}
+
+la_status la_batch_rc(la_batch *b, float **R, float **C)
+{
+    if (!b || !R || !C) return set_error(LA_ERR_INVALID_ARG, "la_batch_rc: NULL argument");
+    *R = b->R;
+    *C = b->C;
+    return LA_OK;
+}
+
+la_status la_elmore(la_batch *b, float *out_delay)
+{
+    if (!b || (!out_delay && b->sinks)) return set_error(LA_ERR_INVALID_ARG, "la_elmore: NULL argument");
+    return elmore_forward(b, b->R, b->C, out_delay);
+}
+
+la_status la_elmore_rc(la_batch *b, const float *R, const float *C, float *out_delay)
+{
+    if (!b || !R || !C || (!out_delay && b->sinks)) return set_error(LA_ERR_INVALID_ARG, "la_elmore_rc: NULL argument");
+    return elmore_forward(b, R, C, out_delay);
+}
+
+la_status la_elmore_backward(la_batch *b, const float *dSlack, float *out_dR, float *out_dC)
+{
+    if (!b || (!dSlack && b->sinks)) return set_error(LA_ERR_INVALID_ARG, "la_elmore_backward: NULL argument");
+    return elmore_backward(b, dSlack, true, out_dR, out_dC);
+}
+
+la_status la_timing_summary(la_batch *b, const float *delay, double *tns, double *wns)
+{
+    if (!b || !tns || !wns || (!delay && b->sinks)) return set_error(LA_ERR_INVALID_ARG, "la_timing_summary: NULL");
+    return timing_summary(b, delay, tns, wns);
+}
+
+la_status la_timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t *seg_w, uint16_t *pin_w,
+                            int32_t *lam, uint8_t *tier)
+{
+    if (!b || !seg_w || !lam || !tier || (b->sinks && (!delay || !pin_w)))
+        return set_error(LA_ERR_INVALID_ARG, "la_timing_weights: NULL argument");
+    if (mode != LA_WEIGHTS_PLAIN && mode != LA_WEIGHTS_ADJOINT)
+        return set_error(LA_ERR_INVALID_ARG, "la_timing_weights: unknown mode");
+    return timing_weights(b, delay, mode, seg_w, pin_w, lam, tier);
+}
+
+static const uint32_t kStateMagic = 0x4c415354u;   // "LAST"
+
+la_status la_save_state(la_batch *b, void *host_buf, size_t *bytes)
+{
+    if (!b || !bytes) return set_error(LA_ERR_INVALID_ARG, "la_save_state: NULL argument");
+    const size_t need = 16 + (size_t)b->E * sizeof(int32_t) + (size_t)b->nodes;
+    if (!host_buf) {
+        *bytes = need;
+        return LA_OK;
+    }
+    if (*bytes < need) return set_error(LA_ERR_INVALID_ARG, "la_save_state: buffer too small");
+    uint8_t *p = (uint8_t *)host_buf;
+    uint32_t hdr[4] = {kStateMagic, (uint32_t)b->has_prev, (uint32_t)b->E, (uint32_t)b->nodes};
+    memcpy(p, hdr, 16);
+    LA_HIP(hipMemcpyAsync(p + 16, b->D, b->E * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    LA_HIP(hipMemcpyAsync(p + 16 + b->E * sizeof(int32_t), b->cur_layer, b->nodes, hipMemcpyDeviceToHost, b->stream));
+    LA_HIP(hipStreamSynchronize(b->stream));
+    *bytes = need;
+    return LA_OK;
+}
+
+la_status la_load_state(la_batch *b, const void *host_buf, size_t bytes)
+{
+    if (!b || !host_buf) return set_error(LA_ERR_INVALID_ARG, "la_load_state: NULL argument");
+    const size_t need = 16 + (size_t)b->E * sizeof(int32_t) + (size_t)b->nodes;
+    const uint8_t *p = (const uint8_t *)host_buf;
+    uint32_t hdr[4];
+    if (bytes < need) return set_error(LA_ERR_INVALID_ARG, "la_load_state: buffer too small");
+    memcpy(hdr, p, 16);
+    if (hdr[0] != kStateMagic || hdr[2] != (uint32_t)b->E || hdr[3] != (uint32_t)b->nodes)
+        return set_error(LA_ERR_INVALID_ARG, "la_load_state: state of a different batch");
+    LA_HIP(hipMemcpyAsync(b->D, p + 16, b->E * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    LA_HIP(hipMemcpyAsync(b->cur_layer, p + 16 + b->E * sizeof(int32_t), b->nodes, hipMemcpyHostToDevice, b->stream));
+    LA_HIP(hipStreamSynchronize(b->stream));
+    b->has_prev = hdr[1] != 0;
+    return b->has_prev ? launch_rc_from_layers(b) : launch_rc_pre(b);
+}
+
+la_status la_sync(la_batch *b)
+{
+    if (!b) return set_error(LA_ERR_INVALID_ARG, "la_sync: NULL batch");
+    LA_HIP(hipStreamSynchronize(b->stream));
+    return LA_OK;
+}
+
+void la_free_batch(la_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    void *ptrs[] = {b->parent, b->ch_ptr, b->ch, b->net, b->net_ptr, b->len, b->g0, b->cpin, b->sink_id,
+                    b->sink_node, b->net_sink_ptr, b->rest, b->budget_fs, b->rdrv, b->dir, b->flags,
+                    b->level_nodes, b->level_ptr, b->height, b->caps, b->D, b->cur_layer, b->vlo, b->vhi,
+                    b->F, b->KA, b->S, b->bt, b->sel, b->bucket_nodes, b->bucket_cnt, b->bucket_cur,
+                    b->chg_node, b->chg_count, b->chg_old, b->chg_new, b->lut, b->R, b->C, b->el_S,
+                    b->el_Slo, b->el_t, b->el_tlo, b->el_G, b->el_Glo, b->el_Sig, b->el_Siglo, b->slack,
+                    b->scratch_f, b->wns_bits, b->red};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete b;
+}
+
+}  // extern "C"

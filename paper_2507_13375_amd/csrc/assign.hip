@@ -1,0 +1,268 @@
+// Tree dynamic program of Alg. 3 with the look-ahead of Sec. III-D, trace-back of
+// Alg. 4, demand commit and history update -- the plain form, in the shape of
+// the paper's Alg. 2: for every batch, one launch per tree level bottom-up and
+// one per level top-down, DP state in HBM between launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "dp_device.h"
+#include "la_internal.h"
+
+namespace gapla {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t n)
+{
+    int64_t g = (n + kBlock - 1) / kBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535 * 8));
+}
+
+__global__ void k_dp_level(DPArgs a, const int32_t *nodes, int32_t cnt)
+{
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = tid / a.NA;
+    const int j = (int)(tid - i * a.NA);
+    if (i >= cnt) return;
+    const int32_t n = nodes[i];
+    const bool root = a.T.flags[n] & kRoot;
+    int l;
+    if (root) {
+        if (j != 0) return;
+        l = 0;
+    } else {
+        const int d = a.T.dir[n];
+        if (j >= a.tab.nA[d]) return;
+        l = a.tab.lay[d][j];
+    }
+    dp_node_layer(a, n, l, j, root);
+}
+
+// Alg. 4: each node takes the layer its parent recorded for the parent's entering layer.
+__global__ void k_trace_level(DPArgs a, const int32_t *nodes, int32_t cnt, uint8_t *cur, uint8_t *vlo, uint8_t *vhi,
+                              uint8_t *out_layers, int has_prev, int32_t *chg_node, uint8_t *chg_old,
+                              uint8_t *chg_new, int32_t *chg_count)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int32_t n = nodes[i];
+    trace_node(a, n, cur, vlo, vhi, out_layers, has_prev, chg_node, chg_old, chg_new, chg_count);
+}
+
+__global__ void k_zero_i32(int32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// demand moves of the segments whose layer changed (HBM atomics; integer, so order-free)
+__global__ void k_commit(TreeDev T, LayerTab tab, const int32_t *chg_node, const uint8_t *chg_old,
+                         const uint8_t *chg_new, const int32_t *chg_count, int32_t *D)
+{
+    const int32_t cnt = *chg_count;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+        const int32_t n = chg_node[i];
+        const int o = chg_old[i], nw = chg_new[i];
+        const int32_t step = T.dir[n] == 0 ? tab.L : tab.X * tab.L;
+        int32_t g = T.g0[n];
+        for (int32_t k = 0; k < T.len[n]; ++k, g += step) {
+            if (o != 255) atomicAdd(&D[g + o], -1);
+            atomicAdd(&D[g + nw], 1);
+        }
+    }
+}
+
+__global__ void k_history(const int32_t *D, const uint8_t *caps, int32_t *H, int64_t E, int32_t inc)
+{
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < E; g += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t over = D[g] - (int32_t)caps[g];
+        if (over > 0) {
+            const int64_t h = (int64_t)H[g] + (int64_t)inc * over;
+            H[g] = (int32_t)(h > kHistSat ? kHistSat : h);
+        }
+    }
+}
+
+__global__ void k_bucket_count(TreeDev T, const int32_t *height, const uint8_t *tier, int32_t ntier, int32_t levels,
+                               int32_t *counts, int32_t *bad)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x) {
+        const int t = tier ? tier[T.net[v]] : 0;
+        if (t >= ntier) {
+            atomicAdd(bad, 1);
+            continue;
+        }
+        atomicAdd(&counts[(int64_t)t * levels + height[v]], 1);
+    }
+}
+
+__global__ void k_bucket_scatter(TreeDev T, const int32_t *height, const uint8_t *tier, int32_t ntier, int32_t levels,
+                                 int32_t *cursor, int32_t *out)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x) {
+        const int t = tier ? tier[T.net[v]] : 0;
+        if (t >= ntier) continue;
+        const int32_t pos = atomicAdd(&cursor[(int64_t)t * levels + height[v]], 1);
+        out[pos] = (int32_t)v;
+    }
+}
+
+__global__ void k_interleave(const uint8_t *lo, const uint8_t *hi, uint8_t *out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        out[2 * i] = lo[i];
+        out[2 * i + 1] = hi[i];
+    }
+}
+
+}  // namespace
+
+la_status interleave_vias(la_batch *b, uint8_t *out)
+{
+    hipLaunchKernelGGL(k_interleave, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, b->vlo, b->vhi, out,
+                       b->nodes);
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+la_status assign_batched(la_batch *, const la_weights *, int32_t *, const int32_t *, uint8_t *)
+{
+    return set_error(LA_ERR_INVALID_ARG, "batched form not available in this build");
+}
+
+DPArgs make_dp_args(la_batch *b, const la_weights *w, const int32_t *H, const int32_t *lut)
+{
+    DPArgs a;
+    a.T = tree_view(b);
+    a.tab = b->tab;
+    a.w.w_cong = w->w_cong;
+    a.w.w_cap = w->w_cap;
+    a.w.w_d = w->w_d;
+    a.w.w_via = w->w_via;
+    a.w.seg_w = w->seg_w_q10;
+    a.w.pin_w = w->pin_w_q10;
+    a.w.lam = w->lambda_mohm;
+    a.w.lut = lut;
+    a.w.self_excl = b->has_prev ? 1 : 0;
+    a.D = b->D;
+    a.caps = b->caps;
+    a.H = H;
+    a.prev = b->cur_layer;
+    a.F = b->F;
+    a.KA = b->KA;
+    a.S = b->S;
+    a.bt = b->bt;
+    a.sel = b->sel;
+    a.NA = b->NAmax;
+    return a;
+}
+
+la_status commit_changed(la_batch *b)
+{
+    hipLaunchKernelGGL(k_commit, dim3(1024), dim3(kBlock), 0, b->stream, tree_view(b), b->tab, b->chg_node,
+                       b->chg_old, b->chg_new, b->chg_count, b->D);
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+la_status zero_i32(la_batch *b, int32_t *p, int64_t n)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(n)), dim3(kBlock), 0, b->stream, p, n);
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+la_status history_update(la_batch *b, int32_t *H, int32_t inc)
+{
+    hipLaunchKernelGGL(k_history, dim3(grid_for(b->E)), dim3(kBlock), 0, b->stream, b->D, b->caps, H, b->E, inc);
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+// Group nodes by (batch, height); returns the per-bucket counts on the host.
+la_status bucket_nodes(la_batch *b, const uint8_t *tier, int32_t ntier, std::vector<int32_t> &counts)
+{
+    const int32_t Hh = b->levels;
+    const size_t need = (size_t)ntier * Hh;
+    if (need + 1 > b->bucket_cap) {
+        if (b->bucket_cnt) (void)hipFree(b->bucket_cnt);
+        if (b->bucket_cur) (void)hipFree(b->bucket_cur);
+        b->bucket_cnt = b->bucket_cur = nullptr;
+        if (hipMalloc((void **)&b->bucket_cnt, (need + 1) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void **)&b->bucket_cur, (need + 1) * sizeof(int32_t)) != hipSuccess)
+            return set_error(LA_ERR_OOM, "bucket allocation failed");
+        b->bucket_cap = need + 1;
+    }
+    la_status s = zero_i32(b, b->bucket_cnt, (int64_t)need + 1);
+    if (s != LA_OK) return s;
+    const TreeDev T = tree_view(b);
+    hipLaunchKernelGGL(k_bucket_count, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->height, tier,
+                       ntier, Hh, b->bucket_cnt, b->bucket_cnt + need);
+    LA_HIP(hipGetLastError());
+    counts.assign(need + 1, 0);
+    LA_HIP(hipMemcpyAsync(counts.data(), b->bucket_cnt, (need + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          b->stream));
+    LA_HIP(hipStreamSynchronize(b->stream));
+    if (counts[need] != 0)
+        return set_error(LA_ERR_INVALID_ARG, "net_tier holds a batch index >= num_tiers");
+    counts.pop_back();
+    std::vector<int32_t> off(need, 0);
+    int64_t acc = 0;
+    for (size_t i = 0; i < need; ++i) {
+        off[i] = (int32_t)acc;
+        acc += counts[i];
+    }
+    LA_HIP(hipMemcpyAsync(b->bucket_cur, off.data(), need * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->height, tier,
+                       ntier, Hh, b->bucket_cur, b->bucket_nodes);
+    LA_HIP(hipGetLastError());
+    // the cursor copy must finish before `off` goes out of scope
+    LA_HIP(hipStreamSynchronize(b->stream));
+    return LA_OK;
+}
+
+la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers)
+{
+    const int32_t ntier = w->net_tier ? w->num_tiers : 1;
+    std::vector<int32_t> counts;
+    la_status s = bucket_nodes(b, w->net_tier, ntier, counts);
+    if (s != LA_OK) return s;
+    const int32_t Hh = b->levels;
+    std::vector<int64_t> off(counts.size() + 1, 0);
+    for (size_t i = 0; i < counts.size(); ++i) off[i + 1] = off[i] + counts[i];
+    for (int32_t r = 0; r < w->rounds; ++r) {
+        DPArgs a = make_dp_args(b, w, H, lut);
+        for (int32_t t = 0; t < ntier; ++t) {
+            for (int32_t h = 0; h < Hh; ++h) {
+                const int64_t q = (int64_t)t * Hh + h;
+                const int32_t cnt = counts[q];
+                if (!cnt) continue;
+                const int64_t threads = (int64_t)cnt * a.NA;
+                hipLaunchKernelGGL(k_dp_level, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                                   b->stream, a, b->bucket_nodes + off[q], cnt);
+            }
+            hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->stream, b->chg_count, (int64_t)1);
+            for (int32_t h = Hh - 1; h >= 0; --h) {
+                const int64_t q = (int64_t)t * Hh + h;
+                const int32_t cnt = counts[q];
+                if (!cnt) continue;
+                hipLaunchKernelGGL(k_trace_level, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, a,
+                                   b->bucket_nodes + off[q], cnt, b->cur_layer, b->vlo, b->vhi, out_layers,
+                                   b->has_prev ? 1 : 0, b->chg_node, b->chg_old, b->chg_new, b->chg_count);
+            }
+            s = commit_changed(b);
+            if (s != LA_OK) return s;
+        }
+        s = history_update(b, H, w->hist_inc);
+        if (s != LA_OK) return s;
+        b->has_prev = true;
+    }
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+}  // namespace gapla

@@ -1,0 +1,532 @@
+// Elmore RC-tree timing on the layer-assignment trees (Sec. II-C; Fig. rc and
+// its d34 example), its exact reverse sweep, and the timing weights that feed
+// the DP (Eq. 4, Eq. 5, Sec. III-D look-ahead).
+//
+// Timing runs in FP32 with compensated (float-float) sums: every downstream
+// capacitance, delay, adjoint sum and path sum is a (hi, lo) pair whose error
+// stays near FP32 eps^2, so deep trees keep delays within 1e-5 of FP64.
+// These kernels are HBM-streaming sweeps over nodes grouped by tree height.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "la_internal.h"
+
+namespace gapla {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t n, int block = kBlock)
+{
+    int64_t g = (n + block - 1) / block;
+    return (int)(g < 1 ? 1 : (g > 65535 * 16 ? 65535 * 16 : g));
+}
+
+// error-free transformations (Knuth TwoSum, FMA TwoProd)
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+struct ff {
+    float hi, lo;
+};
+
+__device__ __forceinline__ ff ff_add(ff a, float x)
+{
+    float s, e;
+    two_sum(a.hi, x, s, e);
+    return {s, a.lo + e};
+}
+
+__device__ __forceinline__ ff ff_add(ff a, ff b)
+{
+    float s, e;
+    two_sum(a.hi, b.hi, s, e);
+    e += a.lo + b.lo;
+    float h = s + e;
+    return {h, e - (h - s)};
+}
+
+__device__ __forceinline__ ff ff_norm(ff a)
+{
+    float h = a.hi + a.lo;
+    return {h, a.lo - (h - a.hi)};
+}
+
+// x * (a.hi + a.lo), compensated
+__device__ __forceinline__ ff ff_mul(float x, ff a)
+{
+    float p = x * a.hi;
+    float e = fmaf(x, a.hi, -p) + x * a.lo;
+    float h = p + e;
+    return {h, e - (h - p)};
+}
+
+__device__ __forceinline__ float ff_val(ff a) { return a.hi + a.lo; }
+
+__device__ __forceinline__ int64_t rvia(const LayerTab &t, int a, int b)
+{
+    int32_t d = t.pv[a] - t.pv[b];
+    return d < 0 ? -d : d;
+}
+
+// ---------------------------------------------------------------------------
+// RC edges: before assignment, average unit R/C per direction and zero-R pin
+// edges (Sec. III-B); after it, lumped via from the parent's entering layer plus
+// wire, and the via down to layer 0 at each sink pin.
+// ---------------------------------------------------------------------------
+__global__ void k_rc(TreeDev T, LayerTab tab, const uint8_t *lay, float *R, float *C)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < T.nodes + T.sinks;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < T.nodes) {
+            const int32_t v = (int32_t)i, p = T.parent[v];
+            if (p < 0) {
+                R[v] = (float)((double)T.rdrv[T.net[v]] * 1e-6);
+                C[v] = 0.f;
+                continue;
+            }
+            const int d = T.dir[v];
+            const int64_t len = T.len[v];
+            int64_t r, c;
+            if (!lay) {
+                r = (int64_t)tab.r_avg[d] * len;
+                c = (int64_t)tab.c_avg[d] * len;
+            } else {
+                const int a = lay[v];
+                const int lp = T.parent[p] < 0 ? 0 : lay[p];
+                r = rvia(tab, lp, a) + (int64_t)tab.r[a] * len;
+                c = (int64_t)tab.c[a] * len;
+            }
+            R[v] = (float)((double)r * 1e-6);
+            C[v] = (float)((double)c * 1e-3);
+        } else {
+            const int64_t k = i - T.nodes;
+            const int32_t v = T.sink_node[k];
+            R[i] = lay ? (float)((double)rvia(tab, lay[v], 0) * 1e-6) : 0.f;
+            C[i] = 0.f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward: S(v) = sum over RC children of (C + S), bottom-up by height;
+// t(v) = t(parent) + R_v (C_v/2 + S_v), top-down; delay at sink pins.
+// ---------------------------------------------------------------------------
+__global__ void k_elmore_up(TreeDev T, const int32_t *nodes, int32_t cnt, const float *R, const float *C, float *S,
+                            float *Slo)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int32_t v = nodes[i];
+    ff s{0.f, 0.f};
+    const int32_t k = T.sink_id[v];
+    if (k >= 0) {
+        s = ff_add(s, C[T.nodes + k]);
+        s = ff_add(s, (float)((double)T.cpin[v] * 1e-3));
+    }
+    for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) {
+        const int32_t c = T.ch[q];
+        s = ff_add(s, C[c]);
+        s = ff_add(s, ff{S[c], Slo[c]});
+    }
+    s = ff_norm(s);
+    S[v] = s.hi;
+    Slo[v] = s.lo;
+}
+
+__global__ void k_elmore_down(TreeDev T, const int32_t *nodes, int32_t cnt, const float *R, const float *C,
+                              const float *S, const float *Slo, float *t, float *tlo, float *delay)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int32_t v = nodes[i], p = T.parent[v];
+    ff up = p < 0 ? ff{0.f, 0.f} : ff{t[p], tlo[p]};
+    ff load = ff_add(ff{S[v], Slo[v]}, 0.5f * C[v]);
+    ff tv = ff_norm(ff_add(up, ff_mul(R[v], load)));
+    t[v] = tv.hi;
+    tlo[v] = tv.lo;
+    const int32_t k = T.sink_id[v];
+    if (k >= 0) {
+        const int64_t e = T.nodes + k;
+        ff pl = ff_add(ff{0.5f * C[e], 0.f}, (float)((double)T.cpin[v] * 1e-3));
+        delay[k] = ff_val(ff_add(tv, ff_mul(R[e], pl)));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse sweep for g_k = dJ/d delay_k: G(v) = sum of g below v (bottom-up),
+// Sig(v) = Sig(parent) + R_v G(v) (top-down), dR_v = G(v)(C_v/2 + S_v),
+// dC_v = R_v G(v)/2 + Sig(parent).
+// ---------------------------------------------------------------------------
+__global__ void k_adj_up(TreeDev T, const int32_t *nodes, int32_t cnt, const float *gbar, float *G, float *Glo)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int32_t v = nodes[i];
+    ff g{0.f, 0.f};
+    const int32_t k = T.sink_id[v];
+    if (k >= 0) g = ff_add(g, gbar[k]);
+    for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) {
+        const int32_t c = T.ch[q];
+        g = ff_add(g, ff{G[c], Glo[c]});
+    }
+    g = ff_norm(g);
+    G[v] = g.hi;
+    Glo[v] = g.lo;
+}
+
+__global__ void k_adj_down(TreeDev T, const int32_t *nodes, int32_t cnt, const float *R, const float *C,
+                           const float *S, const float *Slo, const float *G, const float *Glo, const float *gbar,
+                           float *Sig, float *Siglo, float *dR, float *dC)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int32_t v = nodes[i], p = T.parent[v];
+    const ff up = p < 0 ? ff{0.f, 0.f} : ff{Sig[p], Siglo[p]};
+    const ff g{G[v], Glo[v]};
+    const ff sv = ff_norm(ff_add(up, ff_mul(R[v], g)));
+    Sig[v] = sv.hi;
+    Siglo[v] = sv.lo;
+    if (dR) dR[v] = ff_val(ff_mul(ff_val(g), ff_add(ff{S[v], Slo[v]}, 0.5f * C[v])));
+    if (dC) dC[v] = ff_val(ff_add(up, 0.5f * R[v] * ff_val(g)));
+    const int32_t k = T.sink_id[v];
+    if (k >= 0) {
+        const int64_t e = T.nodes + k;
+        const float gk = gbar[k];
+        if (dR) dR[e] = gk * (0.5f * C[e] + (float)((double)T.cpin[v] * 1e-3));
+        if (dC) dC[e] = ff_val(ff_add(sv, 0.5f * R[e] * gk));
+    }
+}
+
+__global__ void k_neg(const float *x, float *y, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = -x[i];
+}
+
+// ---------------------------------------------------------------------------
+// Slack, WNS, pin weights (Eq. 4), batches (Alg. 1 slack bins)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t f2ord(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float ord2f(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
+}
+
+__global__ void k_slack(TreeDev T, const float *delay, float *slack, uint32_t *wns_ord)
+{
+    __shared__ uint32_t smin;
+    if (threadIdx.x == 0) smin = 0xffffffffu;
+    __syncthreads();
+    uint32_t m = 0xffffffffu;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = T.sink_node[k];
+        const float s = (float)((double)T.budget_fs[T.net[v]] * 1e-3) - delay[k];
+        slack[k] = s;
+        m = min(m, f2ord(s));
+    }
+    atomicMin(&smin, m);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMin(wns_ord, smin);
+}
+
+__global__ void k_pin_weights(TreeDev T, const float *slack, const uint32_t *wns_ord, uint16_t *pin_w)
+{
+    const float wns = ord2f(*wns_ord);
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x) {
+        uint16_t q = 0;
+        if (wns < 0.f) {
+            const float rho = slack[k] / wns;
+            const float w = 1.0f / (1.0f + expf(-10.0f * (rho - 0.3f)));
+            q = (uint16_t)rintf(1024.0f * w);
+        }
+        pin_w[k] = q;
+    }
+}
+
+__global__ void k_tiers(TreeDev T, const float *slack, const uint32_t *wns_ord, uint8_t *tier)
+{
+    const float wns = ord2f(*wns_ord);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < T.nets; i += (int64_t)gridDim.x * blockDim.x) {
+        float ns = INFINITY;
+        for (int32_t k = T.net_sink_ptr[i]; k < T.net_sink_ptr[i + 1]; ++k) ns = fminf(ns, slack[k]);
+        uint8_t tr = (uint8_t)(7 + (i & 3));
+        if (wns < 0.f) {
+            const float rho = ns / wns;
+            if (rho >= 1.0f) tr = 0;
+            else if (rho >= 0.99f) tr = 1;
+            else if (rho >= 0.96f) tr = 2;
+            else if (rho >= 0.91f) tr = 3;
+            else if (rho >= 0.84f) tr = 4;
+            else if (rho >= 0.75f) tr = 5;
+            else if (rho >= 0.7f) tr = 6;
+        }
+        tier[i] = tr;
+    }
+}
+
+// Eq. 5: the edge weight is the largest pin weight in the downstream subtree.
+__global__ void k_edge_w(TreeDev T, const int32_t *nodes, int32_t cnt, const uint16_t *pin_w, uint16_t *seg_w)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const int32_t v = nodes[i];
+    uint16_t w = T.sink_id[v] >= 0 ? pin_w[T.sink_id[v]] : 0;
+    for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) w = max(w, seg_w[T.ch[q]]);
+    seg_w[v] = w;
+}
+
+__global__ void k_lambda_plain(TreeDev T, const uint16_t *seg_w, int32_t *lam)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x)
+        lam[v] = T.parent[v] < 0 ? 0 : (int32_t)(((int64_t)seg_w[v] * T.rest[v]) >> 10);
+}
+
+// gbar = dJ/d delay of J = sum over violating sinks of (w/1024) * slack
+__global__ void k_adj_seed(TreeDev T, const float *slack, const uint16_t *pin_w, float *gbar)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x)
+        gbar[k] = slack[k] < 0.f ? -(float)pin_w[k] * (1.0f / 1024.0f) : 0.f;
+}
+
+__global__ void k_adj_weights(TreeDev T, const float *G, const float *Glo, const float *Sig, const float *Siglo,
+                              const float *gbar, uint16_t *seg_w, uint16_t *pin_w, int32_t *lam)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x) {
+        const float q = rintf(-1024.0f * (G[v] + Glo[v]));
+        seg_w[v] = (uint16_t)(q < 0.f ? 0.f : (q > 1024.f ? 1024.f : q));
+        const int32_t p = T.parent[v];
+        if (p < 0) {
+            lam[v] = 0;
+        } else {
+            // -Sig * 1e6 as a float-float product, then rounded
+            const float sh = -Sig[p], sl = -Siglo[p];
+            const float ph = sh * 1e6f;
+            const float pl = fmaf(sh, 1e6f, -ph) + sl * 1e6f;
+            const float x = rintf(ph + pl);
+            lam[v] = x <= 0.f ? 0 : (x >= 2147483520.f ? 2147483647 : (int32_t)x);
+        }
+    }
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x) {
+        const float q = rintf(-1024.0f * gbar[k]);
+        pin_w[k] = (uint16_t)(q < 0.f ? 0.f : (q > 1024.f ? 1024.f : q));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TNS / WNS: FP64 block partials, then one block sums them in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void k_tns_partial(TreeDev T, const float *delay, double *part)
+{
+    __shared__ double ssum[kBlock];
+    __shared__ double smin[kBlock];
+    double s = 0.0, m = INFINITY;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = T.sink_node[k];
+        const double sl = (double)((float)((double)T.budget_fs[T.net[v]] * 1e-3) - delay[k]);
+        if (sl < 0.0) s += sl;
+        m = fmin(m, sl);
+    }
+    ssum[threadIdx.x] = s;
+    smin[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ssum[0];
+        part[2 * blockIdx.x + 1] = smin[0];
+    }
+}
+
+__global__ void k_tns_final(const double *part, int nb, double *out)
+{
+    __shared__ double ssum[kBlock];
+    __shared__ double smin[kBlock];
+    double s = 0.0, m = INFINITY;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        s += part[2 * i];
+        m = fmin(m, part[2 * i + 1]);
+    }
+    ssum[threadIdx.x] = s;
+    smin[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = ssum[0];
+        out[1] = smin[0];
+    }
+}
+
+}  // namespace
+
+TreeDev tree_view(const la_batch *b)
+{
+    TreeDev t;
+    t.nets = b->nets;
+    t.nodes = b->nodes;
+    t.sinks = b->sinks;
+    t.parent = b->parent;
+    t.ch_ptr = b->ch_ptr;
+    t.ch = b->ch;
+    t.net = b->net;
+    t.net_ptr = b->net_ptr;
+    t.len = b->len;
+    t.g0 = b->g0;
+    t.dir = b->dir;
+    t.flags = b->flags;
+    t.cpin = b->cpin;
+    t.sink_id = b->sink_id;
+    t.sink_node = b->sink_node;
+    t.net_sink_ptr = b->net_sink_ptr;
+    t.rest = b->rest;
+    t.budget_fs = b->budget_fs;
+    t.rdrv = b->rdrv;
+    return t;
+}
+
+la_status launch_rc_pre(la_batch *b)
+{
+    hipLaunchKernelGGL(k_rc, dim3(grid_for(b->nodes + b->sinks)), dim3(kBlock), 0, b->stream, tree_view(b), b->tab,
+                       (const uint8_t *)nullptr, b->R, b->C);
+    LA_HIP(hipGetLastError());
+    b->rc_assigned = false;
+    return LA_OK;
+}
+
+la_status launch_rc_from_layers(la_batch *b)
+{
+    hipLaunchKernelGGL(k_rc, dim3(grid_for(b->nodes + b->sinks)), dim3(kBlock), 0, b->stream, tree_view(b), b->tab,
+                       (const uint8_t *)b->cur_layer, b->R, b->C);
+    LA_HIP(hipGetLastError());
+    b->rc_assigned = true;
+    return LA_OK;
+}
+
+la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay)
+{
+    const TreeDev T = tree_view(b);
+    const auto &lp = b->h_level_ptr;
+    for (int h = 0; h < b->levels; ++h) {
+        const int32_t cnt = lp[h + 1] - lp[h];
+        if (!cnt) continue;
+        hipLaunchKernelGGL(k_elmore_up, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                           b->level_nodes + lp[h], cnt, R, C, b->el_S, b->el_Slo);
+    }
+    for (int h = b->levels - 1; h >= 0; --h) {
+        const int32_t cnt = lp[h + 1] - lp[h];
+        if (!cnt) continue;
+        hipLaunchKernelGGL(k_elmore_down, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                           b->level_nodes + lp[h], cnt, R, C, b->el_S, b->el_Slo, b->el_t, b->el_tlo, delay);
+    }
+    LA_HIP(hipGetLastError());
+    b->fwd_R = R;
+    b->fwd_C = C;
+    b->fwd_done = true;
+    return LA_OK;
+}
+
+// gbar: dJ/d delay per sink (from_dslack: the array holds dJ/dslack and is negated first)
+la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *dR, float *dC)
+{
+    if (!b->fwd_done) return set_error(LA_ERR_STATE, "la_elmore_backward needs a forward on this batch first");
+    const TreeDev T = tree_view(b);
+    const float *gbar = g;
+    if (from_dslack) {
+        hipLaunchKernelGGL(k_neg, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, g, b->scratch_f, b->sinks);
+        gbar = b->scratch_f;
+    }
+    const auto &lp = b->h_level_ptr;
+    float *Glo = b->el_Glo, *Siglo = b->el_Siglo;
+    for (int h = 0; h < b->levels; ++h) {
+        const int32_t cnt = lp[h + 1] - lp[h];
+        if (!cnt) continue;
+        hipLaunchKernelGGL(k_adj_up, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                           b->level_nodes + lp[h], cnt, gbar, b->el_G, Glo);
+    }
+    for (int h = b->levels - 1; h >= 0; --h) {
+        const int32_t cnt = lp[h + 1] - lp[h];
+        if (!cnt) continue;
+        hipLaunchKernelGGL(k_adj_down, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                           b->level_nodes + lp[h], cnt, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, b->el_G, Glo, gbar,
+                           b->el_Sig, Siglo, dR, dC);
+    }
+    LA_HIP(hipGetLastError());
+    b->bwd_done = true;
+    return LA_OK;
+}
+
+la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t *seg_w, uint16_t *pin_w,
+                         int32_t *lam, uint8_t *tier)
+{
+    const TreeDev T = tree_view(b);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, b->stream, b->wns_bits, 0xffffffffu, 1);
+    hipLaunchKernelGGL(k_slack, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, delay, b->slack, b->wns_bits);
+    hipLaunchKernelGGL(k_pin_weights, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, b->slack, b->wns_bits,
+                       pin_w);
+    hipLaunchKernelGGL(k_tiers, dim3(grid_for(b->nets)), dim3(kBlock), 0, b->stream, T, b->slack, b->wns_bits, tier);
+    if (mode == LA_WEIGHTS_PLAIN) {
+        const auto &lp = b->h_level_ptr;
+        for (int h = 0; h < b->levels; ++h) {
+            const int32_t cnt = lp[h + 1] - lp[h];
+            if (!cnt) continue;
+            hipLaunchKernelGGL(k_edge_w, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                               b->level_nodes + lp[h], cnt, pin_w, seg_w);
+        }
+        hipLaunchKernelGGL(k_lambda_plain, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, seg_w, lam);
+        LA_HIP(hipGetLastError());
+        return LA_OK;
+    }
+    if (!b->fwd_done) return set_error(LA_ERR_STATE, "adjoint weights need la_elmore on this batch first");
+    hipLaunchKernelGGL(k_adj_seed, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, b->slack, pin_w,
+                       b->scratch_f);
+    la_status s = elmore_backward(b, b->scratch_f, false, nullptr, nullptr);
+    if (s != LA_OK) return s;
+    hipLaunchKernelGGL(k_adj_weights, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->el_G, b->el_Glo,
+                       b->el_Sig, b->el_Siglo, b->scratch_f, seg_w, pin_w, lam);
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+la_status timing_summary(la_batch *b, const float *delay, double *tns, double *wns)
+{
+    const TreeDev T = tree_view(b);
+    const int nb = (int)std::min<int64_t>(b->red_blocks, std::max<int64_t>(1, (b->sinks + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_tns_partial, dim3(nb), dim3(kBlock), 0, b->stream, T, delay, b->red);
+    hipLaunchKernelGGL(k_tns_final, dim3(1), dim3(kBlock), 0, b->stream, b->red, nb, b->red + 2 * b->red_blocks);
+    LA_HIP(hipGetLastError());
+    double h[2];
+    LA_HIP(hipMemcpyAsync(h, b->red + 2 * b->red_blocks, sizeof(h), hipMemcpyDeviceToHost, b->stream));
+    LA_HIP(hipStreamSynchronize(b->stream));
+    *tns = h[0];
+    *wns = h[1];
+    return LA_OK;
+}
+
+}  // namespace gapla

@@ -1,0 +1,148 @@
+// Internal state of a layer-assignment batch and helpers shared by the HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gapla.h"
+
+namespace gapla {
+
+constexpr int kMaxL = 16;          // layers supported (4-bit layer ids)
+constexpr int kMaxA = 8;           // routable layers per direction
+constexpr int kNDelta = 64;        // congestion table entries per (layer, zero-capacity flag)
+constexpr int kDeltaMin = -32;
+constexpr int32_t kLutSat = 1 << 20;
+constexpr int32_t kHistSat = 1 << 24;
+
+// node flag bits
+constexpr uint8_t kSink = 1, kDriver = 2, kRoot = 4;
+
+// Layer table handed to kernels by value.
+struct LayerTab {
+    int32_t L, min_layer, X, Y;
+    int32_t nA[2];                  // routable layers per direction
+    int8_t lay[2][kMaxA];           // routable layers of each direction, ascending
+    int8_t jidx[kMaxL];             // index of a layer inside its direction list, -1 if not routable
+    uint8_t dir[kMaxL];
+    int32_t r[kMaxL], c[kMaxL];     // mOhm / aF per GCell
+    int32_t pv[kMaxL + 1];          // prefix sums of via R: Rvia(a,b) = |pv[a]-pv[b]|
+    int32_t r_avg[2], c_avg[2];     // integer averages over routable layers per direction
+};
+
+// Integer weights handed to the DP kernels.
+struct DPWeights {
+    int64_t w_cong, w_cap, w_d, w_via;
+    const uint16_t *seg_w;
+    const uint16_t *pin_w;
+    const int32_t *lam;
+    const int32_t *lut;
+    int32_t self_excl;              // exclude each segment's previous demand
+};
+
+// Device view of the layer-assignment tree (canonical node order).
+struct TreeDev {
+    int64_t nets, nodes, sinks;
+    const int32_t *parent;          // global parent, -1 at roots
+    const int32_t *ch_ptr, *ch;     // children, ascending canonical index
+    const int32_t *net;             // node -> net
+    const int32_t *net_ptr;         // [nets+1]
+    const int32_t *len;             // segment length (GCells), 0 at roots
+    const int32_t *g0;              // grid index (layer 0) of the first GCell edge covered
+    const uint8_t *dir;             // 0 H, 1 V (root: 0)
+    const uint8_t *flags;
+    const int32_t *cpin;            // aF, sinks only
+    const int32_t *sink_id;         // node -> sink or -1
+    const int32_t *sink_node;       // [sinks]
+    const int32_t *net_sink_ptr;    // [nets+1] sinks of a net are contiguous
+    const int32_t *rest;            // average-R estimate (mOhm) from the driver to the segment's upper end
+    const int32_t *budget_fs;       // per net
+    const int32_t *rdrv;            // per net, mOhm
+};
+
+}  // namespace gapla
+
+struct la_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    gapla::LayerTab tab{};
+    int64_t nets = 0, nodes = 0, sinks = 0, E = 0;
+    int32_t levels = 0, max_net_nodes = 0;
+    int64_t gcell_edges = 0;
+    int32_t NAmax = 0;              // stride of per-(node, layer index) DP arrays
+
+    // per-net worst-case unit bounds for the range check (max over nets)
+    double bnd_cong = 0, bnd_cap = 0, bnd_via = 0, bnd_d = 0;
+
+    // host copies
+    std::vector<int32_t> h_level_ptr;   // [levels+1]
+    std::vector<int32_t> h_net_ptr;
+
+    // device tree
+    int32_t *parent = nullptr, *ch_ptr = nullptr, *ch = nullptr, *net = nullptr, *net_ptr = nullptr;
+    int32_t *len = nullptr, *g0 = nullptr, *cpin = nullptr, *sink_id = nullptr, *sink_node = nullptr;
+    int32_t *net_sink_ptr = nullptr, *rest = nullptr, *budget_fs = nullptr, *rdrv = nullptr;
+    uint8_t *dir = nullptr, *flags = nullptr;
+    int32_t *level_nodes = nullptr, *level_ptr = nullptr, *height = nullptr;
+    uint8_t *caps = nullptr;
+
+    // negotiation state
+    int32_t *D = nullptr;
+    uint8_t *cur_layer = nullptr, *vlo = nullptr, *vhi = nullptr;
+    bool has_prev = false;
+
+    // plain-form DP state
+    int64_t *F = nullptr, *KA = nullptr;
+    int32_t *S = nullptr;
+    uint8_t *bt = nullptr, *sel = nullptr;
+    int32_t *bucket_nodes = nullptr, *bucket_cnt = nullptr, *bucket_cur = nullptr;
+    size_t bucket_cap = 0;
+
+    // changed-segment list of the current batch (tier)
+    int32_t *chg_node = nullptr, *chg_count = nullptr;
+    uint8_t *chg_old = nullptr, *chg_new = nullptr;
+
+    // default congestion table (device)
+    int32_t *lut = nullptr;
+
+    // RC and Elmore state
+    float *R = nullptr, *C = nullptr;   // batch RC views [nodes+sinks]
+    bool rc_assigned = false;
+    float *el_S = nullptr, *el_Slo = nullptr, *el_t = nullptr, *el_tlo = nullptr;
+    float *el_G = nullptr, *el_Glo = nullptr, *el_Sig = nullptr, *el_Siglo = nullptr;
+    const float *fwd_R = nullptr, *fwd_C = nullptr;
+    bool fwd_done = false, bwd_done = false;
+    float *slack = nullptr;
+    float *scratch_f = nullptr;         // [sinks] temporaries
+    uint32_t *wns_bits = nullptr;       // ordered-int encoding of the WNS float
+    double *red = nullptr;              // reduction partials
+    int32_t red_blocks = 0;
+};
+
+namespace gapla {
+
+// errors ---------------------------------------------------------------------
+la_status set_error(la_status s, const std::string &msg);
+la_status hip_fail(hipError_t e, const char *what);
+
+#define LA_HIP(call)                                                \
+    do {                                                            \
+        hipError_t e_ = (call);                                     \
+        if (e_ != hipSuccess) return gapla::hip_fail(e_, #call);    \
+    } while (0)
+
+TreeDev tree_view(const la_batch *b);
+
+// kernels launched from more than one source file
+la_status launch_rc_from_layers(la_batch *b);
+la_status launch_rc_pre(la_batch *b);
+la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay);
+la_status elmore_backward(la_batch *b, const float *gbar_neg_dslack, bool from_dslack, float *dR, float *dC);
+la_status commit_changed(la_batch *b);
+la_status history_update(la_batch *b, int32_t *H, int32_t hist_inc);
+la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut);
+
+}  // namespace gapla
