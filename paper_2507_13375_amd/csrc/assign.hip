@@ -22,8 +22,12 @@ inline int grid_for(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535 * 8));
 }
 
+// one thread per (node of this level and batch, entering-layer index)
+template <int NAMAX>
 __global__ void k_dp_level(DPArgs a, const int32_t *nodes, int32_t cnt)
 {
+    __shared__ LayerTab tb;
+    load_tab(a.tab, tb);
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t i = tid / a.NA;
     const int j = (int)(tid - i * a.NA);
@@ -36,10 +40,11 @@ __global__ void k_dp_level(DPArgs a, const int32_t *nodes, int32_t cnt)
         l = 0;
     } else {
         const int d = a.T.dir[n];
-        if (j >= a.tab.nA[d]) return;
-        l = a.tab.lay[d][j];
+        if (j >= tb.nA[d]) return;
+        l = tb.lay[d][j];
     }
-    dp_node_layer(a, n, l, j, root);
+    GlobalState st(a);
+    dp_node<GlobalState, NAMAX>(a, tb, st, n, n, l, j, root);
 }
 
 // Alg. 4: each node takes the layer its parent recorded for the parent's entering layer.
@@ -47,10 +52,21 @@ __global__ void k_trace_level(DPArgs a, const int32_t *nodes, int32_t cnt, uint8
                               uint8_t *out_layers, int has_prev, int32_t *chg_node, uint8_t *chg_old,
                               uint8_t *chg_new, int32_t *chg_count)
 {
+    __shared__ LayerTab tb;
+    load_tab(a.tab, tb);
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int32_t n = nodes[i];
-    trace_node(a, n, cur, vlo, vhi, out_layers, has_prev, chg_node, chg_old, chg_new, chg_count);
+    bool changed = false;
+    uint8_t old_l = 0;
+    int ln = 0;
+    int32_t n = 0;
+    if (i < cnt) {
+        n = nodes[i];
+        const int32_t p = a.T.parent[n];
+        const int lp = (p < 0 || a.T.parent[p] < 0) ? 0 : cur[p];
+        GlobalState st(a);
+        ln = trace_node(a, tb, st, n, n, lp, p < 0, cur, vlo, vhi, out_layers, has_prev, &changed, &old_l);
+    }
+    append_change(ChangeList{chg_node, chg_old, chg_new, chg_count}, changed, n, old_l, (uint8_t)ln);
 }
 
 __global__ void k_zero_i32(int32_t *p, int64_t n)
@@ -87,27 +103,71 @@ __global__ void k_history(const int32_t *D, const uint8_t *caps, int32_t *H, int
     }
 }
 
+// Counting sort of nodes by (batch, height).  With few buckets each block keeps a
+// private histogram in LDS and touches each global counter once, which keeps the
+// atomics off a handful of hot addresses.
+constexpr int kLdsBuckets = 4096;
+
 __global__ void k_bucket_count(TreeDev T, const int32_t *height, const uint8_t *tier, int32_t ntier, int32_t levels,
                                int32_t *counts, int32_t *bad)
 {
+    __shared__ int32_t hist[kLdsBuckets];
+    const int64_t nb = (int64_t)ntier * levels;
+    const bool local = nb <= kLdsBuckets;
+    if (local)
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x) {
         const int t = tier ? tier[T.net[v]] : 0;
         if (t >= ntier) {
             atomicAdd(bad, 1);
             continue;
         }
-        atomicAdd(&counts[(int64_t)t * levels + height[v]], 1);
+        const int64_t q = (int64_t)t * levels + height[v];
+        if (local) atomicAdd(&hist[q], 1);
+        else atomicAdd(&counts[q], 1);
     }
+    __syncthreads();
+    if (local)
+        for (int i = threadIdx.x; i < nb; i += blockDim.x)
+            if (hist[i]) atomicAdd(&counts[i], hist[i]);
 }
 
 __global__ void k_bucket_scatter(TreeDev T, const int32_t *height, const uint8_t *tier, int32_t ntier, int32_t levels,
                                  int32_t *cursor, int32_t *out)
 {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x) {
-        const int t = tier ? tier[T.net[v]] : 0;
-        if (t >= ntier) continue;
-        const int32_t pos = atomicAdd(&cursor[(int64_t)t * levels + height[v]], 1);
-        out[pos] = (int32_t)v;
+    __shared__ int32_t hist[kLdsBuckets];
+    __shared__ int32_t base[kLdsBuckets];
+    const int64_t nb = (int64_t)ntier * levels;
+    if (nb > kLdsBuckets) {
+        for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes;
+             v += (int64_t)gridDim.x * blockDim.x) {
+            const int t = tier ? tier[T.net[v]] : 0;
+            if (t >= ntier) continue;
+            out[atomicAdd(&cursor[(int64_t)t * levels + height[v]], 1)] = (int32_t)v;
+        }
+        return;
+    }
+    // one tile of blockDim nodes at a time: rank inside the tile, then reserve per bucket
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < T.nodes; v0 += (int64_t)gridDim.x * blockDim.x) {
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        const int64_t v = v0 + threadIdx.x;
+        int64_t q = -1;
+        int32_t r = 0;
+        if (v < T.nodes) {
+            const int t = tier ? tier[T.net[v]] : 0;
+            if (t < ntier) {
+                q = (int64_t)t * levels + height[v];
+                r = atomicAdd(&hist[q], 1);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nb; i += blockDim.x)
+            if (hist[i]) base[i] = atomicAdd(&cursor[i], hist[i]);
+        __syncthreads();
+        if (q >= 0) out[base[q] + r] = (int32_t)v;
+        __syncthreads();
     }
 }
 
@@ -127,11 +187,6 @@ la_status interleave_vias(la_batch *b, uint8_t *out)
                        b->nodes);
     LA_HIP(hipGetLastError());
     return LA_OK;
-}
-
-la_status assign_batched(la_batch *, const la_weights *, int32_t *, const int32_t *, uint8_t *)
-{
-    return set_error(LA_ERR_INVALID_ARG, "batched form not available in this build");
 }
 
 DPArgs make_dp_args(la_batch *b, const la_weights *w, const int32_t *H, const int32_t *lut)
@@ -242,8 +297,13 @@ la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32
                 const int32_t cnt = counts[q];
                 if (!cnt) continue;
                 const int64_t threads = (int64_t)cnt * a.NA;
-                hipLaunchKernelGGL(k_dp_level, dim3((unsigned)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                                   b->stream, a, b->bucket_nodes + off[q], cnt);
+                const dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
+                if (a.NA <= 4)
+                    hipLaunchKernelGGL(k_dp_level<4>, grid, dim3(kBlock), 0, b->stream, a, b->bucket_nodes + off[q], cnt);
+                else if (a.NA <= 6)
+                    hipLaunchKernelGGL(k_dp_level<6>, grid, dim3(kBlock), 0, b->stream, a, b->bucket_nodes + off[q], cnt);
+                else
+                    hipLaunchKernelGGL(k_dp_level<8>, grid, dim3(kBlock), 0, b->stream, a, b->bucket_nodes + off[q], cnt);
             }
             hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->stream, b->chg_count, (int64_t)1);
             for (int32_t h = Hh - 1; h >= 0; --h) {

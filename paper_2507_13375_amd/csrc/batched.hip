@@ -1,2 +1,522 @@
-// Batched form (filled in below the plain form).
+// Batched form of the layer-assignment DP: one persistent launch per batch (tier)
+// instead of one launch per tree level.  Workgroups pull groups of nets from a
+// work queue, stage whole nets in LDS (DP state, children, height order), run the
+// bottom-up DP of Alg. 3 and the top-down trace-back of Alg. 4 with workgroup
+// barriers between levels, and append changed segments for the commit.  Nets
+// larger than one LDS tile keep their DP state in HBM and walk their own levels
+// inside the same workgroup.  All negotiation rounds of a la_assign call are
+// captured once as a hipGraph and replayed.
+//
+// Every net's result depends only on its own inputs and the demand snapshot of its
+// batch, so the layers equal the plain form's for any grid size or claim order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "dp_device.h"
 #include "la_internal.h"
+
+namespace gapla {
+
+DPArgs make_dp_args(la_batch *b, const la_weights *w, const int32_t *H, const int32_t *lut);
+la_status commit_changed(la_batch *b);
+la_status history_update(la_batch *b, int32_t *H, int32_t inc);
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// DP state of one LDS tile, indexed by tile-local node id.
+template <int NAMAX>
+struct LdsState {
+    int64_t *F_, *KA_;
+    int32_t *S_;
+    uint8_t *bt_, *sel_;
+    const int16_t *chp, *chl;
+    const int32_t *gid;
+    __device__ int nch(int32_t s) const { return chp[s + 1] - chp[s]; }
+    __device__ int32_t ch_state(int32_t s, int q) const { return chl[chp[s] + q]; }
+    __device__ int32_t ch_gid(int32_t s, int q) const { return gid[chl[chp[s] + q]]; }
+    __device__ int64_t &F(int32_t s, int j) const { return F_[s * NAMAX + j]; }
+    __device__ int64_t &KA(int32_t s, int j) const { return KA_[s * NAMAX + j]; }
+    __device__ int32_t &S(int32_t s, int j) const { return S_[s * NAMAX + j]; }
+    __device__ uint8_t *bt(int32_t s, int j) const { return bt_ + 2 * (s * NAMAX + j); }
+    __device__ uint8_t &sel(int32_t s, int l) const { return sel_[s * kMaxL + l]; }
+};
+
+// LDS bytes of one tile
+template <int NAMAX>
+constexpr size_t tile_bytes()
+{
+    return (size_t)kCap * NAMAX * 8 * 2      // F, KA
+           + (size_t)kCap * NAMAX * 4        // S
+           + (size_t)kCap * 4                // gid
+           + (size_t)kCap * 2 * 4 + 2 * 2    // par, chl, order, lvl (+ chp has kCap+1)
+           + (size_t)(kCap + 1) * 2          // chp
+           + (size_t)kCap * NAMAX * 2        // bt
+           + (size_t)kCap * kMaxL            // sel
+           + (size_t)kCap                    // entering layer during trace
+           + (size_t)(kCap + 2) * 4          // level starts
+           + 64 * 4 * 8;                     // per-claim bookkeeping
+}
+
+struct BArgs {
+    const int32_t *tier_nets;
+    const int32_t *tier_off;    // [2*T+1]: bucket starts; batch t spans [off[2t], off[2t+2])
+    int32_t tier;
+    int32_t *ctr;               // work-queue counter of this (round, batch)
+    const int32_t *height;
+    const int32_t *net_big, *bn_order, *bn_lvl, *bn_lvl_off, *bn_nlev;
+    uint8_t *cur, *vlo, *vhi, *out_layers;
+    int has_prev;
+    ChangeList cl;
+};
+
+template <int NAMAX>
+__device__ __forceinline__ void dp_level_items(const DPArgs &a, const LayerTab &tb, const LdsState<NAMAX> &st, const int16_t *order, const int16_t *par,
+                               const int32_t *gid, int32_t lbeg, int32_t lcnt)
+{
+    const int32_t items = lcnt * NAMAX;
+    for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
+        const int32_t u = order[lbeg + it / NAMAX];
+        const int j = it % NAMAX;
+        const int32_t n = gid[u];
+        const bool root = par[u] < 0;
+        int l;
+        if (root) {
+            if (j != 0) continue;
+            l = 0;
+        } else {
+            const int d = a.T.dir[n];
+            if (j >= tb.nA[d]) continue;
+            l = tb.lay[d][j];
+        }
+        dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, n, l, j, root);
+    }
+}
+
+template <int NAMAX>
+__global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ LayerTab tb;
+    load_tab(a.tab, tb);
+    uint8_t *p = smem;
+    int64_t *F = (int64_t *)p;
+    p += kCap * NAMAX * 8;
+    int64_t *KA = (int64_t *)p;
+    p += kCap * NAMAX * 8;
+    int32_t *S = (int32_t *)p;
+    p += kCap * NAMAX * 4;
+    int32_t *gid = (int32_t *)p;
+    p += kCap * 4;
+    int32_t *lstart = (int32_t *)p;          // [kCap+2] level starts into order
+    p += (kCap + 2) * 4;
+    int32_t *book = (int32_t *)p;            // claim bookkeeping
+    p += 64 * 4 * 8;
+    int16_t *par = (int16_t *)p;
+    p += kCap * 2;
+    int16_t *chp = (int16_t *)p;
+    p += (kCap + 2) * 2;
+    int16_t *chl = (int16_t *)p;
+    p += kCap * 2;
+    int16_t *order = (int16_t *)p;
+    p += kCap * 2;
+    int16_t *lvl = (int16_t *)p;
+    p += kCap * 2;
+    uint8_t *bt = p;
+    p += kCap * NAMAX * 2;
+    uint8_t *sel = p;
+    p += kCap * kMaxL;
+    uint8_t *ent = p;
+
+    // bookkeeping layout: [0] claim base, [1] #subs, [2] max level of tile,
+    // [8..8+kClaim] sub start, [48..] sub end (claim-relative),
+    // [128..] per-net local node base, [168..] per-net local child base (tile-relative)
+    int32_t *s_base = book, *s_nsub = book + 1, *s_maxlev = book + 2;
+    int32_t *s_sub0 = book + 8, *s_sub1 = book + 48;
+    int32_t *s_lbase = book + 128, *s_cbase = book + 168;
+
+    LdsState<NAMAX> st{F, KA, S, bt, sel, chp, chl, gid};
+    // the batch's small nets (its big nets run in k_batched_big)
+    const int32_t off0 = ba.tier_off[2 * ba.tier + 1], cnt = ba.tier_off[2 * ba.tier + 2] - off0;
+
+    for (;;) {
+        if (threadIdx.x == 0) *s_base = atomicAdd(ba.ctr, kClaim);
+        __syncthreads();
+        const int32_t base = *s_base;
+        if (base >= cnt) break;
+        const int32_t nclaim = min(kClaim, cnt - base);
+        if (threadIdx.x == 0) {
+            // split the claimed nets into LDS tiles of at most kCap nodes
+            int32_t ns = 0, open = -1, nodes = 0;
+            for (int32_t i = 0; i < nclaim; ++i) {
+                const int32_t net = ba.tier_nets[off0 + base + i];
+                const int32_t n = a.T.net_ptr[net + 1] - a.T.net_ptr[net];
+                if (open >= 0 && nodes + n > kCap) {
+                    s_sub1[ns - 1] = i;
+                    open = -1;
+                }
+                if (open < 0) {
+                    s_sub0[ns] = i;
+                    open = ns++;
+                    nodes = 0;
+                }
+                nodes += n;
+            }
+            if (open >= 0) s_sub1[ns - 1] = nclaim;
+            *s_nsub = ns;
+        }
+        __syncthreads();
+        const int32_t nsub = *s_nsub;
+        for (int32_t sb = 0; sb < nsub; ++sb) {
+            const int32_t i0 = s_sub0[sb], i1 = s_sub1[sb];
+            // ---- small nets: stage the tile in LDS --------------------------------------
+            if (threadIdx.x == 0) {
+                int32_t nb = 0, cb = 0;
+                for (int32_t i = i0; i < i1; ++i) {
+                    const int32_t net = ba.tier_nets[off0 + base + i];
+                    const int32_t n = a.T.net_ptr[net + 1] - a.T.net_ptr[net];
+                    s_lbase[i - i0] = nb;
+                    s_cbase[i - i0] = cb;
+                    nb += n;
+                    cb += n - 1;
+                }
+                s_lbase[i1 - i0] = nb;
+                s_cbase[i1 - i0] = cb;
+            }
+            for (int32_t i = threadIdx.x; i < kCap + 2; i += blockDim.x) lstart[i] = 0;
+            __syncthreads();
+            const int32_t nn = s_lbase[i1 - i0];
+            const int32_t nnets = i1 - i0;
+            for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
+                int32_t k = 0;
+                while (k + 1 < nnets && s_lbase[k + 1] <= u) ++k;
+                const int32_t net = ba.tier_nets[off0 + base + i0 + k];
+                const int32_t g0 = a.T.net_ptr[net];
+                const int32_t g = g0 + (u - s_lbase[k]);
+                gid[u] = g;
+                const int32_t pg = a.T.parent[g];
+                par[u] = (int16_t)(pg < 0 ? -1 : pg - g0 + s_lbase[k]);
+                const int32_t c0 = a.T.ch_ptr[g0];
+                const int32_t cb = s_cbase[k] + (a.T.ch_ptr[g] - c0);
+                chp[u] = (int16_t)cb;
+                for (int32_t e = a.T.ch_ptr[g]; e < a.T.ch_ptr[g + 1]; ++e)
+                    chl[s_cbase[k] + (e - c0)] = (int16_t)(a.T.ch[e] - g0 + s_lbase[k]);
+                const int32_t h = ba.height[g];
+                lvl[u] = (int16_t)h;
+                atomicAdd(&lstart[h + 1], 1);
+            }
+            if (threadIdx.x == 0) chp[nn] = (int16_t)s_cbase[i1 - i0];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int32_t m = 0;
+                for (int32_t h = 0; h < kCap; ++h) {
+                    if (lstart[h + 1]) m = h;
+                    lstart[h + 1] += lstart[h];
+                }
+                *s_maxlev = m;
+            }
+            __syncthreads();
+            // height order: lstart[h] counts down as slots fill, restored below
+            for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
+                const int32_t pos = atomicAdd(&lstart[lvl[u]], 1);
+                order[pos] = (int16_t)u;
+            }
+            __syncthreads();
+            const int32_t maxlev = *s_maxlev;
+            // after the scatter lstart[h] holds the end of level h = start of level h+1
+            for (int32_t h = 0; h <= maxlev; ++h) {
+                const int32_t lb = h == 0 ? 0 : lstart[h - 1], le = lstart[h];
+                dp_level_items<NAMAX>(a, tb, st, order, par, gid, lb, le - lb);
+                __syncthreads();
+            }
+            for (int32_t h = maxlev; h >= 0; --h) {
+                const int32_t lb = h == 0 ? 0 : lstart[h - 1], le = lstart[h];
+                for (int32_t it0 = lb; it0 < le; it0 += blockDim.x) {
+                    const int32_t it = it0 + threadIdx.x;
+                    bool changed = false;
+                    uint8_t old_l = 0;
+                    int ln = 0;
+                    int32_t n = 0;
+                    if (it < le) {
+                        const int32_t u = order[it];
+                        n = gid[u];
+                        const int32_t pu = par[u];
+                        const int lp = (pu < 0 || par[pu] < 0) ? 0 : ent[pu];
+                        ln = trace_node(a, tb, st, u, n, lp, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev,
+                                        &changed, &old_l);
+                        ent[u] = (uint8_t)ln;
+                    }
+                    append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Nets larger than one LDS tile: one workgroup per net, DP state in HBM, the net's own
+// height levels walked with workgroup barriers.
+template <int NAMAX>
+__global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
+{
+    __shared__ LayerTab tb;
+    load_tab(a.tab, tb);
+    GlobalState gst(a);
+    const int32_t off0 = ba.tier_off[2 * ba.tier], cnt = ba.tier_off[2 * ba.tier + 1] - off0;
+    for (int32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const int32_t net = ba.tier_nets[off0 + i];
+        const int32_t q = ba.net_big[net];
+        const int32_t lo = ba.bn_lvl_off[q], nl = ba.bn_nlev[q];
+        for (int32_t h = 0; h < nl; ++h) {
+            const int32_t b0 = ba.bn_lvl[lo + h], c = ba.bn_lvl[lo + h + 1] - b0;
+            for (int32_t it = threadIdx.x; it < c * NAMAX; it += blockDim.x) {
+                const int32_t n = ba.bn_order[b0 + it / NAMAX];
+                const int j = it % NAMAX;
+                const bool root = a.T.parent[n] < 0;
+                int l;
+                if (root) {
+                    if (j != 0) continue;
+                    l = 0;
+                } else {
+                    const int d = a.T.dir[n];
+                    if (j >= tb.nA[d]) continue;
+                    l = tb.lay[d][j];
+                }
+                dp_node<GlobalState, NAMAX>(a, tb, gst, n, n, l, j, root);
+            }
+            __syncthreads();
+        }
+        for (int32_t h = nl - 1; h >= 0; --h) {
+            const int32_t b0 = ba.bn_lvl[lo + h], c = ba.bn_lvl[lo + h + 1] - b0;
+            for (int32_t it0 = 0; it0 < c; it0 += blockDim.x) {
+                const int32_t it = it0 + threadIdx.x;
+                bool changed = false;
+                uint8_t old_l = 0;
+                int ln = 0;
+                int32_t n = 0;
+                if (it < c) {
+                    n = ba.bn_order[b0 + it];
+                    const int32_t pp = a.T.parent[n];
+                    const int lp = (pp < 0 || a.T.parent[pp] < 0) ? 0 : ba.cur[pp];
+                    ln = trace_node(a, tb, gst, n, n, lp, pp < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev,
+                                    &changed, &old_l);
+                }
+                append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---- batch (tier) partition -----------------------------------------------------------
+// bucket of a net: 2*tier + (big ? 0 : 1), so each batch lists its big nets first.
+
+__global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big, int32_t *cnt,
+                             int32_t *bad)
+{
+    __shared__ int32_t hist[512];
+    for (int i = threadIdx.x; i < 2 * ntier; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets; i += (int64_t)gridDim.x * blockDim.x) {
+        const int t = tier ? tier[i] : 0;
+        if (t >= ntier) {
+            atomicAdd(bad, 1);
+            continue;
+        }
+        atomicAdd(&hist[2 * t + (net_big[i] >= 0 ? 0 : 1)], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * ntier; i += blockDim.x)
+        if (hist[i]) atomicAdd(&cnt[i], hist[i]);
+}
+
+__global__ void k_tier_offsets(const int32_t *cnt, int32_t nb, int32_t *off, int32_t *cur, int32_t *claim,
+                               int32_t nclaim)
+{
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int32_t i = 0; i < nb; ++i) {
+            off[i] = acc;
+            cur[i] = acc;
+            acc += cnt[i];
+        }
+        off[nb] = acc;
+    }
+    for (int32_t i = threadIdx.x; i < nclaim; i += blockDim.x) claim[i] = 0;
+}
+
+__global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big,
+                               int32_t *cur, int32_t *out)
+{
+    __shared__ int32_t hist[512];
+    __shared__ int32_t base[512];
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < nets; i0 += (int64_t)gridDim.x * blockDim.x) {
+        for (int i = threadIdx.x; i < 2 * ntier; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        const int64_t i = i0 + threadIdx.x;
+        int q = -1, r = 0;
+        if (i < nets) {
+            const int t = tier ? tier[i] : 0;
+            if (t < ntier) {
+                q = 2 * t + (net_big[i] >= 0 ? 0 : 1);
+                r = atomicAdd(&hist[q], 1);
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < 2 * ntier; k += blockDim.x)
+            if (hist[k]) base[k] = atomicAdd(&cur[k], hist[k]);
+        __syncthreads();
+        if (q >= 0) out[base[q] + r] = (int32_t)i;
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_counts(int32_t *p, int32_t n)
+{
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+inline int grid1d(int64_t n)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+}
+
+template <int NAMAX>
+la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t nbig, int32_t nsmall, hipStream_t s)
+{
+    if (nbig > 0)
+        hipLaunchKernelGGL(k_batched_big<NAMAX>, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, s, a, ba);
+    if (nsmall > 0)
+        hipLaunchKernelGGL(k_batched_dp<NAMAX>, dim3(b->grid_batched), dim3(kThreads), tile_bytes<NAMAX>(), s, a,
+                           ba);
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+template <int NAMAX>
+int occupancy_grid()
+{
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_dp<NAMAX>, kThreads, tile_bytes<NAMAX>());
+    return std::max(1, cus) * std::max(1, per);
+}
+
+}  // namespace
+
+la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers)
+{
+    const int32_t ntier = w->net_tier ? w->num_tiers : 1;
+    const int32_t nb = 2 * ntier;
+    const int32_t R = w->rounds;
+    if (b->claim_cap < R * ntier) {
+        if (b->claim) (void)hipFree(b->claim);
+        b->claim = nullptr;
+        if (hipMalloc((void **)&b->claim, (size_t)R * ntier * sizeof(int32_t)) != hipSuccess)
+            return set_error(LA_ERR_OOM, "claim counters");
+        b->claim_cap = R * ntier;
+    }
+    if (!b->grid_batched) {
+        const int NA = b->NAmax;
+        b->grid_batched = NA <= 4 ? occupancy_grid<4>() : (NA <= 6 ? occupancy_grid<6>() : occupancy_grid<8>());
+    }
+    // partition the nets by batch (big nets first in each) and check the batch indices
+    hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->tier_cnt, nb + 1);
+    hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier, b->nets,
+                       b->net_big, b->tier_cnt, b->tier_cnt + nb);
+    hipLaunchKernelGGL(k_tier_offsets, dim3(1), dim3(256), 0, b->stream, b->tier_cnt, nb, b->tier_off, b->tier_cur,
+                       b->claim, R * ntier);
+    hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier, b->nets,
+                       b->net_big, b->tier_cur, b->tier_nets);
+    LA_HIP(hipGetLastError());
+    std::vector<int32_t> cnt(nb + 1);
+    LA_HIP(hipMemcpyAsync(cnt.data(), b->tier_cnt, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    LA_HIP(hipStreamSynchronize(b->stream));
+    if (cnt[nb]) return set_error(LA_ERR_INVALID_ARG, "net_tier holds a batch index >= num_tiers");
+
+    // the rounds, as one graph: per batch the persistent DP, then the commit; history per round
+    std::vector<int64_t> key = {R, ntier, b->has_prev, w->w_cong, w->w_cap, w->w_d, w->w_via, w->hist_inc,
+                                (int64_t)w->seg_w_q10, (int64_t)w->pin_w_q10, (int64_t)w->lambda_mohm,
+                                (int64_t)lut, (int64_t)H, (int64_t)out_layers};
+    for (int32_t t = 0; t < ntier; ++t) {
+        key.push_back(cnt[2 * t]);
+        key.push_back(cnt[2 * t + 1] > 0);
+    }
+    if (!b->gexec || key != b->gkey) {
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+        if (!b->cap_stream) LA_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        hipStream_t s = b->cap_stream;
+        LA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        la_status st = LA_OK;
+        bool has_prev = b->has_prev;
+        for (int32_t r = 0; r < R && st == LA_OK; ++r) {
+            DPArgs a = make_dp_args(b, w, H, lut);
+            a.w.self_excl = has_prev ? 1 : 0;
+            for (int32_t t = 0; t < ntier && st == LA_OK; ++t) {
+                const int32_t nbig = cnt[2 * t], nsmall = cnt[2 * t + 1];
+                if (nbig + nsmall == 0) continue;
+                hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, b->chg_count, 1);
+                BArgs ba;
+                ba.tier_nets = b->tier_nets;
+                ba.tier_off = b->tier_off;
+                ba.tier = t;
+                ba.ctr = b->claim + r * ntier + t;
+                ba.height = b->height;
+                ba.net_big = b->net_big;
+                ba.bn_order = b->bn_order;
+                ba.bn_lvl = b->bn_lvl;
+                ba.bn_lvl_off = b->bn_lvl_off;
+                ba.bn_nlev = b->bn_nlev;
+                ba.cur = b->cur_layer;
+                ba.vlo = b->vlo;
+                ba.vhi = b->vhi;
+                ba.out_layers = out_layers;
+                ba.has_prev = has_prev ? 1 : 0;
+                ba.cl = ChangeList{b->chg_node, b->chg_old, b->chg_new, b->chg_count};
+                const int NA = b->NAmax;
+                st = NA <= 4   ? launch_batched<4>(b, a, ba, nbig, nsmall, s)
+                     : NA <= 6 ? launch_batched<6>(b, a, ba, nbig, nsmall, s)
+                               : launch_batched<8>(b, a, ba, nbig, nsmall, s);
+                if (st != LA_OK) break;
+                hipStream_t keep = b->stream;
+                b->stream = s;
+                st = commit_changed(b);
+                b->stream = keep;
+            }
+            if (st != LA_OK) break;
+            hipStream_t keep = b->stream;
+            b->stream = s;
+            st = history_update(b, H, w->hist_inc);
+            b->stream = keep;
+            has_prev = true;
+        }
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st != LA_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->gexec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        b->gkey = key;
+    } else {
+        // replay: the work-queue counters start from zero again
+        hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->claim, R * ntier);
+    }
+    LA_HIP(hipGraphLaunch(b->gexec, b->stream));
+    b->has_prev = true;
+    return LA_OK;
+}
+
+}  // namespace gapla

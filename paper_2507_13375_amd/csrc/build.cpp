@@ -342,6 +342,25 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
         for (int64_t v = 0; v < M; ++v) level_nodes[fill[height[v]]++] = (int32_t)v;
     }
 
+    // ---- batched form: nets with more nodes than one LDS tile, nodes grouped by height ---
+    std::vector<int32_t> net_big(std::max<int32_t>(N, 1), -1), bn_order, bn_lvl, bn_lvl_off, bn_nlev;
+    for (int32_t i = 0; i < N; ++i) {
+        const int32_t b0 = net_ptr[i], n = net_ptr[i + 1] - b0;
+        if (n <= kCap) continue;
+        net_big[i] = (int32_t)bn_nlev.size();
+        int32_t hmax = 0;
+        for (int32_t v = b0; v < b0 + n; ++v) hmax = std::max(hmax, height[v]);
+        std::vector<int32_t> cnt(hmax + 2, 0);
+        for (int32_t v = b0; v < b0 + n; ++v) cnt[height[v] + 1]++;
+        for (int32_t h = 0; h <= hmax; ++h) cnt[h + 1] += cnt[h];
+        const int32_t base = (int32_t)bn_order.size();
+        bn_order.resize(base + n);
+        bn_lvl_off.push_back((int32_t)bn_lvl.size());
+        bn_nlev.push_back(hmax + 1);
+        for (int32_t h = 0; h <= hmax + 1; ++h) bn_lvl.push_back(base + cnt[h]);
+        for (int32_t v = b0; v < b0 + n; ++v) bn_order[base + cnt[height[v]]++] = v;
+    }
+
     // ---- allocate and upload --------------------------------------------------------
     la_batch *b = new la_batch();
     b->stream = (hipStream_t)stream;
@@ -388,6 +407,16 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->level_ptr, level_ptr));
     chk(upload(&b->height, height));
     chk(alloc(&b->bucket_nodes, M));
+    b->n_big = (int32_t)bn_nlev.size();
+    chk(upload(&b->net_big, net_big));
+    chk(upload(&b->bn_order, bn_order));
+    chk(upload(&b->bn_lvl, bn_lvl));
+    chk(upload(&b->bn_lvl_off, bn_lvl_off));
+    chk(upload(&b->bn_nlev, bn_nlev));
+    chk(alloc(&b->tier_nets, std::max<int64_t>(N, 1)));
+    chk(alloc(&b->tier_off, 2 * 256 + 2));
+    chk(alloc(&b->tier_cur, 2 * 256 + 2));
+    chk(alloc(&b->tier_cnt, 2 * 256 + 2));
     chk(upload(&b->caps, caps));
     chk(alloc(&b->D, b->E));
     chk(alloc(&b->cur_layer, M));

@@ -1,13 +1,21 @@
-// Device routines of the tree DP (Alg. 3, Sec. III-D look-ahead) and trace-back
-// (Alg. 4), shared by the plain per-level kernels and the batched kernels.
+// Device routines of the tree DP (Alg. 3 with the Sec. III-D look-ahead) and the
+// trace-back (Alg. 4), shared by the plain per-level kernels (state in HBM) and
+// the batched kernels (state in LDS) through a small state-accessor type.
 //
-// For a node n and the layer l its parent segment takes, the DP enumerates the
-// via stacks [b,t] at n that contain l and n's pin layer 0 (b ascending, then t
-// ascending), lets each child take its best layer inside [b,t] by the
-// look-ahead key, and keeps the stack of lowest look-ahead cost f'; ties keep
-// the first (lowest b, then t) stack and the lowest child layer.  The children's
-// running minima are extended one layer at a time as t grows, so each stack
-// costs one key per child whose direction matches layer t.
+// For a node n and the layer l its parent segment takes, the DP considers the
+// via stacks [b,t] at n that contain l and n's pin layer 0, lets each child take
+// its best layer inside [b,t] by the look-ahead key, and keeps the stack of
+// lowest look-ahead cost f'; ties keep the lowest b, then t, and a child's
+// lowest layer.
+//
+// Two evaluation orders give that same result:
+//  - hull candidates (via weight > 0, at most two children): a stack wider than
+//    the hull of l, the pin layer and the chosen child layers costs more than
+//    that hull with the same choices, so only hulls can win.  Each tuple of
+//    child layers names one hull; it is a candidate when every child's choice is
+//    its own key minimum (lowest layer on ties) inside that hull.
+//  - the full enumeration otherwise: b ascending, t ascending, each child's
+//    running minimum extended one layer as t grows.
 #pragma once
 
 #include "la_internal.h"
@@ -16,7 +24,7 @@ namespace gapla {
 
 struct DPArgs {
     TreeDev T;
-    LayerTab tab;
+    LayerTab tab;      // copied into LDS by each kernel (`tb` below) before per-lane use
     DPWeights w;
     const int32_t *D;
     const uint8_t *caps;
@@ -29,7 +37,29 @@ struct DPArgs {
     int32_t NA;
 };
 
-constexpr int kFastChildren = 4;
+// Copies the layer table into LDS: kernels index it with per-lane layer numbers, which
+// must not read the kernel-argument block lane by lane.
+__device__ __forceinline__ void load_tab(const LayerTab &src, LayerTab &dst)
+{
+    const int32_t *s = (const int32_t *)&src;
+    int32_t *d = (int32_t *)&dst;
+    for (int i = threadIdx.x; i < (int)(sizeof(LayerTab) / 4); i += blockDim.x) d[i] = s[i];
+    __syncthreads();
+}
+
+// DP state in HBM, indexed by global node id (plain form).
+struct GlobalState {
+    const DPArgs &a;
+    __device__ GlobalState(const DPArgs &a_) : a(a_) {}
+    __device__ int nch(int32_t s) const { return a.T.ch_ptr[s + 1] - a.T.ch_ptr[s]; }
+    __device__ int32_t ch_state(int32_t s, int q) const { return a.T.ch[a.T.ch_ptr[s] + q]; }
+    __device__ int32_t ch_gid(int32_t s, int q) const { return a.T.ch[a.T.ch_ptr[s] + q]; }
+    __device__ int64_t &F(int32_t s, int j) const { return a.F[(int64_t)s * a.NA + j]; }
+    __device__ int64_t &KA(int32_t s, int j) const { return a.KA[(int64_t)s * a.NA + j]; }
+    __device__ int32_t &S(int32_t s, int j) const { return a.S[(int64_t)s * a.NA + j]; }
+    __device__ uint8_t *bt(int32_t s, int j) const { return a.bt + 2 * ((int64_t)s * a.NA + j); }
+    __device__ uint8_t &sel(int32_t s, int l) const { return a.sel[(int64_t)s * kMaxL + l]; }
+};
 
 // T(w, R, X) = (w * ((R * X) >> 11)) >> 10, operands non-negative
 __device__ __forceinline__ int64_t Tq(int64_t w, int64_t R, int64_t X) { return (w * ((R * X) >> 11)) >> 10; }
@@ -41,10 +71,10 @@ __device__ __forceinline__ int64_t rvia_d(const LayerTab &t, int a, int b)
 }
 
 // congestion cost kappa_n(l): marginal Eq. 3 cost plus history along the GCell edges of segment n
-__device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, int32_t n, int l)
+__device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb, int32_t n, int l)
 {
     const int32_t len = a.T.len[n];
-    const int32_t step = a.T.dir[n] == 0 ? a.tab.L : a.tab.X * a.tab.L;
+    const int32_t step = a.T.dir[n] == 0 ? tb.L : tb.X * tb.L;
     int32_t g = a.T.g0[n] + l;
     const int32_t self = (a.w.self_excl && a.prev[n] == l) ? 1 : 0;
     const int32_t *lut = a.w.lut + l * 2 * kNDelta;
@@ -63,17 +93,20 @@ struct ChildKey {
     int32_t Z;
 };
 
-// key, f-contribution and downstream capacitance of child c on layer t under parent layer l
-__device__ __forceinline__ ChildKey child_key(const DPArgs &a, int32_t c, int32_t clen, int64_t cw, int l, int t)
+// key, f-contribution and downstream capacitance of a child (state cs, attributes of node c)
+// on layer t under parent layer l
+template <class St>
+__device__ __forceinline__ ChildKey child_key(const DPArgs &a, const LayerTab &tb, const St &st, int32_t cs,
+                                              int32_t clen, int64_t cw, int l, int t)
 {
-    const int64_t idx = (int64_t)c * a.NA + a.tab.jidx[t];
-    const int32_t Cc = a.tab.c[t] * clen;
-    const int32_t Sc = a.S[idx];
+    const int jc = tb.jidx[t];
+    const int32_t Cc = tb.c[t] * clen;
+    const int32_t Sc = st.S(cs, jc);
     const int64_t X = (int64_t)Cc + 2 * (int64_t)Sc;
-    const int64_t tv = a.w.w_d * Tq(cw, rvia_d(a.tab, l, t), X);
+    const int64_t tv = a.w.w_d * Tq(cw, rvia_d(tb, l, t), X);
     ChildKey r;
-    r.V = a.F[idx] + tv;
-    r.key = a.KA[idx] + tv;
+    r.V = st.F(cs, jc) + tv;
+    r.key = st.KA(cs, jc) + tv;
     r.Z = Cc + Sc;
     return r;
 }
@@ -83,32 +116,43 @@ __device__ __forceinline__ bool child_layer_ok(const LayerTab &tab, int cdir, in
     return tab.jidx[t] >= 0 && tab.dir[t] == cdir;
 }
 
-// DP of node n for the entering layer l (index j in its direction list; j = 0, l = 0 at the root).
-__device__ void dp_node_layer(const DPArgs &a, int32_t n, int l, int j, bool root)
+// Best candidate so far; `better` applies the (f', b, t) order of the full enumeration.
+struct Best {
+    int64_t fp = INT64_MAX, f = 0, S = 0;
+    int b = 0, t = 0;
+    __device__ bool better(int64_t fp_, int b_, int t_) const
+    {
+        return fp_ < fp || (fp_ == fp && (b_ < b || (b_ == b && t_ < t)));
+    }
+};
+
+// DP of node n (state index s, global id n) for its entering layer l (index j in its
+// direction list; j = 0 and l = 0 at the root).  NAMAX bounds the routable layers per direction.
+template <class St, int NAMAX>
+__device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int32_t n, int l,
+                                        int j, bool root)
 {
-    const int L = a.tab.L;
-    const uint8_t fl = a.T.flags[n];
-    const bool pin = fl & (kSink | kDriver);
+    const int L = tb.L;
+    const bool pin = a.T.flags[n] & (kSink | kDriver);
     const int lo = pin ? 0 : l;
     const int hi = l;
     int64_t own_const = 0, Cs = 0, Rw = 0, segw = 0, lam = 0;
     if (!root) {
         const int32_t len = a.T.len[n];
-        Cs = (int64_t)a.tab.c[l] * len;
-        Rw = (int64_t)a.tab.r[l] * len;
-        own_const = a.w.w_cong * kappa_seg(a, n, l) + a.w.w_cap * Cs;
+        Cs = (int64_t)tb.c[l] * len;
+        Rw = (int64_t)tb.r[l] * len;
+        own_const = a.w.w_cong * kappa_seg(a, tb, n, l) + a.w.w_cap * Cs;
         segw = a.w.seg_w[n];
         lam = a.w.lam[n];
     }
     const int32_t cpin = a.T.cpin[n];
     const int32_t sid = a.T.sink_id[n];
-    const int64_t pin_term = sid >= 0 ? a.w.w_d * Tq(a.w.pin_w[sid], rvia_d(a.tab, l, 0), 2 * (int64_t)cpin) : 0;
-    const int32_t c0 = a.T.ch_ptr[n], k = a.T.ch_ptr[n + 1] - c0;
+    const int64_t pin_term = sid >= 0 ? a.w.w_d * Tq(a.w.pin_w[sid], rvia_d(tb, l, 0), 2 * (int64_t)cpin) : 0;
+    const int k = st.nch(s);
 
-    int64_t best_fp = INT64_MAX, best_f = 0, best_S = 0;
-    int best_b = 0, best_t = 0;
-    uint8_t best_sel[kFastChildren] = {0, 0, 0, 0};
-
+    Best best;
+    uint8_t best_sel[2] = {0, 0};
+    // f and f' of stack [b,t] given the children's summed f-contributions and capacitances
     auto eval = [&](int b, int t, int64_t sumV, int64_t sumZ) -> bool {
         const int64_t Sn = cpin + sumZ;
         int64_t f = a.w.w_via * (t - b) + sumV + pin_term;
@@ -117,167 +161,205 @@ __device__ void dp_node_layer(const DPArgs &a, int32_t n, int l, int j, bool roo
             f += own_const + a.w.w_d * Tq(segw, Rw, Cs + 2 * Sn);
             fp = f + a.w.w_d * ((lam * 2 * (Cs + Sn)) >> 11);
         }
-        if (fp < best_fp) {
-            best_fp = fp;
-            best_f = f;
-            best_S = Sn;
-            best_b = b;
-            best_t = t;
+        if (best.better(fp, b, t)) {
+            best.fp = fp;
+            best.f = f;
+            best.S = Sn;
+            best.b = b;
+            best.t = t;
             return true;
         }
         return false;
     };
 
-    if (k <= kFastChildren) {
-        int32_t cid[kFastChildren], clen[kFastChildren];
-        int cdir[kFastChildren];
-        int64_t cw[kFastChildren];
+    if (a.w.w_via > 0 && k <= 2) {
+        // ---- hull candidates --------------------------------------------------------
+        int64_t kk[2][NAMAX], kv[2][NAMAX];
+        int32_t kz[2][NAMAX];
+        int nc[2] = {0, 0}, cd[2] = {0, 0};
 #pragma unroll
-        for (int q = 0; q < kFastChildren; ++q) {
+        for (int q = 0; q < 2; ++q) {
             if (q < k) {
-                cid[q] = a.T.ch[c0 + q];
-                cdir[q] = a.T.dir[cid[q]];
-                clen[q] = a.T.len[cid[q]];
-                cw[q] = a.w.seg_w[cid[q]];
-            } else {
-                cid[q] = 0;
-                cdir[q] = -1;
-                clen[q] = 0;
-                cw[q] = 0;
+                const int32_t cs = st.ch_state(s, q), cg = st.ch_gid(s, q);
+                cd[q] = a.T.dir[cg];
+                nc[q] = tb.nA[cd[q]];
+                const int32_t clen = a.T.len[cg];
+                const int64_t cw = a.w.seg_w[cg];
+#pragma unroll
+                for (int jj = 0; jj < NAMAX; ++jj) {
+                    if (jj < nc[q]) {
+                        const ChildKey ck = child_key(a, tb, st, cs, clen, cw, l, tb.lay[cd[q]][jj]);
+                        kk[q][jj] = ck.key;
+                        kv[q][jj] = ck.V;
+                        kz[q][jj] = ck.Z;
+                    } else {
+                        kk[q][jj] = 0;
+                        kv[q][jj] = 0;
+                        kz[q][jj] = 0;
+                    }
+                }
             }
         }
-        for (int b = 0; b <= lo; ++b) {
-            bool have[kFastChildren];
-            int64_t bk[kFastChildren], bV[kFastChildren];
-            int32_t bZ[kFastChildren];
-            uint8_t bl[kFastChildren];
+        // is index jq the lowest key minimum of child q over layers [b, t]?
+        // (q and jq are compile-time after unrolling, so every index stays in registers)
+        auto is_min = [&](int q, int jq, int b, int t) -> bool {
+            bool ok = true;
+            const int64_t mine = kk[q][jq];
 #pragma unroll
-            for (int q = 0; q < kFastChildren; ++q) {
-                have[q] = q >= k;   // absent children never block a stack
-                bk[q] = 0;
-                bV[q] = 0;
-                bZ[q] = 0;
-                bl[q] = 0;
+            for (int jj = 0; jj < NAMAX; ++jj) {
+                if (jj < nc[q] && jj != jq) {
+                    const int ly = tb.lay[cd[q]][jj];
+                    if (ly >= b && ly <= t && (kk[q][jj] < mine || (kk[q][jj] == mine && jj < jq))) ok = false;
+                }
             }
-            for (int t = b; t < L; ++t) {
+            return ok;
+        };
+        if (k == 0) {
+            eval(lo, hi, 0, 0);
+        } else if (k == 1) {
 #pragma unroll
-                for (int q = 0; q < kFastChildren; ++q) {
-                    if (q < k && child_layer_ok(a.tab, cdir[q], t)) {
-                        const ChildKey ck = child_key(a, cid[q], clen[q], cw[q], l, t);
-                        if (!have[q] || ck.key < bk[q]) {
-                            have[q] = true;
-                            bk[q] = ck.key;
-                            bV[q] = ck.V;
-                            bZ[q] = ck.Z;
-                            bl[q] = (uint8_t)t;
+            for (int j1 = 0; j1 < NAMAX; ++j1) {
+                if (j1 < nc[0]) {
+                    const int L1 = tb.lay[cd[0]][j1];
+                    const int b = min(lo, L1), t = max(hi, L1);
+                    if (is_min(0, j1, b, t) && eval(b, t, kv[0][j1], kz[0][j1])) best_sel[0] = (uint8_t)L1;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j1 = 0; j1 < NAMAX; ++j1) {
+                if (j1 < nc[0]) {
+                    const int L1 = tb.lay[cd[0]][j1];
+#pragma unroll
+                    for (int j2 = 0; j2 < NAMAX; ++j2) {
+                        if (j2 < nc[1]) {
+                            const int L2 = tb.lay[cd[1]][j2];
+                            const int b = min(lo, min(L1, L2)), t = max(hi, max(L1, L2));
+                            if (is_min(0, j1, b, t) && is_min(1, j2, b, t) &&
+                                eval(b, t, kv[0][j1] + kv[1][j2], (int64_t)kz[0][j1] + kz[1][j2])) {
+                                best_sel[0] = (uint8_t)L1;
+                                best_sel[1] = (uint8_t)L2;
+                            }
                         }
                     }
                 }
-                if (t < hi) continue;
-                bool ok = true;
-                int64_t sumV = 0, sumZ = 0;
-#pragma unroll
-                for (int q = 0; q < kFastChildren; ++q) {
-                    ok = ok && have[q];
-                    sumV += bV[q];
-                    sumZ += bZ[q];
-                }
-                if (!ok) continue;
-                if (eval(b, t, sumV, sumZ)) {
-#pragma unroll
-                    for (int q = 0; q < kFastChildren; ++q) best_sel[q] = bl[q];
-                }
             }
         }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (q < k) st.sel(st.ch_state(s, q), l) = best_sel[q];
     } else {
-        // many children: each stack rescans every child (the definition, written out)
+        // ---- full enumeration: every stack, each child rescanned ------------------------
         for (int b = 0; b <= lo; ++b)
             for (int t = hi; t < L; ++t) {
                 bool ok = true;
                 int64_t sumV = 0, sumZ = 0;
                 for (int q = 0; q < k && ok; ++q) {
-                    const int32_t c = a.T.ch[c0 + q];
-                    const int cd = a.T.dir[c];
-                    const int32_t cl = a.T.len[c];
-                    const int64_t w = a.w.seg_w[c];
+                    const int32_t cs = st.ch_state(s, q), cg = st.ch_gid(s, q);
+                    const int cdr = a.T.dir[cg];
+                    const int32_t cl = a.T.len[cg];
+                    const int64_t w = a.w.seg_w[cg];
                     bool have = false;
-                    ChildKey best{0, 0, 0};
+                    ChildKey bestc{0, 0, 0};
                     for (int lc = b; lc <= t; ++lc) {
-                        if (!child_layer_ok(a.tab, cd, lc)) continue;
-                        const ChildKey ck = child_key(a, c, cl, w, l, lc);
-                        if (!have || ck.key < best.key) {
+                        if (!child_layer_ok(tb, cdr, lc)) continue;
+                        const ChildKey ck = child_key(a, tb, st, cs, cl, w, l, lc);
+                        if (!have || ck.key < bestc.key) {
                             have = true;
-                            best = ck;
+                            bestc = ck;
                         }
                     }
                     ok = have;
-                    sumV += best.V;
-                    sumZ += best.Z;
+                    sumV += bestc.V;
+                    sumZ += bestc.Z;
                 }
                 if (ok) eval(b, t, sumV, sumZ);
             }
-    }
-
-    const int64_t idx = (int64_t)n * a.NA + j;
-    a.F[idx] = best_f;
-    a.S[idx] = (int32_t)best_S;
-    if (!root) a.KA[idx] = best_f + a.w.w_d * ((lam * 2 * (Cs + best_S)) >> 11);
-    a.bt[2 * idx] = (uint8_t)best_b;
-    a.bt[2 * idx + 1] = (uint8_t)best_t;
-    if (k <= kFastChildren) {
-        for (int q = 0; q < k; ++q) a.sel[(int64_t)a.T.ch[c0 + q] * kMaxL + l] = best_sel[q];
-    } else {
+        // each child's layer at the chosen stack, by the same rule
         for (int q = 0; q < k; ++q) {
-            const int32_t c = a.T.ch[c0 + q];
-            const int cd = a.T.dir[c];
-            const int32_t cl = a.T.len[c];
-            const int64_t w = a.w.seg_w[c];
+            const int32_t cs = st.ch_state(s, q), cg = st.ch_gid(s, q);
+            const int cdr = a.T.dir[cg];
+            const int32_t cl = a.T.len[cg];
+            const int64_t w = a.w.seg_w[cg];
             bool have = false;
             int64_t bk = 0;
             int bl = 0;
-            for (int lc = best_b; lc <= best_t; ++lc) {
-                if (!child_layer_ok(a.tab, cd, lc)) continue;
-                const ChildKey ck = child_key(a, c, cl, w, l, lc);
+            for (int lc = best.b; lc <= best.t; ++lc) {
+                if (!child_layer_ok(tb, cdr, lc)) continue;
+                const ChildKey ck = child_key(a, tb, st, cs, cl, w, l, lc);
                 if (!have || ck.key < bk) {
                     have = true;
                     bk = ck.key;
                     bl = lc;
                 }
             }
-            a.sel[(int64_t)c * kMaxL + l] = (uint8_t)bl;
+            st.sel(cs, l) = (uint8_t)bl;
         }
+    }
+
+    st.F(s, j) = best.f;
+    st.S(s, j) = (int32_t)best.S;
+    if (!root) st.KA(s, j) = best.f + a.w.w_d * ((lam * 2 * (Cs + best.S)) >> 11);
+    uint8_t *bt = st.bt(s, j);
+    bt[0] = (uint8_t)best.b;
+    bt[1] = (uint8_t)best.t;
+}
+
+// Commit list of the current batch: segments whose layer changed (old = 255 when the
+// segment has no previous layer).
+struct ChangeList {
+    int32_t *node;
+    uint8_t *old_l, *new_l;
+    int32_t *count;
+};
+
+// Appends one entry per lane with `pred`, one atomic per wavefront.  Every lane of the
+// wavefront must call it (uniform control flow).
+__device__ __forceinline__ void append_change(const ChangeList &cl, bool pred, int32_t n, uint8_t old_l,
+                                              uint8_t new_l)
+{
+    const uint64_t mask = __ballot(pred);
+    if (!mask) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(cl.count, (int32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        const int32_t pos = base + (int32_t)__popcll(mask & __lanemask_lt());
+        cl.node[pos] = n;
+        cl.old_l[pos] = old_l;
+        cl.new_l[pos] = new_l;
     }
 }
 
 // Alg. 4 at node n: its layer is the one its parent recorded for the parent's entering
-// layer; its via span is the stack recorded for its own entering layer.  Segments
-// whose layer changed go to the commit list (old = 255 when there is no previous layer).
-__device__ __forceinline__ void trace_node(const DPArgs &a, int32_t n, uint8_t *cur, uint8_t *vlo, uint8_t *vhi,
-                                           uint8_t *out_layers, int has_prev, int32_t *chg_node, uint8_t *chg_old,
-                                           uint8_t *chg_new, int32_t *chg_count)
+// layer; its via span is the stack recorded for its own entering layer.
+// lp: the parent's entering layer (0 at a root's children).  Returns n's entering layer
+// and sets *changed / *old_l for the commit list.
+template <class St>
+__device__ __forceinline__ int trace_node(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int32_t n,
+                                          int lp, bool root,
+                                          uint8_t *cur, uint8_t *vlo, uint8_t *vhi, uint8_t *out_layers,
+                                          int has_prev, bool *changed, uint8_t *old_l)
 {
-    const int32_t p = a.T.parent[n];
     int ln = 0, j = 0;
-    if (p >= 0) {
-        const int lp = a.T.parent[p] < 0 ? 0 : (cur[p] & (kMaxL - 1));
-        ln = a.sel[(int64_t)n * kMaxL + lp];
+    if (!root) {
+        ln = st.sel(s, lp & (kMaxL - 1));
         // the parent's DP recorded a routable layer of n's direction; the masks only keep
         // every index inside its array
-        ln = ln < a.tab.L ? ln : 0;
-        j = a.tab.jidx[ln] < 0 ? 0 : a.tab.jidx[ln];
+        ln = ln < tb.L ? ln : 0;
+        j = tb.jidx[ln] < 0 ? 0 : tb.jidx[ln];
     }
-    const int64_t idx = (int64_t)n * a.NA + j;
-    vlo[n] = a.bt[2 * idx];
-    vhi[n] = a.bt[2 * idx + 1];
+    const uint8_t *bt = st.bt(s, j);
+    vlo[n] = bt[0];
+    vhi[n] = bt[1];
     const uint8_t old = cur[n];
     cur[n] = (uint8_t)ln;
     if (out_layers) out_layers[n] = (uint8_t)ln;
-    if (p >= 0 && (!has_prev || old != ln)) {
-        const int32_t pos = atomicAdd(chg_count, 1);
-        chg_node[pos] = n;
-        chg_old[pos] = has_prev ? old : (uint8_t)255;
-        chg_new[pos] = (uint8_t)ln;
-    }
+    *changed = !root && (!has_prev || old != ln);
+    *old_l = has_prev ? old : (uint8_t)255;
+    return ln;
 }
 
 }  // namespace gapla

@@ -80,8 +80,16 @@ __device__ __forceinline__ int64_t rvia(const LayerTab &t, int a, int b)
 // edges (Sec. III-B); after it, lumped via from the parent's entering layer plus
 // wire, and the via down to layer 0 at each sink pin.
 // ---------------------------------------------------------------------------
-__global__ void k_rc(TreeDev T, LayerTab tab, const uint8_t *lay, float *R, float *C)
+__global__ void k_rc(TreeDev T, LayerTab targ, const uint8_t *lay, float *R, float *C)
 {
+    // per-lane layer lookups read an LDS copy of the table, not the kernel arguments
+    __shared__ LayerTab tab;
+    {
+        const int32_t *s = (const int32_t *)&targ;
+        int32_t *d = (int32_t *)&tab;
+        for (int i = threadIdx.x; i < (int)(sizeof(LayerTab) / 4); i += blockDim.x) d[i] = s[i];
+        __syncthreads();
+    }
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < T.nodes + T.sinks;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (i < T.nodes) {

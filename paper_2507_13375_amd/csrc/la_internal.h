@@ -12,6 +12,8 @@
 namespace gapla {
 
 constexpr int kMaxL = 16;          // layers supported (4-bit layer ids)
+constexpr int kCap = 256;          // nodes of one batched-form workgroup's LDS tile
+constexpr int kClaim = 32;         // nets claimed per work-queue grab
 constexpr int kMaxA = 8;           // routable layers per direction
 constexpr int kNDelta = 64;        // congestion table entries per (layer, zero-capacity flag)
 constexpr int kDeltaMin = -32;
@@ -107,6 +109,20 @@ struct la_batch {
 
     // default congestion table (device)
     int32_t *lut = nullptr;
+
+    // batched form: nets too large for one workgroup's LDS keep their DP state in HBM and
+    // walk their own height levels (bn_order: node ids per net by height; bn_lvl: level
+    // starts into bn_order; bn_lvl_off/bn_nlev: each big net's first level and level count)
+    int32_t *net_big = nullptr;
+    int32_t *bn_order = nullptr, *bn_lvl = nullptr, *bn_lvl_off = nullptr, *bn_nlev = nullptr;
+    int32_t n_big = 0;
+    int32_t *tier_nets = nullptr, *tier_off = nullptr, *tier_cur = nullptr, *tier_cnt = nullptr;
+    int32_t *claim = nullptr;
+    int32_t claim_cap = 0;
+    int32_t grid_batched = 0;       // persistent workgroups per batched launch
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gkey;
 
     // RC and Elmore state
     float *R = nullptr, *C = nullptr;   // batch RC views [nodes+sinks]

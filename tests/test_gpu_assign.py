@@ -11,7 +11,7 @@ from helpers import make_instance
 
 pytestmark = pytest.mark.gpu
 
-FORMS = [la.LA_FORM_PLAIN]
+FORMS = [la.LA_FORM_PLAIN, la.LA_FORM_BATCHED]
 
 
 def _weights_from_oracle(inst):
@@ -58,9 +58,10 @@ def _star(k, L=8):
     return nodes, wps
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("case", ["star6", "star8_sink_centre", "l16", "l2", "min_layer", "driver_only",
                                   "zero_weights"])
-def test_edge_cases(case):
+def test_edge_cases(case, form):
     L, min_layer, kw = 8, 0, {}
     if case == "star6":
         nets = [_star(6), _star(3)]
@@ -95,7 +96,7 @@ def test_edge_cases(case):
     pw = rng.integers(0, 1025, max(T.sinks, 1))
     lam = rng.integers(0, 500000, T.nodes)
     o = oracle_assign(inst, sw, pw, lam, None, rounds=2, min_layer=min_layer, **kw)
-    g = GpuRun(inst, min_layer=min_layer).assign(sw, pw, lam, None, rounds=2, **kw)
+    g = GpuRun(inst, min_layer=min_layer).assign(sw, pw, lam, None, rounds=2, form=form, **kw)
     assert_assign_equal(g, o, case)
 
 
@@ -165,3 +166,61 @@ def test_config3_full_size_sampled(form):
     nonroot = T.parent >= 0
     per_layer = np.bincount(res["layers"][nonroot], weights=T.len[nonroot], minlength=inst.L)
     assert np.array_equal(res["D"].reshape(-1, inst.L).sum(0), per_layer.astype(np.int64))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_nets_larger_than_a_tile(form):
+    # high-fanout nets (hundreds of layer-assignment nodes) take the HBM-state path
+    inst = gen.generate(400, 160, 160, 8, 17, pin_law=1, pin_max=12, placement=2, fanout_every=37, fanout_min=150,
+                        fanout_max=320, cap_min=2, cap_max=8)
+    T = oracle.Tree(inst)
+    sizes = np.diff(T.net_ptr)
+    assert (sizes > 256).sum() >= 5
+    sw = gen.synthetic_weights(T.nodes, T.sinks, T.nets, seed=8, n_tiers=3)
+    say("big nets form=%d max nodes %d" % (form, sizes.max()))
+    o = oracle_assign(inst, sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], rounds=2)
+    g = GpuRun(inst).assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], num_tiers=3,
+                            rounds=2, form=form)
+    assert_assign_equal(g, o, "big")
+
+
+def test_graph_replays_match_eager_plain_form():
+    # the batched rounds run as a captured hipGraph; every replay, with eager work and
+    # synchronisation in between, must give the plain (eager) form's result
+    inst = gen.config(2, num_nets=30000)
+    w = _weights_from_oracle(inst)
+    ref = GpuRun(inst).assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=3)
+    g = GpuRun(inst)
+    for rep in range(4):
+        la.la_reset(g.b)
+        g.H.zero_()
+        res = g.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=3, form=la.LA_FORM_BATCHED)
+        for k in ("layers", "vlo", "vhi", "D", "H"):
+            assert np.array_equal(res[k], ref[k]), (rep, k)
+        say("replay %d ok" % rep)
+
+
+def test_checkpoint_resume_on_gpu():
+    inst = gen.config(1)
+    w = _weights_from_oracle(inst)
+    g = GpuRun(inst)
+    g.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=2, form=la.LA_FORM_BATCHED)
+    state = la.la_save_state(g.b)
+    H_saved = g.H.clone()
+    nxt = g.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=1, form=la.LA_FORM_BATCHED)
+    g2 = GpuRun(inst)
+    la.la_load_state(g2.b, state)
+    g2.H.copy_(H_saved)
+    again = g2.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=1, form=la.LA_FORM_PLAIN)
+    for k in ("layers", "vlo", "vhi", "D", "H"):
+        assert np.array_equal(nxt[k], again[k]), k
+
+
+def test_out_of_range_batch_index_is_rejected():
+    inst = gen.config(1)
+    g = GpuRun(inst)
+    n = g.b.nodes
+    for form in FORMS:
+        with pytest.raises(la.LAError) as e:
+            g.assign(np.zeros(n), np.zeros(g.b.sinks), np.zeros(n), np.full(g.b.nets, 5), num_tiers=3, form=form)
+        assert e.value.code == la.LA_ERR_INVALID_ARG
