@@ -244,7 +244,7 @@ void la_free_batch(la_batch *b)
     void *ptrs[] = {b->parent, b->ch_ptr, b->ch, b->net, b->net_ptr, b->len, b->g0, b->cpin, b->sink_id,
                     b->sink_node, b->net_sink_ptr, b->rest, b->budget_fs, b->rdrv, b->dir, b->flags,
                     b->level_nodes, b->level_ptr, b->height, b->caps, b->D, b->cur_layer, b->vlo, b->vhi,
-                    b->F, b->KA, b->S, b->bt, b->sel, b->bucket_nodes, b->bucket_cnt, b->bucket_cur,
+                    b->F, b->S, b->bt, b->sel, b->bucket_nodes, b->bucket_cnt, b->bucket_cur,
                     b->chg_node, b->chg_count, b->chg_old, b->chg_new, b->lut, b->R, b->C, b->el_S,
                     b->el_Slo, b->el_t, b->el_tlo, b->el_G, b->el_Glo, b->el_Sig, b->el_Siglo, b->slack,
                     b->scratch_f, b->wns_bits, b->red, b->net_big, b->bn_order, b->bn_lvl, b->bn_lvl_off,

@@ -44,7 +44,8 @@ __global__ void k_dp_level(DPArgs a, const int32_t *nodes, int32_t cnt)
         l = tb.lay[d][j];
     }
     GlobalState st(a);
-    dp_node<GlobalState, NAMAX>(a, tb, st, n, n, l, j, root);
+    const int64_t kap = root ? 0 : kappa_seg(a, tb, n, l);
+    dp_node<GlobalState, NAMAX>(a, tb, st, n, n, l, j, root, kap);
 }
 
 // Alg. 4: each node takes the layer its parent recorded for the parent's entering layer.
@@ -64,7 +65,7 @@ __global__ void k_trace_level(DPArgs a, const int32_t *nodes, int32_t cnt, uint8
         const int32_t p = a.T.parent[n];
         const int lp = (p < 0 || a.T.parent[p] < 0) ? 0 : cur[p];
         GlobalState st(a);
-        ln = trace_node(a, tb, st, n, n, lp, p < 0, cur, vlo, vhi, out_layers, has_prev, &changed, &old_l);
+        ln = trace_node(tb, st, n, n, lp, p < 0, cur, vlo, vhi, out_layers, has_prev, &changed, &old_l);
     }
     append_change(ChangeList{chg_node, chg_old, chg_new, chg_count}, changed, n, old_l, (uint8_t)ln);
 }
@@ -108,11 +109,19 @@ __global__ void k_history(const int32_t *D, const uint8_t *caps, int32_t *H, int
 // atomics off a handful of hot addresses.
 constexpr int kLdsBuckets = 4096;
 
+// bucket of node v: (batch, height, number of children clipped to 3), so that the nodes of
+// one level are grouped by how much DP work they carry
+__device__ __forceinline__ int64_t bucket_key(const TreeDev &T, const int32_t *height, int t, int32_t levels, int64_t v)
+{
+    const int32_t k = T.ch_ptr[v + 1] - T.ch_ptr[v];
+    return ((((int64_t)t * levels + height[v]) << 2) | (k < 3 ? k : 3));
+}
+
 __global__ void k_bucket_count(TreeDev T, const int32_t *height, const uint8_t *tier, int32_t ntier, int32_t levels,
                                int32_t *counts, int32_t *bad)
 {
     __shared__ int32_t hist[kLdsBuckets];
-    const int64_t nb = (int64_t)ntier * levels;
+    const int64_t nb = (int64_t)ntier * levels * 4;
     const bool local = nb <= kLdsBuckets;
     if (local)
         for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
@@ -123,7 +132,7 @@ __global__ void k_bucket_count(TreeDev T, const int32_t *height, const uint8_t *
             atomicAdd(bad, 1);
             continue;
         }
-        const int64_t q = (int64_t)t * levels + height[v];
+        const int64_t q = bucket_key(T, height, t, levels, v);
         if (local) atomicAdd(&hist[q], 1);
         else atomicAdd(&counts[q], 1);
     }
@@ -138,13 +147,13 @@ __global__ void k_bucket_scatter(TreeDev T, const int32_t *height, const uint8_t
 {
     __shared__ int32_t hist[kLdsBuckets];
     __shared__ int32_t base[kLdsBuckets];
-    const int64_t nb = (int64_t)ntier * levels;
+    const int64_t nb = (int64_t)ntier * levels * 4;
     if (nb > kLdsBuckets) {
         for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes;
              v += (int64_t)gridDim.x * blockDim.x) {
             const int t = tier ? tier[T.net[v]] : 0;
             if (t >= ntier) continue;
-            out[atomicAdd(&cursor[(int64_t)t * levels + height[v]], 1)] = (int32_t)v;
+            out[atomicAdd(&cursor[bucket_key(T, height, t, levels, v)], 1)] = (int32_t)v;
         }
         return;
     }
@@ -158,7 +167,7 @@ __global__ void k_bucket_scatter(TreeDev T, const int32_t *height, const uint8_t
         if (v < T.nodes) {
             const int t = tier ? tier[T.net[v]] : 0;
             if (t < ntier) {
-                q = (int64_t)t * levels + height[v];
+                q = bucket_key(T, height, t, levels, v);
                 r = atomicAdd(&hist[q], 1);
             }
         }
@@ -208,7 +217,6 @@ DPArgs make_dp_args(la_batch *b, const la_weights *w, const int32_t *H, const in
     a.H = H;
     a.prev = b->cur_layer;
     a.F = b->F;
-    a.KA = b->KA;
     a.S = b->S;
     a.bt = b->bt;
     a.sel = b->sel;
@@ -238,11 +246,11 @@ la_status history_update(la_batch *b, int32_t *H, int32_t inc)
     return LA_OK;
 }
 
-// Group nodes by (batch, height); returns the per-bucket counts on the host.
+// Group nodes by (batch, height, child class); returns the per-bucket counts on the host.
 la_status bucket_nodes(la_batch *b, const uint8_t *tier, int32_t ntier, std::vector<int32_t> &counts)
 {
     const int32_t Hh = b->levels;
-    const size_t need = (size_t)ntier * Hh;
+    const size_t need = (size_t)ntier * Hh * 4;
     if (need + 1 > b->bucket_cap) {
         if (b->bucket_cnt) (void)hipFree(b->bucket_cnt);
         if (b->bucket_cur) (void)hipFree(b->bucket_cur);
@@ -292,9 +300,10 @@ la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32
     for (int32_t r = 0; r < w->rounds; ++r) {
         DPArgs a = make_dp_args(b, w, H, lut);
         for (int32_t t = 0; t < ntier; ++t) {
+            // one level = the four consecutive child-class buckets of (batch, height)
             for (int32_t h = 0; h < Hh; ++h) {
-                const int64_t q = (int64_t)t * Hh + h;
-                const int32_t cnt = counts[q];
+                const int64_t q = ((int64_t)t * Hh + h) * 4;
+                const int32_t cnt = (int32_t)(off[q + 4] - off[q]);
                 if (!cnt) continue;
                 const int64_t threads = (int64_t)cnt * a.NA;
                 const dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
@@ -307,8 +316,8 @@ la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32
             }
             hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->stream, b->chg_count, (int64_t)1);
             for (int32_t h = Hh - 1; h >= 0; --h) {
-                const int64_t q = (int64_t)t * Hh + h;
-                const int32_t cnt = counts[q];
+                const int64_t q = ((int64_t)t * Hh + h) * 4;
+                const int32_t cnt = (int32_t)(off[q + 4] - off[q]);
                 if (!cnt) continue;
                 hipLaunchKernelGGL(k_trace_level, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, a,
                                    b->bucket_nodes + off[q], cnt, b->cur_layer, b->vlo, b->vhi, out_layers,

@@ -1,11 +1,11 @@
 // Batched form of the layer-assignment DP: one persistent launch per batch (tier)
 // instead of one launch per tree level.  Workgroups pull groups of nets from a
-// work queue, stage whole nets in LDS (DP state, children, height order), run the
-// bottom-up DP of Alg. 3 and the top-down trace-back of Alg. 4 with workgroup
-// barriers between levels, and append changed segments for the commit.  Nets
-// larger than one LDS tile keep their DP state in HBM and walk their own levels
-// inside the same workgroup.  All negotiation rounds of a la_assign call are
-// captured once as a hipGraph and replayed.
+// work queue, stage whole nets in LDS (DP state, congestion costs, children,
+// height order), run the bottom-up DP of Alg. 3 and the top-down trace-back of
+// Alg. 4 with workgroup barriers between levels, and append changed segments for
+// the commit.  Nets larger than one LDS tile keep their DP state in HBM and walk
+// their own levels in a workgroup of their own.  All negotiation rounds of a
+// la_assign call are captured once as a hipGraph and replayed.
 //
 // Every net's result depends only on its own inputs and the demand snapshot of its
 // batch, so the layers equal the plain form's for any grid size or claim order.
@@ -26,11 +26,12 @@ la_status history_update(la_batch *b, int32_t *H, int32_t inc);
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kBook = 256;   // ints of per-claim bookkeeping
 
 // DP state of one LDS tile, indexed by tile-local node id.
 template <int NAMAX>
 struct LdsState {
-    int64_t *F_, *KA_;
+    int64_t *F_;
     int32_t *S_;
     uint8_t *bt_, *sel_;
     const int16_t *chp, *chl;
@@ -39,27 +40,33 @@ struct LdsState {
     __device__ int32_t ch_state(int32_t s, int q) const { return chl[chp[s] + q]; }
     __device__ int32_t ch_gid(int32_t s, int q) const { return gid[chl[chp[s] + q]]; }
     __device__ int64_t &F(int32_t s, int j) const { return F_[s * NAMAX + j]; }
-    __device__ int64_t &KA(int32_t s, int j) const { return KA_[s * NAMAX + j]; }
     __device__ int32_t &S(int32_t s, int j) const { return S_[s * NAMAX + j]; }
     __device__ uint8_t *bt(int32_t s, int j) const { return bt_ + 2 * (s * NAMAX + j); }
     __device__ uint8_t &sel(int32_t s, int l) const { return sel_[s * kMaxL + l]; }
 };
 
-// LDS bytes of one tile
+// LDS layout of one tile (byte offsets), shared by the host launch and the kernel
 template <int NAMAX>
-constexpr size_t tile_bytes()
-{
-    return (size_t)kCap * NAMAX * 8 * 2      // F, KA
-           + (size_t)kCap * NAMAX * 4        // S
-           + (size_t)kCap * 4                // gid
-           + (size_t)kCap * 2 * 4 + 2 * 2    // par, chl, order, lvl (+ chp has kCap+1)
-           + (size_t)(kCap + 1) * 2          // chp
-           + (size_t)kCap * NAMAX * 2        // bt
-           + (size_t)kCap * kMaxL            // sel
-           + (size_t)kCap                    // entering layer during trace
-           + (size_t)(kCap + 2) * 4          // level starts
-           + 64 * 4 * 8;                     // per-claim bookkeeping
-}
+struct Tile {
+    static constexpr int nkey = 4 * kCap + 4;                       // (height, child class) buckets
+    static constexpr size_t F = 0;                                  // int64 [kCap][NAMAX]
+    static constexpr size_t KAP = F + (size_t)kCap * NAMAX * 8;     // int64 [kCap][NAMAX] congestion cost
+    static constexpr size_t S = KAP + (size_t)kCap * NAMAX * 8;     // int32 [kCap][NAMAX]
+    static constexpr size_t GID = S + (size_t)kCap * NAMAX * 4;     // int32 [kCap]
+    static constexpr size_t LEN = GID + (size_t)kCap * 4;           // int32 [kCap+1] prefix of segment lengths
+    static constexpr size_t KEYS = LEN + (size_t)(kCap + 1) * 4;    // int32 [nkey] bucket starts
+    static constexpr size_t BOOK = KEYS + (size_t)nkey * 4;         // int32 [kBook]
+    static constexpr size_t LUT = BOOK + (size_t)kBook * 4;         // int32 [L][2][64]
+    static constexpr size_t PAR = LUT + (size_t)kMaxL * 2 * kNDelta * 4;   // int16 [kCap]
+    static constexpr size_t CHP = PAR + (size_t)kCap * 2;           // int16 [kCap+2]
+    static constexpr size_t CHL = CHP + (size_t)(kCap + 2) * 2;     // int16 [kCap]
+    static constexpr size_t ORD = CHL + (size_t)kCap * 2;           // int16 [kCap]
+    static constexpr size_t KEY = ORD + (size_t)kCap * 2;           // int16 [kCap] bucket of each node
+    static constexpr size_t BT = KEY + (size_t)kCap * 2;            // uint8 [kCap][NAMAX][2]
+    static constexpr size_t SEL = BT + (size_t)kCap * NAMAX * 2;    // uint8 [kCap][kMaxL]
+    static constexpr size_t ENT = SEL + (size_t)kCap * kMaxL;       // uint8 [kCap] entering layer
+    static constexpr size_t BYTES = ENT + (size_t)kCap;
+};
 
 struct BArgs {
     const int32_t *tier_nets;
@@ -74,73 +81,42 @@ struct BArgs {
 };
 
 template <int NAMAX>
-__device__ __forceinline__ void dp_level_items(const DPArgs &a, const LayerTab &tb, const LdsState<NAMAX> &st, const int16_t *order, const int16_t *par,
-                               const int32_t *gid, int32_t lbeg, int32_t lcnt)
-{
-    const int32_t items = lcnt * NAMAX;
-    for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
-        const int32_t u = order[lbeg + it / NAMAX];
-        const int j = it % NAMAX;
-        const int32_t n = gid[u];
-        const bool root = par[u] < 0;
-        int l;
-        if (root) {
-            if (j != 0) continue;
-            l = 0;
-        } else {
-            const int d = a.T.dir[n];
-            if (j >= tb.nA[d]) continue;
-            l = tb.lay[d][j];
-        }
-        dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, n, l, j, root);
-    }
-}
-
-template <int NAMAX>
 __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
 {
+    using TL = Tile<NAMAX>;
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ LayerTab tb;
     load_tab(a.tab, tb);
-    uint8_t *p = smem;
-    int64_t *F = (int64_t *)p;
-    p += kCap * NAMAX * 8;
-    int64_t *KA = (int64_t *)p;
-    p += kCap * NAMAX * 8;
-    int32_t *S = (int32_t *)p;
-    p += kCap * NAMAX * 4;
-    int32_t *gid = (int32_t *)p;
-    p += kCap * 4;
-    int32_t *lstart = (int32_t *)p;          // [kCap+2] level starts into order
-    p += (kCap + 2) * 4;
-    int32_t *book = (int32_t *)p;            // claim bookkeeping
-    p += 64 * 4 * 8;
-    int16_t *par = (int16_t *)p;
-    p += kCap * 2;
-    int16_t *chp = (int16_t *)p;
-    p += (kCap + 2) * 2;
-    int16_t *chl = (int16_t *)p;
-    p += kCap * 2;
-    int16_t *order = (int16_t *)p;
-    p += kCap * 2;
-    int16_t *lvl = (int16_t *)p;
-    p += kCap * 2;
-    uint8_t *bt = p;
-    p += kCap * NAMAX * 2;
-    uint8_t *sel = p;
-    p += kCap * kMaxL;
-    uint8_t *ent = p;
+    int64_t *F = (int64_t *)(smem + TL::F);
+    int64_t *kap = (int64_t *)(smem + TL::KAP);
+    int32_t *S = (int32_t *)(smem + TL::S);
+    int32_t *gid = (int32_t *)(smem + TL::GID);
+    int32_t *lenp = (int32_t *)(smem + TL::LEN);
+    int32_t *kst = (int32_t *)(smem + TL::KEYS);
+    int32_t *book = (int32_t *)(smem + TL::BOOK);
+    int32_t *lut = (int32_t *)(smem + TL::LUT);
+    int16_t *par = (int16_t *)(smem + TL::PAR);
+    int16_t *chp = (int16_t *)(smem + TL::CHP);
+    int16_t *chl = (int16_t *)(smem + TL::CHL);
+    int16_t *order = (int16_t *)(smem + TL::ORD);
+    int16_t *key = (int16_t *)(smem + TL::KEY);
+    uint8_t *bt = smem + TL::BT;
+    uint8_t *sel = smem + TL::SEL;
+    uint8_t *ent = smem + TL::ENT;
 
-    // bookkeeping layout: [0] claim base, [1] #subs, [2] max level of tile,
-    // [8..8+kClaim] sub start, [48..] sub end (claim-relative),
-    // [128..] per-net local node base, [168..] per-net local child base (tile-relative)
+    // bookkeeping: [0] claim base, [1] #tiles, [2] max height, [8..] tile start, [48..] tile
+    // end (claim-relative), [128..] per-net local node base, [168..] per-net local child base
     int32_t *s_base = book, *s_nsub = book + 1, *s_maxlev = book + 2;
     int32_t *s_sub0 = book + 8, *s_sub1 = book + 48;
     int32_t *s_lbase = book + 128, *s_cbase = book + 168;
 
-    LdsState<NAMAX> st{F, KA, S, bt, sel, chp, chl, gid};
+    const int L = tb.L;
+    for (int i = threadIdx.x; i < L * 2 * kNDelta; i += blockDim.x) lut[i] = a.w.lut[i];
+
+    LdsState<NAMAX> st{F, S, bt, sel, chp, chl, gid};
     // the batch's small nets (its big nets run in k_batched_big)
     const int32_t off0 = ba.tier_off[2 * ba.tier + 1], cnt = ba.tier_off[2 * ba.tier + 2] - off0;
+    const int32_t Xl = tb.X * L;
 
     for (;;) {
         if (threadIdx.x == 0) *s_base = atomicAdd(ba.ctr, kClaim);
@@ -172,7 +148,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
         const int32_t nsub = *s_nsub;
         for (int32_t sb = 0; sb < nsub; ++sb) {
             const int32_t i0 = s_sub0[sb], i1 = s_sub1[sb];
-            // ---- small nets: stage the tile in LDS --------------------------------------
+            // ---- stage the tile ------------------------------------------------------------
             if (threadIdx.x == 0) {
                 int32_t nb = 0, cb = 0;
                 for (int32_t i = i0; i < i1; ++i) {
@@ -185,8 +161,9 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                 }
                 s_lbase[i1 - i0] = nb;
                 s_cbase[i1 - i0] = cb;
+                *s_maxlev = 0;
             }
-            for (int32_t i = threadIdx.x; i < kCap + 2; i += blockDim.x) lstart[i] = 0;
+            for (int32_t i = threadIdx.x; i < TL::nkey; i += blockDim.x) kst[i] = 0;
             __syncthreads();
             const int32_t nn = s_lbase[i1 - i0];
             const int32_t nnets = i1 - i0;
@@ -200,40 +177,92 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                 const int32_t pg = a.T.parent[g];
                 par[u] = (int16_t)(pg < 0 ? -1 : pg - g0 + s_lbase[k]);
                 const int32_t c0 = a.T.ch_ptr[g0];
-                const int32_t cb = s_cbase[k] + (a.T.ch_ptr[g] - c0);
-                chp[u] = (int16_t)cb;
-                for (int32_t e = a.T.ch_ptr[g]; e < a.T.ch_ptr[g + 1]; ++e)
+                const int32_t e0 = a.T.ch_ptr[g], e1 = a.T.ch_ptr[g + 1];
+                chp[u] = (int16_t)(s_cbase[k] + (e0 - c0));
+                for (int32_t e = e0; e < e1; ++e)
                     chl[s_cbase[k] + (e - c0)] = (int16_t)(a.T.ch[e] - g0 + s_lbase[k]);
                 const int32_t h = ba.height[g];
-                lvl[u] = (int16_t)h;
-                atomicAdd(&lstart[h + 1], 1);
+                const int32_t kk = e1 - e0;
+                const int32_t bk = 4 * h + (kk < 3 ? kk : 3);
+                key[u] = (int16_t)bk;
+                atomicAdd(&kst[bk + 1], 1);
+                atomicMax(s_maxlev, h);
+                lenp[u] = a.T.len[g];
+#pragma unroll
+                for (int jj = 0; jj < NAMAX; ++jj) kap[u * NAMAX + jj] = 0;
             }
             if (threadIdx.x == 0) chp[nn] = (int16_t)s_cbase[i1 - i0];
             __syncthreads();
-            if (threadIdx.x == 0) {
-                int32_t m = 0;
-                for (int32_t h = 0; h < kCap; ++h) {
-                    if (lstart[h + 1]) m = h;
-                    lstart[h + 1] += lstart[h];
-                }
-                *s_maxlev = m;
-            }
-            __syncthreads();
-            // height order: lstart[h] counts down as slots fill, restored below
-            for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
-                const int32_t pos = atomicAdd(&lstart[lvl[u]], 1);
-                order[pos] = (int16_t)u;
-            }
-            __syncthreads();
             const int32_t maxlev = *s_maxlev;
-            // after the scatter lstart[h] holds the end of level h = start of level h+1
+            const int32_t nk = 4 * maxlev + 4;
+            if (threadIdx.x == 0) {
+                for (int32_t q = 0; q < nk; ++q) kst[q + 1] += kst[q];
+                // exclusive prefix of the segment lengths
+                int32_t acc = 0;
+                for (int32_t u = 0; u < nn; ++u) {
+                    const int32_t l_ = lenp[u];
+                    lenp[u] = acc;
+                    acc += l_;
+                }
+                lenp[nn] = acc;
+            }
+            __syncthreads();
+            // (height, class) order; kst[q] ends as the end of bucket q = start of q+1
+            for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) order[atomicAdd(&kst[key[u]], 1)] = (int16_t)u;
+            // congestion costs: one thread per GCell edge of the tile's segments, every
+            // routable layer of the segment's direction at once
+            const int32_t steps = lenp[nn];
+            for (int32_t pidx = threadIdx.x; pidx < steps; pidx += blockDim.x) {
+                int32_t lo_ = 0, hi_ = nn;      // last u with lenp[u] <= pidx
+                while (hi_ - lo_ > 1) {
+                    const int32_t mid = (lo_ + hi_) >> 1;
+                    if (lenp[mid] <= pidx) lo_ = mid;
+                    else hi_ = mid;
+                }
+                const int32_t u = lo_, n = gid[u];
+                const int d = a.T.dir[n];
+                const int32_t g = a.T.g0[n] + (pidx - lenp[u]) * (d == 0 ? L : Xl);
+                const int self = a.w.self_excl ? (int)a.prev[n] : -1;
+                const int na = tb.nA[d];
+#pragma unroll
+                for (int jj = 0; jj < NAMAX; ++jj) {
+                    if (jj < na) {
+                        const int l = tb.lay[d][jj];
+                        const int32_t cap = a.caps[g + l];
+                        int32_t dd = a.D[g + l] - (self == l ? 1 : 0) - cap;
+                        dd = dd < kDeltaMin ? kDeltaMin : (dd > kDeltaMin + kNDelta - 1 ? kDeltaMin + kNDelta - 1 : dd);
+                        const int64_t v = (int64_t)lut[(l * 2 + (cap > 0 ? 0 : 1)) * kNDelta + dd - kDeltaMin] +
+                                          (int64_t)a.H[g + l];
+                        atomicAdd((unsigned long long *)&kap[u * NAMAX + jj], (unsigned long long)v);
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- DP bottom-up, one height level at a time ----------------------------------
             for (int32_t h = 0; h <= maxlev; ++h) {
-                const int32_t lb = h == 0 ? 0 : lstart[h - 1], le = lstart[h];
-                dp_level_items<NAMAX>(a, tb, st, order, par, gid, lb, le - lb);
+                const int32_t lb = h == 0 ? 0 : kst[4 * h - 1], le = kst[4 * h + 3];
+                const int32_t items = (le - lb) * NAMAX;
+                for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
+                    const int32_t u = order[lb + it / NAMAX];
+                    const int j = it % NAMAX;
+                    const int32_t n = gid[u];
+                    const bool root = par[u] < 0;
+                    int l;
+                    if (root) {
+                        if (j != 0) continue;
+                        l = 0;
+                    } else {
+                        const int d = a.T.dir[n];
+                        if (j >= tb.nA[d]) continue;
+                        l = tb.lay[d][j];
+                    }
+                    dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, n, l, j, root, root ? 0 : kap[u * NAMAX + j]);
+                }
                 __syncthreads();
             }
+            // ---- trace-back top-down -------------------------------------------------------
             for (int32_t h = maxlev; h >= 0; --h) {
-                const int32_t lb = h == 0 ? 0 : lstart[h - 1], le = lstart[h];
+                const int32_t lb = h == 0 ? 0 : kst[4 * h - 1], le = kst[4 * h + 3];
                 for (int32_t it0 = lb; it0 < le; it0 += blockDim.x) {
                     const int32_t it = it0 + threadIdx.x;
                     bool changed = false;
@@ -245,7 +274,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                         n = gid[u];
                         const int32_t pu = par[u];
                         const int lp = (pu < 0 || par[pu] < 0) ? 0 : ent[pu];
-                        ln = trace_node(a, tb, st, u, n, lp, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev,
+                        ln = trace_node(tb, st, u, n, lp, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev,
                                         &changed, &old_l);
                         ent[u] = (uint8_t)ln;
                     }
@@ -286,7 +315,7 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
                     if (j >= tb.nA[d]) continue;
                     l = tb.lay[d][j];
                 }
-                dp_node<GlobalState, NAMAX>(a, tb, gst, n, n, l, j, root);
+                dp_node<GlobalState, NAMAX>(a, tb, gst, n, n, l, j, root, root ? 0 : kappa_seg(a, tb, n, l));
             }
             __syncthreads();
         }
@@ -302,7 +331,7 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
                     n = ba.bn_order[b0 + it];
                     const int32_t pp = a.T.parent[n];
                     const int lp = (pp < 0 || a.T.parent[pp] < 0) ? 0 : ba.cur[pp];
-                    ln = trace_node(a, tb, gst, n, n, lp, pp < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev,
+                    ln = trace_node(tb, gst, n, n, lp, pp < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev,
                                     &changed, &old_l);
                 }
                 append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
@@ -391,7 +420,7 @@ la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t 
     if (nbig > 0)
         hipLaunchKernelGGL(k_batched_big<NAMAX>, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, s, a, ba);
     if (nsmall > 0)
-        hipLaunchKernelGGL(k_batched_dp<NAMAX>, dim3(b->grid_batched), dim3(kThreads), tile_bytes<NAMAX>(), s, a,
+        hipLaunchKernelGGL(k_batched_dp<NAMAX>, dim3(b->grid_batched), dim3(kThreads), Tile<NAMAX>::BYTES, s, a,
                            ba);
     LA_HIP(hipGetLastError());
     return LA_OK;
@@ -403,7 +432,7 @@ int occupancy_grid()
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_dp<NAMAX>, kThreads, tile_bytes<NAMAX>());
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_dp<NAMAX>, kThreads, Tile<NAMAX>::BYTES);
     return std::max(1, cus) * std::max(1, per);
 }
 

@@ -423,7 +423,6 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(alloc(&b->vlo, M));
     chk(alloc(&b->vhi, M));
     chk(alloc(&b->F, M * b->NAmax));
-    chk(alloc(&b->KA, M * b->NAmax));
     chk(alloc(&b->S, M * b->NAmax));
     chk(alloc(&b->bt, M * b->NAmax * 2));
     chk(alloc(&b->sel, M * kMaxL));
@@ -455,7 +454,6 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     la_default_cong_lut(L, nullptr, lut.data());
     LA_HIP(hipMemcpy(b->lut, lut.data(), lut.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     LA_HIP(hipMemsetAsync(b->F, 0, M * b->NAmax * sizeof(int64_t), b->stream));
-    LA_HIP(hipMemsetAsync(b->KA, 0, M * b->NAmax * sizeof(int64_t), b->stream));
     LA_HIP(hipMemsetAsync(b->S, 0, M * b->NAmax * sizeof(int32_t), b->stream));
     LA_HIP(hipMemsetAsync(b->bt, 0, M * b->NAmax * 2, b->stream));
     LA_HIP(hipMemsetAsync(b->sel, 0, M * kMaxL, b->stream));

@@ -13,9 +13,13 @@
 //    the hull of l, the pin layer and the chosen child layers costs more than
 //    that hull with the same choices, so only hulls can win.  Each tuple of
 //    child layers names one hull; it is a candidate when every child's choice is
-//    its own key minimum (lowest layer on ties) inside that hull.
-//  - the full enumeration otherwise: b ascending, t ascending, each child's
-//    running minimum extended one layer as t grows.
+//    its own key minimum (lowest layer on ties) inside that hull.  Valid tuples
+//    are collected in a bit mask first and only those are costed.
+//  - the full enumeration otherwise: every stack, each child's minimum rescanned.
+//
+// Integer widths: la_build_batch bounds every net so that R < 2^31, C, S < 2^30 and
+// via sums < 2^24, hence R*X fits a 32x32-bit product; weights are Q10 (<= 1024);
+// la_assign bounds w_d < 2^20 and the whole cost of a net below 2^62.
 #pragma once
 
 #include "la_internal.h"
@@ -30,8 +34,8 @@ struct DPArgs {
     const uint8_t *caps;
     const int32_t *H;
     const uint8_t *prev;
-    int64_t *F, *KA;   // [node][NA] subtree cost f and f + look-ahead of the node's own segment
-    int32_t *S;        // [node][NA] downstream capacitance of the chosen candidate (aF)
+    int64_t *F;        // [node][NA] subtree cost f of the chosen candidate
+    int32_t *S;        // [node][NA] its downstream capacitance (aF)
     uint8_t *bt;       // [node][NA][2] chosen via stack
     uint8_t *sel;      // [node][kMaxL] node's layer for each entering layer of its parent
     int32_t NA;
@@ -55,19 +59,38 @@ struct GlobalState {
     __device__ int32_t ch_state(int32_t s, int q) const { return a.T.ch[a.T.ch_ptr[s] + q]; }
     __device__ int32_t ch_gid(int32_t s, int q) const { return a.T.ch[a.T.ch_ptr[s] + q]; }
     __device__ int64_t &F(int32_t s, int j) const { return a.F[(int64_t)s * a.NA + j]; }
-    __device__ int64_t &KA(int32_t s, int j) const { return a.KA[(int64_t)s * a.NA + j]; }
     __device__ int32_t &S(int32_t s, int j) const { return a.S[(int64_t)s * a.NA + j]; }
     __device__ uint8_t *bt(int32_t s, int j) const { return a.bt + 2 * ((int64_t)s * a.NA + j); }
     __device__ uint8_t &sel(int32_t s, int l) const { return a.sel[(int64_t)s * kMaxL + l]; }
 };
 
-// T(w, R, X) = (w * ((R * X) >> 11)) >> 10, operands non-negative
-__device__ __forceinline__ int64_t Tq(int64_t w, int64_t R, int64_t X) { return (w * ((R * X) >> 11)) >> 10; }
+// exact products of operands of known width
+__device__ __forceinline__ uint64_t mul_u32(uint32_t a, uint32_t b) { return (uint64_t)a * (uint64_t)b; }
+// a * b for a result below 2^64
+__device__ __forceinline__ uint64_t mul_u64_u32(uint64_t a, uint32_t b)
+{
+    return (uint64_t)(uint32_t)a * b + (((uint64_t)(uint32_t)(a >> 32) * b) << 32);
+}
 
-__device__ __forceinline__ int64_t rvia_d(const LayerTab &t, int a, int b)
+// T(w, R, X) = (w * ((R * X) >> 11)) >> 10 for R, X < 2^32 and w <= 1024
+__device__ __forceinline__ int64_t Tq(uint32_t w, uint32_t R, uint32_t X)
+{
+    return (int64_t)(mul_u64_u32(mul_u32(R, X) >> 11, w) >> 10);
+}
+
+// multiplication by the delay weight w_d (uniform; 1 by default)
+struct Wd {
+    uint32_t v;
+    __device__ __forceinline__ int64_t operator()(int64_t x) const
+    {
+        return v == 1 ? x : (int64_t)mul_u64_u32((uint64_t)x, v);
+    }
+};
+
+__device__ __forceinline__ uint32_t rvia_d(const LayerTab &t, int a, int b)
 {
     const int32_t d = t.pv[a] - t.pv[b];
-    return d < 0 ? -d : d;
+    return (uint32_t)(d < 0 ? -d : d);
 }
 
 // congestion cost kappa_n(l): marginal Eq. 3 cost plus history along the GCell edges of segment n
@@ -93,21 +116,43 @@ struct ChildKey {
     int32_t Z;
 };
 
-// key, f-contribution and downstream capacitance of a child (state cs, attributes of node c)
-// on layer t under parent layer l
+// Per-child inputs that do not depend on the parent's layer.
+struct ChildIn {
+    int32_t cs;       // state index
+    int32_t len;
+    uint32_t w;       // Q10 segment weight
+    uint32_t lam;     // look-ahead coefficient
+    int dir;
+};
+
 template <class St>
-__device__ __forceinline__ ChildKey child_key(const DPArgs &a, const LayerTab &tb, const St &st, int32_t cs,
-                                              int32_t clen, int64_t cw, int l, int t)
+__device__ __forceinline__ ChildIn child_in(const DPArgs &a, const St &st, int32_t s, int q)
+{
+    const int32_t cg = st.ch_gid(s, q);
+    ChildIn c;
+    c.cs = st.ch_state(s, q);
+    c.len = a.T.len[cg];
+    c.w = a.w.seg_w[cg];
+    c.lam = (uint32_t)a.w.lam[cg];
+    c.dir = a.T.dir[cg];
+    return c;
+}
+
+// key = f + w_d T(w, Rvia(l, t), X) + look-ahead; V = the part that enters f; Z = C + S
+template <class St>
+__device__ __forceinline__ ChildKey child_key(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
+                                              int t)
 {
     const int jc = tb.jidx[t];
-    const int32_t Cc = tb.c[t] * clen;
-    const int32_t Sc = st.S(cs, jc);
-    const int64_t X = (int64_t)Cc + 2 * (int64_t)Sc;
-    const int64_t tv = a.w.w_d * Tq(cw, rvia_d(tb, l, t), X);
+    const uint32_t Cc = (uint32_t)(tb.c[t] * c.len);
+    const uint32_t Sc = (uint32_t)st.S(c.cs, jc);
+    const uint32_t Z = Cc + Sc;
+    const int64_t tv = wd(Tq(c.w, rvia_d(tb, l, t), Cc + 2 * Sc));
+    const int64_t la = wd((int64_t)(mul_u32(c.lam, 2 * Z) >> 11));
     ChildKey r;
-    r.V = st.F(cs, jc) + tv;
-    r.key = st.KA(cs, jc) + tv;
-    r.Z = Cc + Sc;
+    r.V = st.F(c.cs, jc) + tv;
+    r.key = r.V + la;
+    r.Z = (int32_t)Z;
     return r;
 }
 
@@ -126,40 +171,54 @@ struct Best {
     }
 };
 
+// value of a register array at a run-time index, without indexing registers dynamically
+template <typename T, int N>
+__device__ __forceinline__ T pick(const T (&arr)[N], int i)
+{
+    T v = arr[0];
+#pragma unroll
+    for (int x = 1; x < N; ++x)
+        if (x == i) v = arr[x];
+    return v;
+}
+
 // DP of node n (state index s, global id n) for its entering layer l (index j in its
-// direction list; j = 0 and l = 0 at the root).  NAMAX bounds the routable layers per direction.
+// direction list; j = 0 and l = 0 at the root).  kap is kappa_n(l) (0 at the root).
+// NAMAX bounds the routable layers per direction.
 template <class St, int NAMAX>
 __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int32_t n, int l,
-                                        int j, bool root)
+                                        int j, bool root, int64_t kap)
 {
     const int L = tb.L;
+    const Wd wd{(uint32_t)a.w.w_d};
     const bool pin = a.T.flags[n] & (kSink | kDriver);
     const int lo = pin ? 0 : l;
     const int hi = l;
-    int64_t own_const = 0, Cs = 0, Rw = 0, segw = 0, lam = 0;
+    int64_t own_const = 0;
+    uint32_t Cs = 0, Rw = 0, segw = 0, lam = 0;
     if (!root) {
         const int32_t len = a.T.len[n];
-        Cs = (int64_t)tb.c[l] * len;
-        Rw = (int64_t)tb.r[l] * len;
-        own_const = a.w.w_cong * kappa_seg(a, tb, n, l) + a.w.w_cap * Cs;
+        Cs = (uint32_t)(tb.c[l] * len);
+        Rw = (uint32_t)(tb.r[l] * len);
+        own_const = a.w.w_cong * kap + a.w.w_cap * (int64_t)Cs;
         segw = a.w.seg_w[n];
-        lam = a.w.lam[n];
+        lam = (uint32_t)a.w.lam[n];
     }
     const int32_t cpin = a.T.cpin[n];
     const int32_t sid = a.T.sink_id[n];
-    const int64_t pin_term = sid >= 0 ? a.w.w_d * Tq(a.w.pin_w[sid], rvia_d(tb, l, 0), 2 * (int64_t)cpin) : 0;
+    const int64_t pin_term = sid >= 0 ? wd(Tq(a.w.pin_w[sid], rvia_d(tb, l, 0), 2 * (uint32_t)cpin)) : 0;
     const int k = st.nch(s);
 
     Best best;
     uint8_t best_sel[2] = {0, 0};
     // f and f' of stack [b,t] given the children's summed f-contributions and capacitances
     auto eval = [&](int b, int t, int64_t sumV, int64_t sumZ) -> bool {
-        const int64_t Sn = cpin + sumZ;
+        const uint32_t Sn = (uint32_t)(cpin + sumZ);
         int64_t f = a.w.w_via * (t - b) + sumV + pin_term;
         int64_t fp = f;
         if (!root) {
-            f += own_const + a.w.w_d * Tq(segw, Rw, Cs + 2 * Sn);
-            fp = f + a.w.w_d * ((lam * 2 * (Cs + Sn)) >> 11);
+            f += own_const + wd(Tq(segw, Rw, Cs + 2 * Sn));
+            fp = f + wd((int64_t)(mul_u32(lam, 2 * (Cs + Sn)) >> 11));
         }
         if (best.better(fp, b, t)) {
             best.fp = fp;
@@ -174,29 +233,21 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 
     if (a.w.w_via > 0 && k <= 2) {
         // ---- hull candidates --------------------------------------------------------
-        int64_t kk[2][NAMAX], kv[2][NAMAX];
-        int32_t kz[2][NAMAX];
-        int nc[2] = {0, 0}, cd[2] = {0, 0};
+        // keys of every child layer decide which tuples are candidates; the few valid
+        // tuples then recompute their f-contributions (no run-time register indexing)
+        int64_t kk[2][NAMAX];
+        int ly[2][NAMAX];
+        int nc[2] = {0, 0};
+        ChildIn cin[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             if (q < k) {
-                const int32_t cs = st.ch_state(s, q), cg = st.ch_gid(s, q);
-                cd[q] = a.T.dir[cg];
-                nc[q] = tb.nA[cd[q]];
-                const int32_t clen = a.T.len[cg];
-                const int64_t cw = a.w.seg_w[cg];
+                cin[q] = child_in(a, st, s, q);
+                nc[q] = tb.nA[cin[q].dir];
 #pragma unroll
                 for (int jj = 0; jj < NAMAX; ++jj) {
-                    if (jj < nc[q]) {
-                        const ChildKey ck = child_key(a, tb, st, cs, clen, cw, l, tb.lay[cd[q]][jj]);
-                        kk[q][jj] = ck.key;
-                        kv[q][jj] = ck.V;
-                        kz[q][jj] = ck.Z;
-                    } else {
-                        kk[q][jj] = 0;
-                        kv[q][jj] = 0;
-                        kz[q][jj] = 0;
-                    }
+                    ly[q][jj] = tb.lay[cin[q].dir][jj < nc[q] ? jj : 0];
+                    kk[q][jj] = jj < nc[q] ? child_key(tb, st, wd, cin[q], l, ly[q][jj]).key : 0;
                 }
             }
         }
@@ -206,42 +257,47 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
             bool ok = true;
             const int64_t mine = kk[q][jq];
 #pragma unroll
-            for (int jj = 0; jj < NAMAX; ++jj) {
-                if (jj < nc[q] && jj != jq) {
-                    const int ly = tb.lay[cd[q]][jj];
-                    if (ly >= b && ly <= t && (kk[q][jj] < mine || (kk[q][jj] == mine && jj < jq))) ok = false;
-                }
-            }
+            for (int jj = 0; jj < NAMAX; ++jj)
+                if (jj < nc[q] && jj != jq && ly[q][jj] >= b && ly[q][jj] <= t &&
+                    (kk[q][jj] < mine || (kk[q][jj] == mine && jj < jq)))
+                    ok = false;
             return ok;
         };
         if (k == 0) {
             eval(lo, hi, 0, 0);
         } else if (k == 1) {
+            uint32_t mask = 0;
 #pragma unroll
-            for (int j1 = 0; j1 < NAMAX; ++j1) {
-                if (j1 < nc[0]) {
-                    const int L1 = tb.lay[cd[0]][j1];
-                    const int b = min(lo, L1), t = max(hi, L1);
-                    if (is_min(0, j1, b, t) && eval(b, t, kv[0][j1], kz[0][j1])) best_sel[0] = (uint8_t)L1;
-                }
+            for (int j1 = 0; j1 < NAMAX; ++j1)
+                if (j1 < nc[0] && is_min(0, j1, min(lo, ly[0][j1]), max(hi, ly[0][j1]))) mask |= 1u << j1;
+            while (mask) {
+                const int j1 = __ffs(mask) - 1;
+                mask &= mask - 1;
+                const int L1 = tb.lay[cin[0].dir][j1];
+                const ChildKey c1 = child_key(tb, st, wd, cin[0], l, L1);
+                if (eval(min(lo, L1), max(hi, L1), c1.V, c1.Z)) best_sel[0] = (uint8_t)L1;
             }
         } else {
+            uint64_t mask = 0;
 #pragma unroll
-            for (int j1 = 0; j1 < NAMAX; ++j1) {
-                if (j1 < nc[0]) {
-                    const int L1 = tb.lay[cd[0]][j1];
+            for (int j1 = 0; j1 < NAMAX; ++j1)
 #pragma unroll
-                    for (int j2 = 0; j2 < NAMAX; ++j2) {
-                        if (j2 < nc[1]) {
-                            const int L2 = tb.lay[cd[1]][j2];
-                            const int b = min(lo, min(L1, L2)), t = max(hi, max(L1, L2));
-                            if (is_min(0, j1, b, t) && is_min(1, j2, b, t) &&
-                                eval(b, t, kv[0][j1] + kv[1][j2], (int64_t)kz[0][j1] + kz[1][j2])) {
-                                best_sel[0] = (uint8_t)L1;
-                                best_sel[1] = (uint8_t)L2;
-                            }
-                        }
+                for (int j2 = 0; j2 < NAMAX; ++j2)
+                    if (j1 < nc[0] && j2 < nc[1]) {
+                        const int b = min(lo, min(ly[0][j1], ly[1][j2]));
+                        const int t = max(hi, max(ly[0][j1], ly[1][j2]));
+                        if (is_min(0, j1, b, t) && is_min(1, j2, b, t)) mask |= 1ull << (j1 * NAMAX + j2);
                     }
+            while (mask) {
+                const int p = __ffsll((unsigned long long)mask) - 1;
+                mask &= mask - 1;
+                const int j1 = p / NAMAX, j2 = p - (p / NAMAX) * NAMAX;
+                const int L1 = tb.lay[cin[0].dir][j1], L2 = tb.lay[cin[1].dir][j2];
+                const ChildKey c1 = child_key(tb, st, wd, cin[0], l, L1);
+                const ChildKey c2 = child_key(tb, st, wd, cin[1], l, L2);
+                if (eval(min(lo, min(L1, L2)), max(hi, max(L1, L2)), c1.V + c2.V, (int64_t)c1.Z + c2.Z)) {
+                    best_sel[0] = (uint8_t)L1;
+                    best_sel[1] = (uint8_t)L2;
                 }
             }
         }
@@ -255,15 +311,12 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
                 bool ok = true;
                 int64_t sumV = 0, sumZ = 0;
                 for (int q = 0; q < k && ok; ++q) {
-                    const int32_t cs = st.ch_state(s, q), cg = st.ch_gid(s, q);
-                    const int cdr = a.T.dir[cg];
-                    const int32_t cl = a.T.len[cg];
-                    const int64_t w = a.w.seg_w[cg];
+                    const ChildIn c = child_in(a, st, s, q);
                     bool have = false;
                     ChildKey bestc{0, 0, 0};
                     for (int lc = b; lc <= t; ++lc) {
-                        if (!child_layer_ok(tb, cdr, lc)) continue;
-                        const ChildKey ck = child_key(a, tb, st, cs, cl, w, l, lc);
+                        if (!child_layer_ok(tb, c.dir, lc)) continue;
+                        const ChildKey ck = child_key(tb, st, wd, c, l, lc);
                         if (!have || ck.key < bestc.key) {
                             have = true;
                             bestc = ck;
@@ -277,29 +330,25 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
             }
         // each child's layer at the chosen stack, by the same rule
         for (int q = 0; q < k; ++q) {
-            const int32_t cs = st.ch_state(s, q), cg = st.ch_gid(s, q);
-            const int cdr = a.T.dir[cg];
-            const int32_t cl = a.T.len[cg];
-            const int64_t w = a.w.seg_w[cg];
+            const ChildIn c = child_in(a, st, s, q);
             bool have = false;
             int64_t bk = 0;
             int bl = 0;
             for (int lc = best.b; lc <= best.t; ++lc) {
-                if (!child_layer_ok(tb, cdr, lc)) continue;
-                const ChildKey ck = child_key(a, tb, st, cs, cl, w, l, lc);
+                if (!child_layer_ok(tb, c.dir, lc)) continue;
+                const ChildKey ck = child_key(tb, st, wd, c, l, lc);
                 if (!have || ck.key < bk) {
                     have = true;
                     bk = ck.key;
                     bl = lc;
                 }
             }
-            st.sel(cs, l) = (uint8_t)bl;
+            st.sel(c.cs, l) = (uint8_t)bl;
         }
     }
 
     st.F(s, j) = best.f;
     st.S(s, j) = (int32_t)best.S;
-    if (!root) st.KA(s, j) = best.f + a.w.w_d * ((lam * 2 * (Cs + best.S)) >> 11);
     uint8_t *bt = st.bt(s, j);
     bt[0] = (uint8_t)best.b;
     bt[1] = (uint8_t)best.t;
@@ -338,8 +387,7 @@ __device__ __forceinline__ void append_change(const ChangeList &cl, bool pred, i
 // lp: the parent's entering layer (0 at a root's children).  Returns n's entering layer
 // and sets *changed / *old_l for the commit list.
 template <class St>
-__device__ __forceinline__ int trace_node(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int32_t n,
-                                          int lp, bool root,
+__device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int32_t s, int32_t n, int lp, bool root,
                                           uint8_t *cur, uint8_t *vlo, uint8_t *vhi, uint8_t *out_layers,
                                           int has_prev, bool *changed, uint8_t *old_l)
 {

@@ -12,7 +12,7 @@
 namespace gapla {
 
 constexpr int kMaxL = 16;          // layers supported (4-bit layer ids)
-constexpr int kCap = 256;          // nodes of one batched-form workgroup's LDS tile
+constexpr int kCap = 224;          // nodes of one batched-form workgroup's LDS tile
 constexpr int kClaim = 32;         // nets claimed per work-queue grab
 constexpr int kMaxA = 8;           // routable layers per direction
 constexpr int kNDelta = 64;        // congestion table entries per (layer, zero-capacity flag)
@@ -97,7 +97,7 @@ struct la_batch {
     bool has_prev = false;
 
     // plain-form DP state
-    int64_t *F = nullptr, *KA = nullptr;
+    int64_t *F = nullptr;
     int32_t *S = nullptr;
     uint8_t *bt = nullptr, *sel = nullptr;
     int32_t *bucket_nodes = nullptr, *bucket_cnt = nullptr, *bucket_cur = nullptr;
