@@ -35,7 +35,6 @@ def main():
     ap.add_argument("--nets", type=int, default=None, help="truncate the workload (testing only)")
     ap.add_argument("--forms", default="batched,plain")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile", action="store_true", help="per-kernel event timing (roofline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -101,6 +100,13 @@ def main():
         results[name] = dict(ms=ms, nets_per_s=inst.num_nets * R_ROUNDS * I_ITERS / (ms * 1e-3), tns=tns, wns=wns)
         log("form %s: %.2f ms/step, %.3e nets/s, TNS %.1f ps, WNS %.2f ps" % (name, ms, results[name]["nets_per_s"],
                                                                           tns, wns))
+        # one more step on the same stream with every hot launch bracketed by HIP events
+        # (the batched form then launches its kernels directly instead of replaying its graph)
+        la.la_profile_begin(b)
+        step(form)
+        results[name]["kernels"] = la.la_profile_end(b)
+        for k, (n, t) in sorted(results[name]["kernels"].items(), key=lambda kv: -kv[1][1]):
+            log("  %-16s %6d launches %10.3f ms/step %9.2f us/launch" % (k, n, t, 1e3 * t / n))
 
     cpu = None
     if not args.no_cpu:
@@ -108,6 +114,7 @@ def main():
 
     main_form = "batched" if "batched" in results else "plain"
     r = results[main_form]
+    roof = {k: roofline(b, k, v["kernels"]) for k, v in results.items()}
     out = {
         "metric": "nets layer-assigned/sec (DP+Elmore) at 2M nets; batched vs plain, same GPU",
         "value": r["nets_per_s"],
@@ -126,9 +133,11 @@ def main():
                                   "batched+adjoint" if main_form == "batched" else "plain", R_ROUNDS, I_ITERS),
                    "nets": inst.num_nets, "la_nodes": b.nodes, "rounds": R_ROUNDS, "iterations": I_ITERS,
                    "form": main_form},
-        "forms": {k: {"nets_per_s": v["nets_per_s"], "ms_per_step": v["ms"], "tns_ps": v["tns"], "wns_ps": v["wns"]}
+        "forms": {k: {"nets_per_s": v["nets_per_s"], "ms_per_step": v["ms"], "tns_ps": v["tns"], "wns_ps": v["wns"],
+                      "roofline": roof[k], "elmore": elmore_rate(b, v["kernels"]),
+                      "kernel_ms_per_step": {n: round(t, 4) for n, (c, t) in v["kernels"].items()}}
                   for k, v in results.items()},
-        "roofline": None,
+        "roofline": roof[main_form],
         "cpu_baseline": cpu,
     }
     if "batched" in results and "plain" in results:
@@ -136,30 +145,64 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(inst):
-    """The oracle (as it stands) on a bounded sample: one round, one iteration of the plain
-    pipeline over the first nets of the same workload."""
-    import numpy as np
+# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes, one int32 op per lane per clock at 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
+
+def roofline(b, form, kernels):
+    """The DP enumeration kernel against the vector-ALU peak.  Algorithmic work = stacks x
+    (6 ops per child + 10) over every node and entering layer (la_info.dp_ops_per_round),
+    times the rounds the step runs; divided by that kernel's summed launch time."""
+    name = "k_batched_dp" if form == "batched" else "k_dp_level"
+    if name not in kernels:
+        return None
+    n, ms = kernels[name]
+    ops_round = b.dp_ops_per_round - (b.dp_ops_big_per_round if form == "batched" else 0.0)
+    ops = ops_round * R_ROUNDS * I_ITERS
+    achieved = ops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "launches": n, "avg_launch_us": 1e3 * ms / n,
+            "ops_per_launch": ops / n}
+
+
+def elmore_rate(b, kernels):
+    """Algorithmic HBM rate of the Elmore forward sweeps (28 B per RC edge per sweep)."""
+    up, down = kernels.get("k_elmore_up"), kernels.get("k_elmore_down")
+    if not up or not down:
+        return None
+    sweeps = I_ITERS + 1
+    ms = up[1] + down[1]
+    gbs = b.elmore_fwd_bytes * sweeps / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+            "ms_per_sweep": ms / sweeps}
+
+
+def cpu_baseline(inst, n_max=300000):
+    """The oracle (as it stands) on a bounded sample: the plain form's whole schedule (I
+    iterations of Elmore -> Eq. 4/5 weights -> R rounds, then Elmore) over the first nets of
+    the same workload, timed on the host threads."""
     import gen
     import oracle
 
-    n = min(inst.num_nets, 400000)
-    sub = gen.config(4, num_nets=n) if inst.name == "c4" or inst.name == "c3" else inst
-    t0 = time.time()
+    n = min(inst.num_nets, n_max)
+    sub = gen.config(4, num_nets=n) if inst.name in ("c3", "c4") else inst
     T = oracle.Tree(sub)
+    t0 = time.time()
     P0 = oracle.Params(T)
-    w = oracle.plain_weights(T, P0)
-    P = oracle.Params(T, seg_w=w["seg_w"], pin_w=w["pin_w"], lam=w["lam"])
     st = oracle.State(T)
-    lay, _, _, _ = oracle.assign(T, P, st, w["tier"], rounds=1)
-    R, C = oracle.rc(T, P, lay)
+    lay = None
+    for _ in range(I_ITERS):
+        w = oracle.plain_weights(T, P0, lay)
+        P = oracle.Params(T, seg_w=w["seg_w"], pin_w=w["pin_w"], lam=w["lam"])
+        lay, _, _, _ = oracle.assign(T, P, st, w["tier"], rounds=R_ROUNDS)
+    R, C = oracle.rc(T, P0, lay)
     oracle.elmore(T, R, C)
     dt = time.time() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count()
-    log("cpu oracle: %d nets, 1 round x 1 iteration in %.1fs on %d threads" % (n, dt, cores))
-    return {"value": n / dt, "unit": "nets/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d nets of the workload, plain weights, 1 round x 1 iteration, then Elmore" % n}
+    cores = oracle.num_threads()
+    log("cpu oracle: %d nets, %d rounds x %d iterations in %.1fs on %d threads" % (n, R_ROUNDS, I_ITERS, dt, cores))
+    return {"value": n * R_ROUNDS * I_ITERS / dt, "unit": "nets/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d nets of the workload, plain form schedule (%d iterations x %d rounds, then Elmore)"
+                      % (n, I_ITERS, R_ROUNDS)}
 
 
 if __name__ == "__main__":

@@ -108,6 +108,14 @@ typedef struct {
     const int32_t *node_parent;   /* device [nodes] global parent index, -1 at roots (batch-owned) */
     const int32_t *node_net;      /* device [nodes] */
     const int32_t *sink_node;     /* device [sinks] */
+    /* Algorithmic work of one DP round over every net (Alg. 3 as written): integer lane-ops of
+     * the stack enumeration, sum over nodes n and entering layers l of (lo+1)(L-hi) stacks x
+     * (6 per child + 10), and the compulsory bytes (node inputs, congestion gathers of 9 B per
+     * GCell edge and routable layer, outputs).  Elmore: compulsory bytes of one forward and one
+     * reverse sweep.  dp_ops_big_per_round: the part of dp_ops_per_round from nets of more than
+     * 224 nodes, which the batched form runs in its own kernel with the DP state in HBM. */
+    double dp_ops_per_round, dp_bytes_per_round, elmore_fwd_bytes, elmore_bwd_bytes;
+    double dp_ops_big_per_round;
 } la_info;
 la_status la_batch_info(const la_batch *b, la_info *out);
 
@@ -228,6 +236,19 @@ la_status la_load_state(la_batch *b, const void *host_buf, size_t bytes);
 
 /* Wait for all work the batch enqueued. */
 la_status la_sync(la_batch *b);
+
+/* Kernel timing for roofline reports.  Between la_profile_begin and la_profile_end every
+ * launch of the library's hot kernels is bracketed by hipEvents on the batch's stream, and
+ * the batched form launches its kernels directly instead of replaying its hipGraph.
+ * la_profile_end synchronises and writes, for up to `cap` kernels, the kernel name, the
+ * number of launches and the summed launch durations (ms) into `out`, and the count to *n. */
+typedef struct {
+    char name[32];
+    int32_t launches;
+    double total_ms;
+} la_kernel_stat;
+la_status la_profile_begin(la_batch *b);
+la_status la_profile_end(la_batch *b, la_kernel_stat *out, int32_t cap, int32_t *n);
 
 void la_free_batch(la_batch *b);
 const char *la_status_str(la_status s);

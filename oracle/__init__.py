@@ -237,6 +237,11 @@ def kappa(tree: Tree, P: Params, node: int, layer: int, D, H=None, self_layer: i
                             _p(caps), _p(np.ascontiguousarray(H, np.int32)), self_layer)
 
 
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops run on."""
+    return int(_load().oracle_num_threads())
+
+
 def rc(tree: Tree, P: Params, layers=None):
     """R (kOhm) and C (fF) of every RC edge [nodes + sinks]; layers=None gives the pre-assignment RC."""
     lib = _load()

@@ -36,6 +36,7 @@
 #include <string.h>
 #include <math.h>
 #include <limits.h>
+#include <omp.h>
 
 #define O_OK 0
 #define O_ERR_INVALID_ARG -1
@@ -851,3 +852,6 @@ void oracle_adjoint_weights(const otree *T, const double *G, const double *Sig, 
         pin_w[k] = (uint16_t)(q < 0 ? 0 : (q > 1024 ? 1024 : q));
     }
 }
+
+/* Threads the OpenMP loops above use (for reporting timings). */
+int oracle_num_threads(void) { return omp_get_max_threads(); }

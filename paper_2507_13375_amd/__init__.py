@@ -24,8 +24,8 @@ W_CONG, W_CAP, W_D, W_VIA, HIST_INC = 1000, 100, 1, 100000, 64
 
 EXPORTS = ["la_build_batch", "la_batch_info", "la_assign", "la_vias", "la_demand", "la_reset", "la_batch_rc",
            "la_elmore", "la_elmore_rc", "la_elmore_backward", "la_timing_summary", "la_timing_weights",
-           "la_default_cong_lut", "la_save_state", "la_load_state", "la_sync", "la_free_batch", "la_status_str",
-           "la_last_error"]
+           "la_default_cong_lut", "la_save_state", "la_load_state", "la_sync", "la_profile_begin", "la_profile_end",
+           "la_free_batch", "la_status_str", "la_last_error"]
 
 V, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 
@@ -47,7 +47,13 @@ class la_layer_rc(ctypes.Structure):
 class la_info(ctypes.Structure):
     _fields_ = [("nets", I64), ("nodes", I64), ("sinks", I64), ("rc_edges", I64), ("grid_edges", I64),
                 ("levels", I32), ("max_net_nodes", I32), ("gcell_edges", I64), ("node_parent", V),
-                ("node_net", V), ("sink_node", V)]
+                ("node_net", V), ("sink_node", V), ("dp_ops_per_round", ctypes.c_double),
+                ("dp_bytes_per_round", ctypes.c_double), ("elmore_fwd_bytes", ctypes.c_double),
+                ("elmore_bwd_bytes", ctypes.c_double), ("dp_ops_big_per_round", ctypes.c_double)]
+
+
+class la_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", I32), ("total_ms", ctypes.c_double)]
 
 
 class la_weights(ctypes.Structure):
@@ -95,6 +101,8 @@ def _load():
         lib.la_save_state.argtypes = [V, V, ctypes.POINTER(ctypes.c_size_t)]
         lib.la_load_state.argtypes = [V, V, ctypes.c_size_t]
         lib.la_sync.argtypes = [V]
+        lib.la_profile_begin.argtypes = [V]
+        lib.la_profile_end.argtypes = [V, ctypes.POINTER(la_kernel_stat), I32, ctypes.POINTER(I32)]
         lib.la_free_batch.argtypes = [V]
         lib.la_free_batch.restype = None
         for name in EXPORTS:
@@ -137,6 +145,9 @@ class Batch:
         self.nets, self.nodes, self.sinks = info.nets, info.nodes, info.sinks
         self.rc_edges, self.grid_edges, self.levels = info.rc_edges, info.grid_edges, info.levels
         self.max_net_nodes, self.gcell_edges = info.max_net_nodes, info.gcell_edges
+        self.dp_ops_per_round, self.dp_bytes_per_round = info.dp_ops_per_round, info.dp_bytes_per_round
+        self.elmore_fwd_bytes, self.elmore_bwd_bytes = info.elmore_fwd_bytes, info.elmore_bwd_bytes
+        self.dp_ops_big_per_round = info.dp_ops_big_per_round
         self.X, self.Y, self.L = inst.X, inst.Y, inst.L
         self._info = info
 
@@ -257,6 +268,19 @@ def la_load_state(b: Batch, state: bytes):
 
 def la_sync(b: Batch):
     _chk(_load().la_sync(b.h), "la_sync")
+
+
+def la_profile_begin(b: Batch):
+    _chk(_load().la_profile_begin(b.h), "la_profile_begin")
+
+
+def la_profile_end(b: Batch) -> dict:
+    """{kernel name: (launches, summed launch time in ms)} of the launches since la_profile_begin."""
+    cap = 64
+    out = (la_kernel_stat * cap)()
+    n = I32(0)
+    _chk(_load().la_profile_end(b.h, out, cap, ctypes.byref(n)), "la_profile_end")
+    return {out[i].name.decode(): (out[i].launches, out[i].total_ms) for i in range(min(n.value, cap))}
 
 
 def la_status_str(code: int) -> str:

@@ -31,6 +31,31 @@ la_status timing_summary(la_batch *b, const float *delay, double *tns, double *w
 la_status zero_i32(la_batch *b, int32_t *p, int64_t n);
 la_status interleave_vias(la_batch *b, uint8_t *out);
 
+KernelTimer::KernelTimer(la_batch *b, const char *name, hipStream_t s) : b_(b), s_(s)
+{
+    if (!b->prof_on) return;
+    const size_t need = 2 * (b->prof_used + 1);
+    while (b->prof_ev.size() < need) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return;   // the launch then goes untimed
+        b->prof_ev.push_back(e);
+    }
+    rec_ = b->prof_used;
+    if (hipEventRecord(b->prof_ev[2 * rec_], s) != hipSuccess) {
+        rec_ = SIZE_MAX;
+        return;
+    }
+    if (b->prof_name.size() <= rec_) b->prof_name.resize(rec_ + 1);
+    b->prof_name[rec_] = name;
+    b->prof_used = rec_ + 1;
+}
+
+KernelTimer::~KernelTimer()
+{
+    if (rec_ == SIZE_MAX) return;
+    (void)hipEventRecord(b_->prof_ev[2 * rec_ + 1], s_);
+}
+
 static la_status set_device(const la_batch *b)
 {
     int cur = -1;
@@ -98,6 +123,11 @@ la_status la_batch_info(const la_batch *b, la_info *o)
     o->node_parent = b->parent;
     o->node_net = b->net;
     o->sink_node = b->sink_node;
+    o->dp_ops_per_round = b->dp_ops;
+    o->dp_bytes_per_round = b->dp_bytes;
+    o->elmore_fwd_bytes = b->el_fwd_bytes;
+    o->elmore_bwd_bytes = b->el_bwd_bytes;
+    o->dp_ops_big_per_round = b->dp_ops_big;
     return LA_OK;
 }
 
@@ -237,10 +267,48 @@ la_status la_sync(la_batch *b)
     return LA_OK;
 }
 
+la_status la_profile_begin(la_batch *b)
+{
+    if (!b) return set_error(LA_ERR_INVALID_ARG, "la_profile_begin: NULL batch");
+    if (b->prof_on) return set_error(LA_ERR_STATE, "la_profile_begin: profiling already on");
+    b->prof_used = 0;
+    b->prof_on = true;
+    return LA_OK;
+}
+
+la_status la_profile_end(la_batch *b, la_kernel_stat *out, int32_t cap, int32_t *n)
+{
+    if (!b || !n || cap < 0 || (cap > 0 && !out)) return set_error(LA_ERR_INVALID_ARG, "la_profile_end: bad argument");
+    if (!b->prof_on) return set_error(LA_ERR_STATE, "la_profile_end: profiling is not on");
+    b->prof_on = false;
+    const la_status sd = set_device(b);
+    if (sd != LA_OK) return sd;
+    LA_HIP(hipStreamSynchronize(b->stream));
+    std::vector<la_kernel_stat> acc;
+    for (size_t i = 0; i < b->prof_used; ++i) {
+        float ms = 0.f;
+        LA_HIP(hipEventElapsedTime(&ms, b->prof_ev[2 * i], b->prof_ev[2 * i + 1]));
+        size_t k = 0;
+        while (k < acc.size() && std::strncmp(acc[k].name, b->prof_name[i], sizeof(acc[k].name)) != 0) ++k;
+        if (k == acc.size()) {
+            la_kernel_stat z{};
+            std::strncpy(z.name, b->prof_name[i], sizeof(z.name) - 1);
+            acc.push_back(z);
+        }
+        acc[k].launches += 1;
+        acc[k].total_ms += ms;
+    }
+    b->prof_used = 0;
+    *n = (int32_t)acc.size();
+    for (size_t k = 0; k < acc.size() && (int32_t)k < cap; ++k) out[k] = acc[k];
+    return LA_OK;
+}
+
 void la_free_batch(la_batch *b)
 {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
+    for (hipEvent_t e : b->prof_ev) (void)hipEventDestroy(e);
     void *ptrs[] = {b->parent, b->ch_ptr, b->ch, b->net, b->net_ptr, b->len, b->g0, b->cpin, b->sink_id,
                     b->sink_node, b->net_sink_ptr, b->rest, b->budget_fs, b->rdrv, b->dir, b->flags,
                     b->level_nodes, b->level_ptr, b->height, b->caps, b->D, b->cur_layer, b->vlo, b->vhi,

@@ -192,8 +192,9 @@ __global__ void k_interleave(const uint8_t *lo, const uint8_t *hi, uint8_t *out,
 
 la_status interleave_vias(la_batch *b, uint8_t *out)
 {
-    hipLaunchKernelGGL(k_interleave, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, b->vlo, b->vhi, out,
-                       b->nodes);
+    LA_TIMED(b, "k_interleave", b->stream,
+             hipLaunchKernelGGL(k_interleave, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, b->vlo, b->vhi,
+                                out, b->nodes));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }
@@ -226,8 +227,9 @@ DPArgs make_dp_args(la_batch *b, const la_weights *w, const int32_t *H, const in
 
 la_status commit_changed(la_batch *b)
 {
-    hipLaunchKernelGGL(k_commit, dim3(1024), dim3(kBlock), 0, b->stream, tree_view(b), b->tab, b->chg_node,
-                       b->chg_old, b->chg_new, b->chg_count, b->D);
+    LA_TIMED(b, "k_commit", b->stream,
+             hipLaunchKernelGGL(k_commit, dim3(1024), dim3(kBlock), 0, b->stream, tree_view(b), b->tab, b->chg_node,
+                                b->chg_old, b->chg_new, b->chg_count, b->D));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }
@@ -241,7 +243,9 @@ la_status zero_i32(la_batch *b, int32_t *p, int64_t n)
 
 la_status history_update(la_batch *b, int32_t *H, int32_t inc)
 {
-    hipLaunchKernelGGL(k_history, dim3(grid_for(b->E)), dim3(kBlock), 0, b->stream, b->D, b->caps, H, b->E, inc);
+    LA_TIMED(b, "k_history", b->stream,
+             hipLaunchKernelGGL(k_history, dim3(grid_for(b->E)), dim3(kBlock), 0, b->stream, b->D, b->caps, H, b->E,
+                                inc));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }
@@ -263,8 +267,9 @@ la_status bucket_nodes(la_batch *b, const uint8_t *tier, int32_t ntier, std::vec
     la_status s = zero_i32(b, b->bucket_cnt, (int64_t)need + 1);
     if (s != LA_OK) return s;
     const TreeDev T = tree_view(b);
-    hipLaunchKernelGGL(k_bucket_count, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->height, tier,
-                       ntier, Hh, b->bucket_cnt, b->bucket_cnt + need);
+    LA_TIMED(b, "k_bucket_count", b->stream,
+             hipLaunchKernelGGL(k_bucket_count, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->height,
+                                tier, ntier, Hh, b->bucket_cnt, b->bucket_cnt + need));
     LA_HIP(hipGetLastError());
     counts.assign(need + 1, 0);
     LA_HIP(hipMemcpyAsync(counts.data(), b->bucket_cnt, (need + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -280,8 +285,9 @@ la_status bucket_nodes(la_batch *b, const uint8_t *tier, int32_t ntier, std::vec
         acc += counts[i];
     }
     LA_HIP(hipMemcpyAsync(b->bucket_cur, off.data(), need * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->height, tier,
-                       ntier, Hh, b->bucket_cur, b->bucket_nodes);
+    LA_TIMED(b, "k_bucket_scatter", b->stream,
+             hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->height,
+                                tier, ntier, Hh, b->bucket_cur, b->bucket_nodes));
     LA_HIP(hipGetLastError());
     // the cursor copy must finish before `off` goes out of scope
     LA_HIP(hipStreamSynchronize(b->stream));
@@ -300,6 +306,7 @@ la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32
     for (int32_t r = 0; r < w->rounds; ++r) {
         DPArgs a = make_dp_args(b, w, H, lut);
         for (int32_t t = 0; t < ntier; ++t) {
+            if (off[((int64_t)t + 1) * Hh * 4] == off[(int64_t)t * Hh * 4]) continue;   // empty batch
             // one level = the four consecutive child-class buckets of (batch, height)
             for (int32_t h = 0; h < Hh; ++h) {
                 const int64_t q = ((int64_t)t * Hh + h) * 4;
@@ -308,20 +315,28 @@ la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32
                 const int64_t threads = (int64_t)cnt * a.NA;
                 const dim3 grid((unsigned)((threads + kBlock - 1) / kBlock));
                 if (a.NA <= 4)
-                    hipLaunchKernelGGL(k_dp_level<4>, grid, dim3(kBlock), 0, b->stream, a, b->bucket_nodes + off[q], cnt);
+                    LA_TIMED(b, "k_dp_level", b->stream,
+                             hipLaunchKernelGGL(k_dp_level<4>, grid, dim3(kBlock), 0, b->stream, a,
+                                                b->bucket_nodes + off[q], cnt));
                 else if (a.NA <= 6)
-                    hipLaunchKernelGGL(k_dp_level<6>, grid, dim3(kBlock), 0, b->stream, a, b->bucket_nodes + off[q], cnt);
+                    LA_TIMED(b, "k_dp_level", b->stream,
+                             hipLaunchKernelGGL(k_dp_level<6>, grid, dim3(kBlock), 0, b->stream, a,
+                                                b->bucket_nodes + off[q], cnt));
                 else
-                    hipLaunchKernelGGL(k_dp_level<8>, grid, dim3(kBlock), 0, b->stream, a, b->bucket_nodes + off[q], cnt);
+                    LA_TIMED(b, "k_dp_level", b->stream,
+                             hipLaunchKernelGGL(k_dp_level<8>, grid, dim3(kBlock), 0, b->stream, a,
+                                                b->bucket_nodes + off[q], cnt));
             }
             hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->stream, b->chg_count, (int64_t)1);
             for (int32_t h = Hh - 1; h >= 0; --h) {
                 const int64_t q = ((int64_t)t * Hh + h) * 4;
                 const int32_t cnt = (int32_t)(off[q + 4] - off[q]);
                 if (!cnt) continue;
-                hipLaunchKernelGGL(k_trace_level, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, a,
-                                   b->bucket_nodes + off[q], cnt, b->cur_layer, b->vlo, b->vhi, out_layers,
-                                   b->has_prev ? 1 : 0, b->chg_node, b->chg_old, b->chg_new, b->chg_count);
+                LA_TIMED(b, "k_trace_level", b->stream,
+                         hipLaunchKernelGGL(k_trace_level, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                                            b->stream, a, b->bucket_nodes + off[q], cnt, b->cur_layer, b->vlo, b->vhi,
+                                            out_layers, b->has_prev ? 1 : 0, b->chg_node, b->chg_old, b->chg_new,
+                                            b->chg_count));
             }
             s = commit_changed(b);
             if (s != LA_OK) return s;

@@ -418,10 +418,12 @@ template <int NAMAX>
 la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t nbig, int32_t nsmall, hipStream_t s)
 {
     if (nbig > 0)
-        hipLaunchKernelGGL(k_batched_big<NAMAX>, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, s, a, ba);
+        LA_TIMED(b, "k_batched_big", s,
+                 hipLaunchKernelGGL(k_batched_big<NAMAX>, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, s, a, ba));
     if (nsmall > 0)
-        hipLaunchKernelGGL(k_batched_dp<NAMAX>, dim3(b->grid_batched), dim3(kThreads), Tile<NAMAX>::BYTES, s, a,
-                           ba);
+        LA_TIMED(b, "k_batched_dp", s,
+                 hipLaunchKernelGGL(k_batched_dp<NAMAX>, dim3(b->grid_batched), dim3(kThreads), Tile<NAMAX>::BYTES, s,
+                                    a, ba));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }
@@ -434,6 +436,54 @@ int occupancy_grid()
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_dp<NAMAX>, kThreads, Tile<NAMAX>::BYTES);
     return std::max(1, cus) * std::max(1, per);
+}
+
+// R rounds over the batches onto stream s: per batch the persistent DP kernels and the
+// commit of the changed segments, then the history update of the round.
+la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
+                         const std::vector<int32_t> &cnt, hipStream_t s)
+{
+    const int32_t ntier = w->net_tier ? w->num_tiers : 1;
+    const int32_t R = w->rounds;
+    la_status st = LA_OK;
+    bool has_prev = b->has_prev;
+    const hipStream_t keep = b->stream;
+    b->stream = s;   // commit_changed and history_update launch on the batch's stream
+    for (int32_t r = 0; r < R && st == LA_OK; ++r) {
+        DPArgs a = make_dp_args(b, w, H, lut);
+        a.w.self_excl = has_prev ? 1 : 0;
+        for (int32_t t = 0; t < ntier && st == LA_OK; ++t) {
+            const int32_t nbig = cnt[2 * t], nsmall = cnt[2 * t + 1];
+            if (nbig + nsmall == 0) continue;
+            hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, b->chg_count, 1);
+            BArgs ba;
+            ba.tier_nets = b->tier_nets;
+            ba.tier_off = b->tier_off;
+            ba.tier = t;
+            ba.ctr = b->claim + r * ntier + t;
+            ba.height = b->height;
+            ba.net_big = b->net_big;
+            ba.bn_order = b->bn_order;
+            ba.bn_lvl = b->bn_lvl;
+            ba.bn_lvl_off = b->bn_lvl_off;
+            ba.bn_nlev = b->bn_nlev;
+            ba.cur = b->cur_layer;
+            ba.vlo = b->vlo;
+            ba.vhi = b->vhi;
+            ba.out_layers = out_layers;
+            ba.has_prev = has_prev ? 1 : 0;
+            ba.cl = ChangeList{b->chg_node, b->chg_old, b->chg_new, b->chg_count};
+            const int NA = b->NAmax;
+            st = NA <= 4   ? launch_batched<4>(b, a, ba, nbig, nsmall, s)
+                 : NA <= 6 ? launch_batched<6>(b, a, ba, nbig, nsmall, s)
+                           : launch_batched<8>(b, a, ba, nbig, nsmall, s);
+            if (st == LA_OK) st = commit_changed(b);
+        }
+        if (st == LA_OK) st = history_update(b, H, w->hist_inc);
+        has_prev = true;
+    }
+    b->stream = keep;
+    return st;
 }
 
 }  // namespace
@@ -456,19 +506,29 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     }
     // partition the nets by batch (big nets first in each) and check the batch indices
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->tier_cnt, nb + 1);
-    hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier, b->nets,
-                       b->net_big, b->tier_cnt, b->tier_cnt + nb);
+    LA_TIMED(b, "k_tier_count", b->stream,
+             hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
+                                b->nets, b->net_big, b->tier_cnt, b->tier_cnt + nb));
     hipLaunchKernelGGL(k_tier_offsets, dim3(1), dim3(256), 0, b->stream, b->tier_cnt, nb, b->tier_off, b->tier_cur,
                        b->claim, R * ntier);
-    hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier, b->nets,
-                       b->net_big, b->tier_cur, b->tier_nets);
+    LA_TIMED(b, "k_tier_scatter", b->stream,
+             hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
+                                b->nets, b->net_big, b->tier_cur, b->tier_nets));
     LA_HIP(hipGetLastError());
     std::vector<int32_t> cnt(nb + 1);
     LA_HIP(hipMemcpyAsync(cnt.data(), b->tier_cnt, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
     LA_HIP(hipStreamSynchronize(b->stream));
     if (cnt[nb]) return set_error(LA_ERR_INVALID_ARG, "net_tier holds a batch index >= num_tiers");
 
-    // the rounds, as one graph: per batch the persistent DP, then the commit; history per round
+    // the rounds, as one graph: per batch the persistent DP, then the commit; history per round.
+    // While kernels are being timed the same launches go straight to the batch's stream.
+    if (b->prof_on) {
+        hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->claim, R * ntier);
+        la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, b->stream);
+        if (st != LA_OK) return st;
+        b->has_prev = true;
+        return LA_OK;
+    }
     std::vector<int64_t> key = {R, ntier, b->has_prev, w->w_cong, w->w_cap, w->w_d, w->w_via, w->hist_inc,
                                 (int64_t)w->seg_w_q10, (int64_t)w->pin_w_q10, (int64_t)w->lambda_mohm,
                                 (int64_t)lut, (int64_t)H, (int64_t)out_layers};
@@ -482,49 +542,7 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         if (!b->cap_stream) LA_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         hipStream_t s = b->cap_stream;
         LA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        la_status st = LA_OK;
-        bool has_prev = b->has_prev;
-        for (int32_t r = 0; r < R && st == LA_OK; ++r) {
-            DPArgs a = make_dp_args(b, w, H, lut);
-            a.w.self_excl = has_prev ? 1 : 0;
-            for (int32_t t = 0; t < ntier && st == LA_OK; ++t) {
-                const int32_t nbig = cnt[2 * t], nsmall = cnt[2 * t + 1];
-                if (nbig + nsmall == 0) continue;
-                hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, b->chg_count, 1);
-                BArgs ba;
-                ba.tier_nets = b->tier_nets;
-                ba.tier_off = b->tier_off;
-                ba.tier = t;
-                ba.ctr = b->claim + r * ntier + t;
-                ba.height = b->height;
-                ba.net_big = b->net_big;
-                ba.bn_order = b->bn_order;
-                ba.bn_lvl = b->bn_lvl;
-                ba.bn_lvl_off = b->bn_lvl_off;
-                ba.bn_nlev = b->bn_nlev;
-                ba.cur = b->cur_layer;
-                ba.vlo = b->vlo;
-                ba.vhi = b->vhi;
-                ba.out_layers = out_layers;
-                ba.has_prev = has_prev ? 1 : 0;
-                ba.cl = ChangeList{b->chg_node, b->chg_old, b->chg_new, b->chg_count};
-                const int NA = b->NAmax;
-                st = NA <= 4   ? launch_batched<4>(b, a, ba, nbig, nsmall, s)
-                     : NA <= 6 ? launch_batched<6>(b, a, ba, nbig, nsmall, s)
-                               : launch_batched<8>(b, a, ba, nbig, nsmall, s);
-                if (st != LA_OK) break;
-                hipStream_t keep = b->stream;
-                b->stream = s;
-                st = commit_changed(b);
-                b->stream = keep;
-            }
-            if (st != LA_OK) break;
-            hipStream_t keep = b->stream;
-            b->stream = s;
-            st = history_update(b, H, w->hist_inc);
-            b->stream = keep;
-            has_prev = true;
-        }
+        const la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
         if (st != LA_OK) {

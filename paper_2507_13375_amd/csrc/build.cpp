@@ -361,8 +361,44 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
         for (int32_t v = b0; v < b0 + n; ++v) bn_order[base + cnt[height[v]]++] = v;
     }
 
+    // ---- algorithmic work of one DP round and of the Elmore sweeps -------------------
+    // Enumeration (Alg. 3): an entering layer l of node v takes the stacks [b, t] holding l
+    // (and the pin layer 0 at pins); each stack folds every child's best layer (an int64
+    // add and compare/select, 6 VALU ops) and prices the stack (10 ops).  Bytes: node
+    // inputs, congestion gathers (demand 4 B, capacity 1 B, history 4 B per GCell edge and
+    // routable layer, Eq. 3) and the chosen layer and via span.
+    double dp_ops = 0, dp_bytes = 0, dp_ops_big = 0;
+    for (int32_t i = 0; i < N; ++i) {
+        double ops = 0;
+        for (int64_t v = net_ptr[i]; v < net_ptr[i + 1]; ++v) {
+            const int k = ch_ptr[v + 1] - ch_ptr[v];
+            const bool pin = (flags[v] & (kSink | kDriver)) != 0;
+            const double per_stack = 6.0 * k + 10.0;
+            if (parent[v] < 0) {
+                ops += (double)L * per_stack;
+            } else {
+                const int d = dir[v];
+                for (int j = 0; j < tab.nA[d]; ++j) {
+                    const int l = tab.lay[d][j];
+                    const int lo = pin ? 0 : l;
+                    ops += (double)(lo + 1) * (double)(L - l) * per_stack;
+                }
+                dp_bytes += 9.0 * (double)len[v] * (double)tab.nA[d];
+            }
+            dp_bytes += 25.0 + 3.0 + ((flags[v] & kSink) ? 6.0 : 0.0);
+        }
+        dp_ops += ops;
+        if (net_ptr[i + 1] - net_ptr[i] > kCap) dp_ops_big += ops;
+    }
+    dp_bytes += 9.0 * (double)N;
+
     // ---- allocate and upload --------------------------------------------------------
     la_batch *b = new la_batch();
+    b->dp_ops = dp_ops;
+    b->dp_bytes = dp_bytes;
+    b->dp_ops_big = dp_ops_big;
+    b->el_fwd_bytes = 28.0 * (double)(M + S);
+    b->el_bwd_bytes = 40.0 * (double)(M + S);
     b->stream = (hipStream_t)stream;
     LA_HIP(hipGetDevice(&b->device));
     b->tab = tab;

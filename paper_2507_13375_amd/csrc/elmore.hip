@@ -421,8 +421,9 @@ TreeDev tree_view(const la_batch *b)
 
 la_status launch_rc_pre(la_batch *b)
 {
-    hipLaunchKernelGGL(k_rc, dim3(grid_for(b->nodes + b->sinks)), dim3(kBlock), 0, b->stream, tree_view(b), b->tab,
-                       (const uint8_t *)nullptr, b->R, b->C);
+    LA_TIMED(b, "k_rc", b->stream,
+             hipLaunchKernelGGL(k_rc, dim3(grid_for(b->nodes + b->sinks)), dim3(kBlock), 0, b->stream, tree_view(b),
+                                b->tab, (const uint8_t *)nullptr, b->R, b->C));
     LA_HIP(hipGetLastError());
     b->rc_assigned = false;
     return LA_OK;
@@ -430,8 +431,9 @@ la_status launch_rc_pre(la_batch *b)
 
 la_status launch_rc_from_layers(la_batch *b)
 {
-    hipLaunchKernelGGL(k_rc, dim3(grid_for(b->nodes + b->sinks)), dim3(kBlock), 0, b->stream, tree_view(b), b->tab,
-                       (const uint8_t *)b->cur_layer, b->R, b->C);
+    LA_TIMED(b, "k_rc", b->stream,
+             hipLaunchKernelGGL(k_rc, dim3(grid_for(b->nodes + b->sinks)), dim3(kBlock), 0, b->stream, tree_view(b),
+                                b->tab, (const uint8_t *)b->cur_layer, b->R, b->C));
     LA_HIP(hipGetLastError());
     b->rc_assigned = true;
     return LA_OK;
@@ -444,14 +446,17 @@ la_status elmore_forward(la_batch *b, const float *R, const float *C, float *del
     for (int h = 0; h < b->levels; ++h) {
         const int32_t cnt = lp[h + 1] - lp[h];
         if (!cnt) continue;
-        hipLaunchKernelGGL(k_elmore_up, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                           b->level_nodes + lp[h], cnt, R, C, b->el_S, b->el_Slo);
+        LA_TIMED(b, "k_elmore_up", b->stream,
+                 hipLaunchKernelGGL(k_elmore_up, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                                    b->level_nodes + lp[h], cnt, R, C, b->el_S, b->el_Slo));
     }
     for (int h = b->levels - 1; h >= 0; --h) {
         const int32_t cnt = lp[h + 1] - lp[h];
         if (!cnt) continue;
-        hipLaunchKernelGGL(k_elmore_down, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                           b->level_nodes + lp[h], cnt, R, C, b->el_S, b->el_Slo, b->el_t, b->el_tlo, delay);
+        LA_TIMED(b, "k_elmore_down", b->stream,
+                 hipLaunchKernelGGL(k_elmore_down, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                                    b->level_nodes + lp[h], cnt, R, C, b->el_S, b->el_Slo, b->el_t, b->el_tlo,
+                                    delay));
     }
     LA_HIP(hipGetLastError());
     b->fwd_R = R;
@@ -467,7 +472,9 @@ la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *
     const TreeDev T = tree_view(b);
     const float *gbar = g;
     if (from_dslack) {
-        hipLaunchKernelGGL(k_neg, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, g, b->scratch_f, b->sinks);
+        LA_TIMED(b, "k_neg", b->stream,
+                 hipLaunchKernelGGL(k_neg, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, g, b->scratch_f,
+                                    b->sinks));
         gbar = b->scratch_f;
     }
     const auto &lp = b->h_level_ptr;
@@ -475,15 +482,17 @@ la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *
     for (int h = 0; h < b->levels; ++h) {
         const int32_t cnt = lp[h + 1] - lp[h];
         if (!cnt) continue;
-        hipLaunchKernelGGL(k_adj_up, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                           b->level_nodes + lp[h], cnt, gbar, b->el_G, Glo);
+        LA_TIMED(b, "k_adj_up", b->stream,
+                 hipLaunchKernelGGL(k_adj_up, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                                    b->level_nodes + lp[h], cnt, gbar, b->el_G, Glo));
     }
     for (int h = b->levels - 1; h >= 0; --h) {
         const int32_t cnt = lp[h + 1] - lp[h];
         if (!cnt) continue;
-        hipLaunchKernelGGL(k_adj_down, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                           b->level_nodes + lp[h], cnt, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, b->el_G, Glo, gbar,
-                           b->el_Sig, Siglo, dR, dC);
+        LA_TIMED(b, "k_adj_down", b->stream,
+                 hipLaunchKernelGGL(k_adj_down, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                                    b->level_nodes + lp[h], cnt, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, b->el_G, Glo,
+                                    gbar, b->el_Sig, Siglo, dR, dC));
     }
     LA_HIP(hipGetLastError());
     b->bwd_done = true;
@@ -495,29 +504,39 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
 {
     const TreeDev T = tree_view(b);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, b->stream, b->wns_bits, 0xffffffffu, 1);
-    hipLaunchKernelGGL(k_slack, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, delay, b->slack, b->wns_bits);
-    hipLaunchKernelGGL(k_pin_weights, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, b->slack, b->wns_bits,
-                       pin_w);
-    hipLaunchKernelGGL(k_tiers, dim3(grid_for(b->nets)), dim3(kBlock), 0, b->stream, T, b->slack, b->wns_bits, tier);
+    LA_TIMED(b, "k_slack", b->stream,
+             hipLaunchKernelGGL(k_slack, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, delay, b->slack,
+                                b->wns_bits));
+    LA_TIMED(b, "k_pin_weights", b->stream,
+             hipLaunchKernelGGL(k_pin_weights, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, b->slack,
+                                b->wns_bits, pin_w));
+    LA_TIMED(b, "k_tiers", b->stream,
+             hipLaunchKernelGGL(k_tiers, dim3(grid_for(b->nets)), dim3(kBlock), 0, b->stream, T, b->slack,
+                                b->wns_bits, tier));
     if (mode == LA_WEIGHTS_PLAIN) {
         const auto &lp = b->h_level_ptr;
         for (int h = 0; h < b->levels; ++h) {
             const int32_t cnt = lp[h + 1] - lp[h];
             if (!cnt) continue;
-            hipLaunchKernelGGL(k_edge_w, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                               b->level_nodes + lp[h], cnt, pin_w, seg_w);
+            LA_TIMED(b, "k_edge_w", b->stream,
+                     hipLaunchKernelGGL(k_edge_w, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
+                                        b->level_nodes + lp[h], cnt, pin_w, seg_w));
         }
-        hipLaunchKernelGGL(k_lambda_plain, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, seg_w, lam);
+        LA_TIMED(b, "k_lambda_plain", b->stream,
+                 hipLaunchKernelGGL(k_lambda_plain, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, seg_w,
+                                    lam));
         LA_HIP(hipGetLastError());
         return LA_OK;
     }
     if (!b->fwd_done) return set_error(LA_ERR_STATE, "adjoint weights need la_elmore on this batch first");
-    hipLaunchKernelGGL(k_adj_seed, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, b->slack, pin_w,
-                       b->scratch_f);
+    LA_TIMED(b, "k_adj_seed", b->stream,
+             hipLaunchKernelGGL(k_adj_seed, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, b->slack, pin_w,
+                                b->scratch_f));
     la_status s = elmore_backward(b, b->scratch_f, false, nullptr, nullptr);
     if (s != LA_OK) return s;
-    hipLaunchKernelGGL(k_adj_weights, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->el_G, b->el_Glo,
-                       b->el_Sig, b->el_Siglo, b->scratch_f, seg_w, pin_w, lam);
+    LA_TIMED(b, "k_adj_weights", b->stream,
+             hipLaunchKernelGGL(k_adj_weights, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->el_G,
+                                b->el_Glo, b->el_Sig, b->el_Siglo, b->scratch_f, seg_w, pin_w, lam));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }

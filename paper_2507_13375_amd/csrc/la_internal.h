@@ -136,6 +136,15 @@ struct la_batch {
     uint32_t *wns_bits = nullptr;       // ordered-int encoding of the WNS float
     double *red = nullptr;              // reduction partials
     int32_t red_blocks = 0;
+
+    // algorithmic work per DP round and per Elmore sweep (computed at build)
+    double dp_ops = 0, dp_bytes = 0, el_fwd_bytes = 0, el_bwd_bytes = 0, dp_ops_big = 0;
+
+    // kernel timing (la_profile_begin/end): an event pair per bracketed launch
+    bool prof_on = false;
+    std::vector<const char *> prof_name;
+    std::vector<hipEvent_t> prof_ev;    // 2 per record, reused across sessions
+    size_t prof_used = 0;
 };
 
 namespace gapla {
@@ -151,6 +160,26 @@ la_status hip_fail(hipError_t e, const char *what);
     } while (0)
 
 TreeDev tree_view(const la_batch *b);
+
+// Brackets the launches made in its scope with events on `s` while profiling is on.
+class KernelTimer {
+public:
+    KernelTimer(la_batch *b, const char *name, hipStream_t s);
+    ~KernelTimer();
+    KernelTimer(const KernelTimer &) = delete;
+    KernelTimer &operator=(const KernelTimer &) = delete;
+
+private:
+    la_batch *b_;
+    hipStream_t s_;
+    size_t rec_ = SIZE_MAX;
+};
+
+#define LA_TIMED(b, name, s, ...)                         \
+    do {                                                  \
+        gapla::KernelTimer kt_((b), (name), (s));         \
+        __VA_ARGS__;                                      \
+    } while (0)
 
 // kernels launched from more than one source file
 la_status launch_rc_from_layers(la_batch *b);
