@@ -45,7 +45,7 @@ __global__ void k_dp_level(DPArgs a, const int32_t *nodes, int32_t cnt)
     }
     GlobalState st(a);
     const int64_t kap = root ? 0 : kappa_seg(a, tb, n, l);
-    dp_node<GlobalState, NAMAX>(a, tb, st, n, n, l, j, root, kap);
+    dp_node<GlobalState, NAMAX>(a, tb, st, n, l, j, root, kap);
 }
 
 // Alg. 4: each node takes the layer its parent recorded for the parent's entering layer.
@@ -63,9 +63,9 @@ __global__ void k_trace_level(DPArgs a, const int32_t *nodes, int32_t cnt, uint8
     if (i < cnt) {
         n = nodes[i];
         const int32_t p = a.T.parent[n];
-        const int lp = (p < 0 || a.T.parent[p] < 0) ? 0 : cur[p];
+        const int jp = (p < 0 || a.T.parent[p] < 0) ? 0 : tb.jidx[cur[p] & (kMaxL - 1)];
         GlobalState st(a);
-        ln = trace_node(tb, st, n, n, lp, p < 0, cur, vlo, vhi, out_layers, has_prev, &changed, &old_l);
+        trace_node(tb, st, n, n, jp, p < 0, cur, vlo, vhi, out_layers, has_prev, &ln, &changed, &old_l);
     }
     append_change(ChangeList{chg_node, chg_old, chg_new, chg_count}, changed, n, old_l, (uint8_t)ln);
 }

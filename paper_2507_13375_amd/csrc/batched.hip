@@ -26,26 +26,35 @@ la_status history_update(la_batch *b, int32_t *H, int32_t inc);
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBook = 256;   // ints of per-claim bookkeeping
+constexpr int kBook = 320;   // ints of per-claim bookkeeping
 
-// DP state of one LDS tile, indexed by tile-local node id.
+// DP state and per-node inputs of one LDS tile, indexed by tile-local node id.
 template <int NAMAX>
 struct LdsState {
     int64_t *F_;
     int32_t *S_;
     uint8_t *bt_, *sel_;
     const int16_t *chp, *chl;
-    const int32_t *gid;
+    const int32_t *lenp, *lam_, *cpin_;
+    const uint16_t *segw_, *pinw_;
+    const uint8_t *fld;   // flags | direction << 4
     __device__ int nch(int32_t s) const { return chp[s + 1] - chp[s]; }
     __device__ int32_t ch_state(int32_t s, int q) const { return chl[chp[s] + q]; }
-    __device__ int32_t ch_gid(int32_t s, int q) const { return gid[chl[chp[s] + q]]; }
     __device__ int64_t &F(int32_t s, int j) const { return F_[s * NAMAX + j]; }
     __device__ int32_t &S(int32_t s, int j) const { return S_[s * NAMAX + j]; }
     __device__ uint8_t *bt(int32_t s, int j) const { return bt_ + 2 * (s * NAMAX + j); }
-    __device__ uint8_t &sel(int32_t s, int l) const { return sel_[s * kMaxL + l]; }
+    __device__ uint8_t &sel(int32_t s, int jp) const { return sel_[s * NAMAX + jp]; }
+    __device__ uint8_t flags(int32_t s) const { return fld[s] & 15; }
+    __device__ int dir(int32_t s) const { return fld[s] >> 4; }
+    __device__ int32_t len(int32_t s) const { return lenp[s + 1] - lenp[s]; }
+    __device__ uint32_t segw(int32_t s) const { return segw_[s]; }
+    __device__ uint32_t lam(int32_t s) const { return (uint32_t)lam_[s]; }
+    __device__ int32_t cpin(int32_t s) const { return cpin_[s]; }
+    __device__ uint32_t pinw(int32_t s) const { return pinw_[s]; }
 };
 
-// LDS layout of one tile (byte offsets), shared by the host launch and the kernel
+// LDS layout of one tile (byte offsets), shared by the host launch and the kernel.  The
+// congestion table (L x 2 x 64 int32) follows at LUT; the launch sizes it by L.
 template <int NAMAX>
 struct Tile {
     static constexpr int nkey = 4 * kCap + 4;                       // (height, child class) buckets
@@ -54,18 +63,25 @@ struct Tile {
     static constexpr size_t S = KAP + (size_t)kCap * NAMAX * 8;     // int32 [kCap][NAMAX]
     static constexpr size_t GID = S + (size_t)kCap * NAMAX * 4;     // int32 [kCap]
     static constexpr size_t LEN = GID + (size_t)kCap * 4;           // int32 [kCap+1] prefix of segment lengths
-    static constexpr size_t KEYS = LEN + (size_t)(kCap + 1) * 4;    // int32 [nkey] bucket starts
+    static constexpr size_t G0 = LEN + (size_t)(kCap + 1) * 4;      // int32 [kCap] first GCell edge (layer 0)
+    static constexpr size_t LAM = G0 + (size_t)kCap * 4;            // int32 [kCap]
+    static constexpr size_t CPIN = LAM + (size_t)kCap * 4;          // int32 [kCap]
+    static constexpr size_t KEYS = CPIN + (size_t)kCap * 4;         // int32 [nkey] bucket starts
     static constexpr size_t BOOK = KEYS + (size_t)nkey * 4;         // int32 [kBook]
-    static constexpr size_t LUT = BOOK + (size_t)kBook * 4;         // int32 [L][2][64]
-    static constexpr size_t PAR = LUT + (size_t)kMaxL * 2 * kNDelta * 4;   // int16 [kCap]
+    static constexpr size_t PAR = BOOK + (size_t)kBook * 4;         // int16 [kCap]
     static constexpr size_t CHP = PAR + (size_t)kCap * 2;           // int16 [kCap+2]
     static constexpr size_t CHL = CHP + (size_t)(kCap + 2) * 2;     // int16 [kCap]
     static constexpr size_t ORD = CHL + (size_t)kCap * 2;           // int16 [kCap]
     static constexpr size_t KEY = ORD + (size_t)kCap * 2;           // int16 [kCap] bucket of each node
-    static constexpr size_t BT = KEY + (size_t)kCap * 2;            // uint8 [kCap][NAMAX][2]
-    static constexpr size_t SEL = BT + (size_t)kCap * NAMAX * 2;    // uint8 [kCap][kMaxL]
-    static constexpr size_t ENT = SEL + (size_t)kCap * kMaxL;       // uint8 [kCap] entering layer
-    static constexpr size_t BYTES = ENT + (size_t)kCap;
+    static constexpr size_t SEGW = KEY + (size_t)kCap * 2;          // uint16 [kCap]
+    static constexpr size_t PINW = SEGW + (size_t)kCap * 2;         // uint16 [kCap]
+    static constexpr size_t BT = PINW + (size_t)kCap * 2;           // uint8 [kCap][NAMAX][2]
+    static constexpr size_t SEL = BT + (size_t)kCap * NAMAX * 2;    // uint8 [kCap][NAMAX]
+    static constexpr size_t ENT = SEL + (size_t)kCap * NAMAX;       // uint8 [kCap] entering-layer index
+    static constexpr size_t FLD = ENT + (size_t)kCap;               // uint8 [kCap] flags | dir << 4
+    static constexpr size_t PRV = FLD + (size_t)kCap;               // uint8 [kCap] previous layer (255: none)
+    static constexpr size_t LUT = (PRV + (size_t)kCap + 15) & ~(size_t)15;
+    static size_t bytes(int L) { return LUT + (size_t)L * 2 * kNDelta * 4; }
 };
 
 struct BArgs {
@@ -80,40 +96,78 @@ struct BArgs {
     ChangeList cl;
 };
 
+// In-place inclusive prefix sum of x[0, n) by the whole workgroup (wave scans, then the
+// wave totals); tmp holds one int per wavefront.  Ends with a barrier.
+__device__ __forceinline__ void block_scan(int32_t *x, int32_t n, int32_t *tmp)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int32_t carry = 0;
+    for (int32_t c0 = 0; c0 < n; c0 += blockDim.x) {
+        const int32_t i = c0 + threadIdx.x;
+        int32_t v = i < n ? x[i] : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t y = __shfl_up(v, d);
+            if (lane >= d) v += y;
+        }
+        if (lane == 63) tmp[w] = v;
+        __syncthreads();
+        int32_t pre = carry, tot = carry;
+        for (int q = 0; q < nw; ++q) {
+            const int32_t t = tmp[q];
+            if (q < w) pre += t;
+            tot += t;
+        }
+        if (i < n) x[i] = v + pre;
+        carry = tot;
+        __syncthreads();
+    }
+}
+
 template <int NAMAX>
 __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
 {
     using TL = Tile<NAMAX>;
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ LayerTab tb;
+    __shared__ int32_t scan_tmp[kThreads / 64];
     load_tab(a.tab, tb);
     int64_t *F = (int64_t *)(smem + TL::F);
     int64_t *kap = (int64_t *)(smem + TL::KAP);
     int32_t *S = (int32_t *)(smem + TL::S);
     int32_t *gid = (int32_t *)(smem + TL::GID);
     int32_t *lenp = (int32_t *)(smem + TL::LEN);
+    int32_t *g0a = (int32_t *)(smem + TL::G0);
+    int32_t *lam = (int32_t *)(smem + TL::LAM);
+    int32_t *cpin = (int32_t *)(smem + TL::CPIN);
     int32_t *kst = (int32_t *)(smem + TL::KEYS);
     int32_t *book = (int32_t *)(smem + TL::BOOK);
-    int32_t *lut = (int32_t *)(smem + TL::LUT);
     int16_t *par = (int16_t *)(smem + TL::PAR);
     int16_t *chp = (int16_t *)(smem + TL::CHP);
     int16_t *chl = (int16_t *)(smem + TL::CHL);
     int16_t *order = (int16_t *)(smem + TL::ORD);
     int16_t *key = (int16_t *)(smem + TL::KEY);
+    uint16_t *segw = (uint16_t *)(smem + TL::SEGW);
+    uint16_t *pinw = (uint16_t *)(smem + TL::PINW);
     uint8_t *bt = smem + TL::BT;
     uint8_t *sel = smem + TL::SEL;
     uint8_t *ent = smem + TL::ENT;
+    uint8_t *fld = smem + TL::FLD;
+    uint8_t *prv = smem + TL::PRV;
+    int32_t *lut = (int32_t *)(smem + TL::LUT);
 
-    // bookkeeping: [0] claim base, [1] #tiles, [2] max height, [8..] tile start, [48..] tile
-    // end (claim-relative), [128..] per-net local node base, [168..] per-net local child base
+    // bookkeeping: [0] claim base, [1] #tiles, [2] max height of the tile; per tile: first
+    // and end claim index, node count; per claimed net: node count, first global node,
+    // first global child entry, tile-local node base and child base
     int32_t *s_base = book, *s_nsub = book + 1, *s_maxlev = book + 2;
-    int32_t *s_sub0 = book + 8, *s_sub1 = book + 48;
-    int32_t *s_lbase = book + 128, *s_cbase = book + 168;
+    int32_t *s_sub0 = book + 32, *s_sub1 = book + 64, *s_tn = book + 96;
+    int32_t *s_nn = book + 128, *s_g0 = book + 160, *s_c0 = book + 192, *s_lb = book + 224, *s_cb = book + 256;
+    static_assert(kClaim <= 32 && kBook >= 288, "bookkeeping layout");
 
     const int L = tb.L;
     for (int i = threadIdx.x; i < L * 2 * kNDelta; i += blockDim.x) lut[i] = a.w.lut[i];
 
-    LdsState<NAMAX> st{F, S, bt, sel, chp, chl, gid};
+    LdsState<NAMAX> st{F, S, bt, sel, chp, chl, lenp, lam, cpin, segw, pinw, fld};
     // the batch's small nets (its big nets run in k_batched_big)
     const int32_t off0 = ba.tier_off[2 * ba.tier + 1], cnt = ba.tier_off[2 * ba.tier + 2] - off0;
     const int32_t Xl = tb.X * L;
@@ -124,89 +178,87 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
         const int32_t base = *s_base;
         if (base >= cnt) break;
         const int32_t nclaim = min(kClaim, cnt - base);
+        if (threadIdx.x < nclaim) {
+            const int32_t net = ba.tier_nets[off0 + base + threadIdx.x];
+            const int32_t g0 = a.T.net_ptr[net];
+            s_nn[threadIdx.x] = a.T.net_ptr[net + 1] - g0;
+            s_g0[threadIdx.x] = g0;
+            s_c0[threadIdx.x] = a.T.ch_ptr[g0];
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
-            // split the claimed nets into LDS tiles of at most kCap nodes
-            int32_t ns = 0, open = -1, nodes = 0;
+            // split the claimed nets (each of at most kCap nodes) into tiles of at most kCap
+            int32_t ns = 0, nodes = 0, kids = 0;
             for (int32_t i = 0; i < nclaim; ++i) {
-                const int32_t net = ba.tier_nets[off0 + base + i];
-                const int32_t n = a.T.net_ptr[net + 1] - a.T.net_ptr[net];
-                if (open >= 0 && nodes + n > kCap) {
-                    s_sub1[ns - 1] = i;
-                    open = -1;
-                }
-                if (open < 0) {
-                    s_sub0[ns] = i;
-                    open = ns++;
+                const int32_t n = s_nn[i];
+                if (i == 0 || nodes + n > kCap) {
+                    if (i) {
+                        s_sub1[ns - 1] = i;
+                        s_tn[ns - 1] = nodes;
+                    }
+                    s_sub0[ns++] = i;
                     nodes = 0;
+                    kids = 0;
                 }
+                s_lb[i] = nodes;
+                s_cb[i] = kids;
                 nodes += n;
+                kids += n - 1;
             }
-            if (open >= 0) s_sub1[ns - 1] = nclaim;
+            s_sub1[ns - 1] = nclaim;
+            s_tn[ns - 1] = nodes;
             *s_nsub = ns;
         }
         __syncthreads();
         const int32_t nsub = *s_nsub;
         for (int32_t sb = 0; sb < nsub; ++sb) {
-            const int32_t i0 = s_sub0[sb], i1 = s_sub1[sb];
-            // ---- stage the tile ------------------------------------------------------------
-            if (threadIdx.x == 0) {
-                int32_t nb = 0, cb = 0;
-                for (int32_t i = i0; i < i1; ++i) {
-                    const int32_t net = ba.tier_nets[off0 + base + i];
-                    const int32_t n = a.T.net_ptr[net + 1] - a.T.net_ptr[net];
-                    s_lbase[i - i0] = nb;
-                    s_cbase[i - i0] = cb;
-                    nb += n;
-                    cb += n - 1;
-                }
-                s_lbase[i1 - i0] = nb;
-                s_cbase[i1 - i0] = cb;
-                *s_maxlev = 0;
-            }
+            const int32_t i0 = s_sub0[sb], i1 = s_sub1[sb], nn = s_tn[sb];
+            // ---- stage the tile: topology, inputs, (height, class) counts ----------------
             for (int32_t i = threadIdx.x; i < TL::nkey; i += blockDim.x) kst[i] = 0;
+            if (threadIdx.x == 0) {
+                *s_maxlev = 0;
+                lenp[0] = 0;
+                chp[nn] = (int16_t)(s_cb[i1 - 1] + s_nn[i1 - 1] - 1);
+            }
             __syncthreads();
-            const int32_t nn = s_lbase[i1 - i0];
-            const int32_t nnets = i1 - i0;
             for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
-                int32_t k = 0;
-                while (k + 1 < nnets && s_lbase[k + 1] <= u) ++k;
-                const int32_t net = ba.tier_nets[off0 + base + i0 + k];
-                const int32_t g0 = a.T.net_ptr[net];
-                const int32_t g = g0 + (u - s_lbase[k]);
+                int32_t lo_ = i0, hi_ = i1;      // the net of u: last k with s_lb[k] <= u
+                while (hi_ - lo_ > 1) {
+                    const int32_t mid = (lo_ + hi_) >> 1;
+                    if (s_lb[mid] <= u) lo_ = mid;
+                    else hi_ = mid;
+                }
+                const int32_t g0 = s_g0[lo_], lb = s_lb[lo_];
+                const int32_t g = g0 + (u - lb);
                 gid[u] = g;
                 const int32_t pg = a.T.parent[g];
-                par[u] = (int16_t)(pg < 0 ? -1 : pg - g0 + s_lbase[k]);
-                const int32_t c0 = a.T.ch_ptr[g0];
+                par[u] = (int16_t)(pg < 0 ? -1 : pg - g0 + lb);
                 const int32_t e0 = a.T.ch_ptr[g], e1 = a.T.ch_ptr[g + 1];
-                chp[u] = (int16_t)(s_cbase[k] + (e0 - c0));
-                for (int32_t e = e0; e < e1; ++e)
-                    chl[s_cbase[k] + (e - c0)] = (int16_t)(a.T.ch[e] - g0 + s_lbase[k]);
+                const int32_t cb = s_cb[lo_] + (e0 - s_c0[lo_]);
+                chp[u] = (int16_t)cb;
+                for (int32_t e = e0; e < e1; ++e) chl[cb + (e - e0)] = (int16_t)(a.T.ch[e] - g0 + lb);
                 const int32_t h = ba.height[g];
                 const int32_t kk = e1 - e0;
                 const int32_t bk = 4 * h + (kk < 3 ? kk : 3);
                 key[u] = (int16_t)bk;
                 atomicAdd(&kst[bk + 1], 1);
                 atomicMax(s_maxlev, h);
-                lenp[u] = a.T.len[g];
+                lenp[u + 1] = a.T.len[g];
+                g0a[u] = a.T.g0[g];
+                fld[u] = (uint8_t)(a.T.flags[g] | (a.T.dir[g] << 4));
+                segw[u] = a.w.seg_w[g];
+                lam[u] = a.w.lam[g];
+                cpin[u] = a.T.cpin[g];
+                const int32_t sid = a.T.sink_id[g];
+                pinw[u] = sid >= 0 ? a.w.pin_w[sid] : (uint16_t)0;
+                prv[u] = a.w.self_excl ? a.prev[g] : (uint8_t)255;
 #pragma unroll
                 for (int jj = 0; jj < NAMAX; ++jj) kap[u * NAMAX + jj] = 0;
             }
-            if (threadIdx.x == 0) chp[nn] = (int16_t)s_cbase[i1 - i0];
             __syncthreads();
             const int32_t maxlev = *s_maxlev;
-            const int32_t nk = 4 * maxlev + 4;
-            if (threadIdx.x == 0) {
-                for (int32_t q = 0; q < nk; ++q) kst[q + 1] += kst[q];
-                // exclusive prefix of the segment lengths
-                int32_t acc = 0;
-                for (int32_t u = 0; u < nn; ++u) {
-                    const int32_t l_ = lenp[u];
-                    lenp[u] = acc;
-                    acc += l_;
-                }
-                lenp[nn] = acc;
-            }
-            __syncthreads();
+            block_scan(kst, 4 * maxlev + 5, scan_tmp);   // bucket starts
+            block_scan(lenp, nn + 1, scan_tmp);          // lenp[u]: first GCell step of u
             // (height, class) order; kst[q] ends as the end of bucket q = start of q+1
             for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) order[atomicAdd(&kst[key[u]], 1)] = (int16_t)u;
             // congestion costs: one thread per GCell edge of the tile's segments, every
@@ -219,10 +271,10 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                     if (lenp[mid] <= pidx) lo_ = mid;
                     else hi_ = mid;
                 }
-                const int32_t u = lo_, n = gid[u];
-                const int d = a.T.dir[n];
-                const int32_t g = a.T.g0[n] + (pidx - lenp[u]) * (d == 0 ? L : Xl);
-                const int self = a.w.self_excl ? (int)a.prev[n] : -1;
+                const int32_t u = lo_;
+                const int d = fld[u] >> 4;
+                const int32_t g = g0a[u] + (pidx - lenp[u]) * (d == 0 ? L : Xl);
+                const int self = prv[u];
                 const int na = tb.nA[d];
 #pragma unroll
                 for (int jj = 0; jj < NAMAX; ++jj) {
@@ -245,18 +297,17 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                 for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
                     const int32_t u = order[lb + it / NAMAX];
                     const int j = it % NAMAX;
-                    const int32_t n = gid[u];
                     const bool root = par[u] < 0;
                     int l;
                     if (root) {
                         if (j != 0) continue;
                         l = 0;
                     } else {
-                        const int d = a.T.dir[n];
+                        const int d = fld[u] >> 4;
                         if (j >= tb.nA[d]) continue;
                         l = tb.lay[d][j];
                     }
-                    dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, n, l, j, root, root ? 0 : kap[u * NAMAX + j]);
+                    dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, root ? 0 : kap[u * NAMAX + j]);
                 }
                 __syncthreads();
             }
@@ -273,10 +324,9 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                         const int32_t u = order[it];
                         n = gid[u];
                         const int32_t pu = par[u];
-                        const int lp = (pu < 0 || par[pu] < 0) ? 0 : ent[pu];
-                        ln = trace_node(tb, st, u, n, lp, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev,
-                                        &changed, &old_l);
-                        ent[u] = (uint8_t)ln;
+                        const int jp = (pu < 0 || par[pu] < 0) ? 0 : ent[pu];
+                        ent[u] = (uint8_t)trace_node(tb, st, u, n, jp, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers,
+                                                     ba.has_prev, &ln, &changed, &old_l);
                     }
                     append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
                 }
@@ -315,7 +365,7 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
                     if (j >= tb.nA[d]) continue;
                     l = tb.lay[d][j];
                 }
-                dp_node<GlobalState, NAMAX>(a, tb, gst, n, n, l, j, root, root ? 0 : kappa_seg(a, tb, n, l));
+                dp_node<GlobalState, NAMAX>(a, tb, gst, n, l, j, root, root ? 0 : kappa_seg(a, tb, n, l));
             }
             __syncthreads();
         }
@@ -330,9 +380,9 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
                 if (it < c) {
                     n = ba.bn_order[b0 + it];
                     const int32_t pp = a.T.parent[n];
-                    const int lp = (pp < 0 || a.T.parent[pp] < 0) ? 0 : ba.cur[pp];
-                    ln = trace_node(tb, gst, n, n, lp, pp < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev,
-                                    &changed, &old_l);
+                    const int jp = (pp < 0 || a.T.parent[pp] < 0) ? 0 : tb.jidx[ba.cur[pp] & (kMaxL - 1)];
+                    trace_node(tb, gst, n, n, jp, pp < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev, &ln,
+                               &changed, &old_l);
                 }
                 append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
             }
@@ -422,19 +472,19 @@ la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t 
                  hipLaunchKernelGGL(k_batched_big<NAMAX>, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, s, a, ba));
     if (nsmall > 0)
         LA_TIMED(b, "k_batched_dp", s,
-                 hipLaunchKernelGGL(k_batched_dp<NAMAX>, dim3(b->grid_batched), dim3(kThreads), Tile<NAMAX>::BYTES, s,
-                                    a, ba));
+                 hipLaunchKernelGGL(k_batched_dp<NAMAX>, dim3(b->grid_batched), dim3(kThreads),
+                                    Tile<NAMAX>::bytes(b->tab.L), s, a, ba));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }
 
 template <int NAMAX>
-int occupancy_grid()
+int occupancy_grid(int L)
 {
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_dp<NAMAX>, kThreads, Tile<NAMAX>::BYTES);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_dp<NAMAX>, kThreads, Tile<NAMAX>::bytes(L));
     return std::max(1, cus) * std::max(1, per);
 }
 
@@ -502,7 +552,8 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     }
     if (!b->grid_batched) {
         const int NA = b->NAmax;
-        b->grid_batched = NA <= 4 ? occupancy_grid<4>() : (NA <= 6 ? occupancy_grid<6>() : occupancy_grid<8>());
+        const int L = b->tab.L;
+        b->grid_batched = NA <= 4 ? occupancy_grid<4>(L) : (NA <= 6 ? occupancy_grid<6>(L) : occupancy_grid<8>(L));
     }
     // partition the nets by batch (big nets first in each) and check the batch indices
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->tier_cnt, nb + 1);

@@ -37,7 +37,7 @@ struct DPArgs {
     int64_t *F;        // [node][NA] subtree cost f of the chosen candidate
     int32_t *S;        // [node][NA] its downstream capacitance (aF)
     uint8_t *bt;       // [node][NA][2] chosen via stack
-    uint8_t *sel;      // [node][kMaxL] node's layer for each entering layer of its parent
+    uint8_t *sel;      // [node][NA] node's layer for each entering-layer index of its parent
     int32_t NA;
 };
 
@@ -51,17 +51,29 @@ __device__ __forceinline__ void load_tab(const LayerTab &src, LayerTab &dst)
     __syncthreads();
 }
 
-// DP state in HBM, indexed by global node id (plain form).
+// DP state in HBM, indexed by global node id (plain form).  Besides the DP state, a state
+// type gives the per-node inputs the DP reads: flags, segment length and direction, Q10
+// segment weight, look-ahead coefficient, pin capacitance and (at sinks) pin weight.
 struct GlobalState {
     const DPArgs &a;
     __device__ GlobalState(const DPArgs &a_) : a(a_) {}
     __device__ int nch(int32_t s) const { return a.T.ch_ptr[s + 1] - a.T.ch_ptr[s]; }
     __device__ int32_t ch_state(int32_t s, int q) const { return a.T.ch[a.T.ch_ptr[s] + q]; }
-    __device__ int32_t ch_gid(int32_t s, int q) const { return a.T.ch[a.T.ch_ptr[s] + q]; }
     __device__ int64_t &F(int32_t s, int j) const { return a.F[(int64_t)s * a.NA + j]; }
     __device__ int32_t &S(int32_t s, int j) const { return a.S[(int64_t)s * a.NA + j]; }
     __device__ uint8_t *bt(int32_t s, int j) const { return a.bt + 2 * ((int64_t)s * a.NA + j); }
-    __device__ uint8_t &sel(int32_t s, int l) const { return a.sel[(int64_t)s * kMaxL + l]; }
+    __device__ uint8_t &sel(int32_t s, int jp) const { return a.sel[(int64_t)s * a.NA + jp]; }
+    __device__ uint8_t flags(int32_t s) const { return a.T.flags[s]; }
+    __device__ int32_t len(int32_t s) const { return a.T.len[s]; }
+    __device__ int dir(int32_t s) const { return a.T.dir[s]; }
+    __device__ uint32_t segw(int32_t s) const { return a.w.seg_w[s]; }
+    __device__ uint32_t lam(int32_t s) const { return (uint32_t)a.w.lam[s]; }
+    __device__ int32_t cpin(int32_t s) const { return a.T.cpin[s]; }
+    __device__ uint32_t pinw(int32_t s) const
+    {
+        const int32_t sid = a.T.sink_id[s];
+        return sid >= 0 ? a.w.pin_w[sid] : 0u;
+    }
 };
 
 // exact products of operands of known width
@@ -126,15 +138,14 @@ struct ChildIn {
 };
 
 template <class St>
-__device__ __forceinline__ ChildIn child_in(const DPArgs &a, const St &st, int32_t s, int q)
+__device__ __forceinline__ ChildIn child_in(const St &st, int32_t s, int q)
 {
-    const int32_t cg = st.ch_gid(s, q);
     ChildIn c;
     c.cs = st.ch_state(s, q);
-    c.len = a.T.len[cg];
-    c.w = a.w.seg_w[cg];
-    c.lam = (uint32_t)a.w.lam[cg];
-    c.dir = a.T.dir[cg];
+    c.len = st.len(c.cs);
+    c.w = st.segw(c.cs);
+    c.lam = st.lam(c.cs);
+    c.dir = st.dir(c.cs);
     return c;
 }
 
@@ -182,31 +193,31 @@ __device__ __forceinline__ T pick(const T (&arr)[N], int i)
     return v;
 }
 
-// DP of node n (state index s, global id n) for its entering layer l (index j in its
-// direction list; j = 0 and l = 0 at the root).  kap is kappa_n(l) (0 at the root).
-// NAMAX bounds the routable layers per direction.
+// DP of node state s for its entering layer l (index j in its direction list; j = 0 and
+// l = 0 at the root).  kap is kappa_n(l) (0 at the root).  NAMAX bounds the routable
+// layers per direction.
 template <class St, int NAMAX>
-__device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int32_t n, int l,
-                                        int j, bool root, int64_t kap)
+__device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int l, int j,
+                                        bool root, int64_t kap)
 {
     const int L = tb.L;
     const Wd wd{(uint32_t)a.w.w_d};
-    const bool pin = a.T.flags[n] & (kSink | kDriver);
+    const uint8_t fl = st.flags(s);
+    const bool pin = fl & (kSink | kDriver);
     const int lo = pin ? 0 : l;
     const int hi = l;
     int64_t own_const = 0;
     uint32_t Cs = 0, Rw = 0, segw = 0, lam = 0;
     if (!root) {
-        const int32_t len = a.T.len[n];
+        const int32_t len = st.len(s);
         Cs = (uint32_t)(tb.c[l] * len);
         Rw = (uint32_t)(tb.r[l] * len);
         own_const = a.w.w_cong * kap + a.w.w_cap * (int64_t)Cs;
-        segw = a.w.seg_w[n];
-        lam = (uint32_t)a.w.lam[n];
+        segw = st.segw(s);
+        lam = st.lam(s);
     }
-    const int32_t cpin = a.T.cpin[n];
-    const int32_t sid = a.T.sink_id[n];
-    const int64_t pin_term = sid >= 0 ? wd(Tq(a.w.pin_w[sid], rvia_d(tb, l, 0), 2 * (uint32_t)cpin)) : 0;
+    const int32_t cpin = st.cpin(s);
+    const int64_t pin_term = (fl & kSink) ? wd(Tq(st.pinw(s), rvia_d(tb, l, 0), 2 * (uint32_t)cpin)) : 0;
     const int k = st.nch(s);
 
     Best best;
@@ -242,7 +253,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             if (q < k) {
-                cin[q] = child_in(a, st, s, q);
+                cin[q] = child_in(st, s, q);
                 nc[q] = tb.nA[cin[q].dir];
 #pragma unroll
                 for (int jj = 0; jj < NAMAX; ++jj) {
@@ -303,7 +314,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-            if (q < k) st.sel(st.ch_state(s, q), l) = best_sel[q];
+            if (q < k) st.sel(st.ch_state(s, q), j) = best_sel[q];
     } else {
         // ---- full enumeration: every stack, each child rescanned ------------------------
         for (int b = 0; b <= lo; ++b)
@@ -311,7 +322,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
                 bool ok = true;
                 int64_t sumV = 0, sumZ = 0;
                 for (int q = 0; q < k && ok; ++q) {
-                    const ChildIn c = child_in(a, st, s, q);
+                    const ChildIn c = child_in(st, s, q);
                     bool have = false;
                     ChildKey bestc{0, 0, 0};
                     for (int lc = b; lc <= t; ++lc) {
@@ -330,7 +341,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
             }
         // each child's layer at the chosen stack, by the same rule
         for (int q = 0; q < k; ++q) {
-            const ChildIn c = child_in(a, st, s, q);
+            const ChildIn c = child_in(st, s, q);
             bool have = false;
             int64_t bk = 0;
             int bl = 0;
@@ -343,7 +354,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
                     bl = lc;
                 }
             }
-            st.sel(c.cs, l) = (uint8_t)bl;
+            st.sel(c.cs, j) = (uint8_t)bl;
         }
     }
 
@@ -382,20 +393,21 @@ __device__ __forceinline__ void append_change(const ChangeList &cl, bool pred, i
     }
 }
 
-// Alg. 4 at node n: its layer is the one its parent recorded for the parent's entering
-// layer; its via span is the stack recorded for its own entering layer.
-// lp: the parent's entering layer (0 at a root's children).  Returns n's entering layer
-// and sets *changed / *old_l for the commit list.
+// Alg. 4 at node n (state s): its layer is the one its parent recorded for the parent's
+// entering layer; its via span is the stack recorded for its own entering layer.
+// jp: the index of the parent's entering layer in the parent's direction list (0 when
+// the parent is the root).  Returns n's entering-layer index (0 at the root), sets *ln to
+// the layer and *changed / *old_l for the commit list.
 template <class St>
-__device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int32_t s, int32_t n, int lp, bool root,
+__device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int32_t s, int32_t n, int jp, bool root,
                                           uint8_t *cur, uint8_t *vlo, uint8_t *vhi, uint8_t *out_layers,
-                                          int has_prev, bool *changed, uint8_t *old_l)
+                                          int has_prev, int *ln_out, bool *changed, uint8_t *old_l)
 {
     int ln = 0, j = 0;
     if (!root) {
-        ln = st.sel(s, lp & (kMaxL - 1));
-        // the parent's DP recorded a routable layer of n's direction; the masks only keep
-        // every index inside its array
+        // jp < the parent's routable-layer count and the parent's DP recorded a routable
+        // layer of n's direction; the clamps only keep every index inside its array
+        ln = st.sel(s, (jp >= 0 && jp < kMaxA) ? jp : 0);
         ln = ln < tb.L ? ln : 0;
         j = tb.jidx[ln] < 0 ? 0 : tb.jidx[ln];
     }
@@ -407,7 +419,8 @@ __device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int3
     if (out_layers) out_layers[n] = (uint8_t)ln;
     *changed = !root && (!has_prev || old != ln);
     *old_l = has_prev ? old : (uint8_t)255;
-    return ln;
+    *ln_out = ln;
+    return j;
 }
 
 }  // namespace gapla
