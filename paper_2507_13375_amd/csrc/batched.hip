@@ -27,6 +27,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kBook = 320;   // ints of per-claim bookkeeping
+constexpr int kHB = 32;      // height classes of small nets per batch
+constexpr int kNB = 1 + kHB; // partition buckets per batch
 
 // DP state and per-node inputs of one LDS tile, indexed by tile-local node id.
 template <int NAMAX>
@@ -58,9 +60,9 @@ struct LdsState {
 template <int NAMAX>
 struct Tile {
     static constexpr int nkey = 4 * kCap + 4;                       // (height, child class) buckets
+    // F holds kappa_n(l) until the DP item (n, l) reads it and overwrites it with f
     static constexpr size_t F = 0;                                  // int64 [kCap][NAMAX]
-    static constexpr size_t KAP = F + (size_t)kCap * NAMAX * 8;     // int64 [kCap][NAMAX] congestion cost
-    static constexpr size_t S = KAP + (size_t)kCap * NAMAX * 8;     // int32 [kCap][NAMAX]
+    static constexpr size_t S = F + (size_t)kCap * NAMAX * 8;       // int32 [kCap][NAMAX]
     static constexpr size_t GID = S + (size_t)kCap * NAMAX * 4;     // int32 [kCap]
     static constexpr size_t LEN = GID + (size_t)kCap * 4;           // int32 [kCap+1] prefix of segment lengths
     static constexpr size_t G0 = LEN + (size_t)(kCap + 1) * 4;      // int32 [kCap] first GCell edge (layer 0)
@@ -125,7 +127,7 @@ __device__ __forceinline__ void block_scan(int32_t *x, int32_t n, int32_t *tmp)
 }
 
 template <int NAMAX>
-__global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
+__global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPArgs a, BArgs ba)
 {
     using TL = Tile<NAMAX>;
     extern __shared__ __align__(16) uint8_t smem[];
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
     __shared__ int32_t scan_tmp[kThreads / 64];
     load_tab(a.tab, tb);
     int64_t *F = (int64_t *)(smem + TL::F);
-    int64_t *kap = (int64_t *)(smem + TL::KAP);
+    int64_t *kap = F;   // congestion costs, replaced by f item by item
     int32_t *S = (int32_t *)(smem + TL::S);
     int32_t *gid = (int32_t *)(smem + TL::GID);
     int32_t *lenp = (int32_t *)(smem + TL::LEN);
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
 
     LdsState<NAMAX> st{F, S, bt, sel, chp, chl, lenp, lam, cpin, segw, pinw, fld};
     // the batch's small nets (its big nets run in k_batched_big)
-    const int32_t off0 = ba.tier_off[2 * ba.tier + 1], cnt = ba.tier_off[2 * ba.tier + 2] - off0;
+    const int32_t off0 = ba.tier_off[ba.tier * kNB + 1], cnt = ba.tier_off[(ba.tier + 1) * kNB] - off0;
     const int32_t Xl = tb.X * L;
 
     for (;;) {
@@ -345,7 +347,7 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
     __shared__ LayerTab tb;
     load_tab(a.tab, tb);
     GlobalState gst(a);
-    const int32_t off0 = ba.tier_off[2 * ba.tier], cnt = ba.tier_off[2 * ba.tier + 1] - off0;
+    const int32_t off0 = ba.tier_off[ba.tier * kNB], cnt = ba.tier_off[ba.tier * kNB + 1] - off0;
     for (int32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         const int32_t net = ba.tier_nets[off0 + i];
         const int32_t q = ba.net_big[net];
@@ -392,13 +394,25 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
 }
 
 // ---- batch (tier) partition -----------------------------------------------------------
-// bucket of a net: 2*tier + (big ? 0 : 1), so each batch lists its big nets first.
-
-__global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big, int32_t *cnt,
-                             int32_t *bad)
+// Bucket of a net: its batch's big nets first, then its small nets from the tallest
+// tree to the shortest (height classes 0..kHB-1, taller trees share the last class), so
+// a workgroup's tile holds trees of similar height and walks few levels, and the work
+// queue hands out the long trees first.
+__device__ __forceinline__ int32_t net_bucket(int t, bool big, int32_t h)
 {
-    __shared__ int32_t hist[512];
-    for (int i = threadIdx.x; i < 2 * ntier; i += blockDim.x) hist[i] = 0;
+    return t * kNB + (big ? 0 : 1 + (kHB - 1 - (h < kHB - 1 ? h : kHB - 1)));
+}
+
+constexpr int kLdsNB = 2048;   // buckets counted in LDS; more go straight to HBM counters
+
+__global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big,
+                             const int32_t *net_ptr, const int32_t *height, int32_t *cnt, int32_t *bad)
+{
+    __shared__ int32_t hist[kLdsNB];
+    const int32_t nb = ntier * kNB;
+    const bool local = nb <= kLdsNB;
+    if (local)
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
     __syncthreads();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets; i += (int64_t)gridDim.x * blockDim.x) {
         const int t = tier ? tier[i] : 0;
@@ -406,47 +420,57 @@ __global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, c
             atomicAdd(bad, 1);
             continue;
         }
-        atomicAdd(&hist[2 * t + (net_big[i] >= 0 ? 0 : 1)], 1);
+        const int32_t q = net_bucket(t, net_big[i] >= 0, height[net_ptr[i]]);
+        atomicAdd(local ? &hist[q] : &cnt[q], 1);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 2 * ntier; i += blockDim.x)
-        if (hist[i]) atomicAdd(&cnt[i], hist[i]);
+    if (local)
+        for (int i = threadIdx.x; i < nb; i += blockDim.x)
+            if (hist[i]) atomicAdd(&cnt[i], hist[i]);
 }
 
+// off[0..nb] = exclusive prefix of cnt, cur = off; the claim counters start at zero
 __global__ void k_tier_offsets(const int32_t *cnt, int32_t nb, int32_t *off, int32_t *cur, int32_t *claim,
                                int32_t nclaim)
 {
-    if (threadIdx.x == 0) {
-        int32_t acc = 0;
-        for (int32_t i = 0; i < nb; ++i) {
-            off[i] = acc;
-            cur[i] = acc;
-            acc += cnt[i];
-        }
-        off[nb] = acc;
-    }
+    __shared__ int32_t tmp[1024 / 64];
+    for (int32_t i = threadIdx.x; i <= nb; i += blockDim.x) off[i] = i == 0 ? 0 : cnt[i - 1];
+    __syncthreads();
+    block_scan(off, nb + 1, tmp);
+    for (int32_t i = threadIdx.x; i < nb; i += blockDim.x) cur[i] = off[i];
     for (int32_t i = threadIdx.x; i < nclaim; i += blockDim.x) claim[i] = 0;
 }
 
 __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big,
-                               int32_t *cur, int32_t *out)
+                               const int32_t *net_ptr, const int32_t *height, int32_t *cur, int32_t *out)
 {
-    __shared__ int32_t hist[512];
-    __shared__ int32_t base[512];
+    __shared__ int32_t hist[kLdsNB];
+    __shared__ int32_t base[kLdsNB];
+    const int32_t nb = ntier * kNB;
+    if (nb > kLdsNB) {
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const int t = tier ? tier[i] : 0;
+            if (t >= ntier) continue;
+            out[atomicAdd(&cur[net_bucket(t, net_big[i] >= 0, height[net_ptr[i]])], 1)] = (int32_t)i;
+        }
+        return;
+    }
+    // one tile of blockDim nets at a time: rank inside the tile, then reserve per bucket
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < nets; i0 += (int64_t)gridDim.x * blockDim.x) {
-        for (int i = threadIdx.x; i < 2 * ntier; i += blockDim.x) hist[i] = 0;
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
         __syncthreads();
         const int64_t i = i0 + threadIdx.x;
-        int q = -1, r = 0;
+        int32_t q = -1, r = 0;
         if (i < nets) {
             const int t = tier ? tier[i] : 0;
             if (t < ntier) {
-                q = 2 * t + (net_big[i] >= 0 ? 0 : 1);
+                q = net_bucket(t, net_big[i] >= 0, height[net_ptr[i]]);
                 r = atomicAdd(&hist[q], 1);
             }
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < 2 * ntier; k += blockDim.x)
+        for (int k = threadIdx.x; k < nb; k += blockDim.x)
             if (hist[k]) base[k] = atomicAdd(&cur[k], hist[k]);
         __syncthreads();
         if (q >= 0) out[base[q] + r] = (int32_t)i;
@@ -488,6 +512,14 @@ int occupancy_grid(int L)
     return std::max(1, cus) * std::max(1, per);
 }
 
+// small nets of batch t in the partition counts
+int32_t small_nets(const std::vector<int32_t> &cnt, int32_t t)
+{
+    int32_t n = 0;
+    for (int q = 1; q < kNB; ++q) n += cnt[t * kNB + q];
+    return n;
+}
+
 // R rounds over the batches onto stream s: per batch the persistent DP kernels and the
 // commit of the changed segments, then the history update of the round.
 la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
@@ -503,7 +535,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
         DPArgs a = make_dp_args(b, w, H, lut);
         a.w.self_excl = has_prev ? 1 : 0;
         for (int32_t t = 0; t < ntier && st == LA_OK; ++t) {
-            const int32_t nbig = cnt[2 * t], nsmall = cnt[2 * t + 1];
+            const int32_t nbig = cnt[t * kNB], nsmall = small_nets(cnt, t);
             if (nbig + nsmall == 0) continue;
             hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, b->chg_count, 1);
             BArgs ba;
@@ -541,7 +573,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
 la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers)
 {
     const int32_t ntier = w->net_tier ? w->num_tiers : 1;
-    const int32_t nb = 2 * ntier;
+    const int32_t nb = ntier * kNB;
     const int32_t R = w->rounds;
     if (b->claim_cap < R * ntier) {
         if (b->claim) (void)hipFree(b->claim);
@@ -555,16 +587,16 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         const int L = b->tab.L;
         b->grid_batched = NA <= 4 ? occupancy_grid<4>(L) : (NA <= 6 ? occupancy_grid<6>(L) : occupancy_grid<8>(L));
     }
-    // partition the nets by batch (big nets first in each) and check the batch indices
-    hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->tier_cnt, nb + 1);
+    // partition the nets by batch (big nets first, then by height) and check the batch indices
+    hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb + 1);
     LA_TIMED(b, "k_tier_count", b->stream,
              hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
-                                b->nets, b->net_big, b->tier_cnt, b->tier_cnt + nb));
-    hipLaunchKernelGGL(k_tier_offsets, dim3(1), dim3(256), 0, b->stream, b->tier_cnt, nb, b->tier_off, b->tier_cur,
+                                b->nets, b->net_big, b->net_ptr, b->height, b->tier_cnt, b->tier_cnt + nb));
+    hipLaunchKernelGGL(k_tier_offsets, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb, b->tier_off, b->tier_cur,
                        b->claim, R * ntier);
     LA_TIMED(b, "k_tier_scatter", b->stream,
              hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
-                                b->nets, b->net_big, b->tier_cur, b->tier_nets));
+                                b->nets, b->net_big, b->net_ptr, b->height, b->tier_cur, b->tier_nets));
     LA_HIP(hipGetLastError());
     std::vector<int32_t> cnt(nb + 1);
     LA_HIP(hipMemcpyAsync(cnt.data(), b->tier_cnt, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
@@ -584,8 +616,8 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
                                 (int64_t)w->seg_w_q10, (int64_t)w->pin_w_q10, (int64_t)w->lambda_mohm,
                                 (int64_t)lut, (int64_t)H, (int64_t)out_layers};
     for (int32_t t = 0; t < ntier; ++t) {
-        key.push_back(cnt[2 * t]);
-        key.push_back(cnt[2 * t + 1] > 0);
+        key.push_back(cnt[t * kNB]);
+        key.push_back(small_nets(cnt, t) > 0);
     }
     if (!b->gexec || key != b->gkey) {
         if (b->gexec) (void)hipGraphExecDestroy(b->gexec);

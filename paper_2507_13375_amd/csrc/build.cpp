@@ -450,9 +450,10 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->bn_lvl_off, bn_lvl_off));
     chk(upload(&b->bn_nlev, bn_nlev));
     chk(alloc(&b->tier_nets, std::max<int64_t>(N, 1)));
-    chk(alloc(&b->tier_off, 2 * 256 + 2));
-    chk(alloc(&b->tier_cur, 2 * 256 + 2));
-    chk(alloc(&b->tier_cnt, 2 * 256 + 2));
+    // batch partition of the batched form: up to 256 batches x 33 buckets (+ error counter)
+    chk(alloc(&b->tier_off, 256 * 33 + 2));
+    chk(alloc(&b->tier_cur, 256 * 33 + 2));
+    chk(alloc(&b->tier_cnt, 256 * 33 + 2));
     chk(upload(&b->caps, caps));
     chk(alloc(&b->D, b->E));
     chk(alloc(&b->cur_layer, M));

@@ -8,13 +8,16 @@
 // lowest look-ahead cost f'; ties keep the lowest b, then t, and a child's
 // lowest layer.
 //
-// Two evaluation orders give that same result:
+// Three evaluation orders give that same result:
 //  - hull candidates (via weight > 0, at most two children): a stack wider than
 //    the hull of l, the pin layer and the chosen child layers costs more than
 //    that hull with the same choices, so only hulls can win.  Each tuple of
 //    child layers names one hull; it is a candidate when every child's choice is
 //    its own key minimum (lowest layer on ties) inside that hull.  Valid tuples
 //    are collected in a bit mask first and only those are costed.
+//  - self-hull stacks (via weight > 0, three children): each child's keys are
+//    computed once; a stack is costed only when it equals the hull of l, the pin layer
+//    and the children's key minima inside it (any other stack loses to that hull).
 //  - the full enumeration otherwise: every stack, each child's minimum rescanned.
 //
 // Integer widths: la_build_batch bounds every net so that R < 2^31, C, S < 2^30 and
@@ -123,6 +126,9 @@ __device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb
     return s;
 }
 
+// children per node handled by the self-hull stack enumeration (more: full enumeration)
+constexpr int kHullKids = 3;
+
 struct ChildKey {
     int64_t key, V;
     int32_t Z;
@@ -170,6 +176,32 @@ __device__ __forceinline__ ChildKey child_key(const LayerTab &tb, const St &st, 
 __device__ __forceinline__ bool child_layer_ok(const LayerTab &tab, int cdir, int t)
 {
     return tab.jidx[t] >= 0 && tab.dir[t] == cdir;
+}
+
+// Bit jj is set when a child's layer ly[jj] (ascending in jj; n of them) is its lowest-layer
+// key minimum inside the hull of [lo, hi] and ly[jj]: no lower layer in that hull has a key
+// <= its key and no higher one a smaller key.  Two running minima, O(NAMAX).
+template <int NAMAX>
+__device__ __forceinline__ uint32_t hull_min_mask(const int64_t (&ky)[NAMAX], const int (&ly)[NAMAX], int n, int lo,
+                                                  int hi)
+{
+    bool low_ok[NAMAX];
+    int64_t pm = INT64_MAX;   // minimum over the lower layers at or above lo
+#pragma unroll
+    for (int jj = 0; jj < NAMAX; ++jj) {
+        low_ok[jj] = ly[jj] < lo || ky[jj] < pm;
+        if (jj < n && ly[jj] >= lo) pm = min(pm, ky[jj]);
+    }
+    uint32_t m = 0;
+    int64_t sm = INT64_MAX;   // minimum over the higher layers at or below hi
+#pragma unroll
+    for (int jj = NAMAX - 1; jj >= 0; --jj) {
+        if (jj < n) {
+            if (low_ok[jj] && (ly[jj] > hi || ky[jj] <= sm)) m |= 1u << jj;
+            if (ly[jj] <= hi) sm = min(sm, ky[jj]);
+        }
+    }
+    return m;
 }
 
 // Best candidate so far; `better` applies the (f', b, t) order of the full enumeration.
@@ -242,24 +274,49 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
         return false;
     };
 
-    if (a.w.w_via > 0 && k <= 2) {
-        // ---- hull candidates --------------------------------------------------------
+    if (a.w.w_via > 0 && k == 0) {
+        eval(lo, hi, 0, 0);
+    } else if (a.w.w_via > 0 && k == 1) {
+        // ---- one child: each of its layers names one hull ---------------------------------
+        const ChildIn c0 = child_in(st, s, 0);
+        const int n0 = tb.nA[c0.dir];
+        int64_t kv[NAMAX], ky[NAMAX];
+        int32_t kz[NAMAX];
+        int ly[NAMAX];
+#pragma unroll
+        for (int jj = 0; jj < NAMAX; ++jj) {
+            ly[jj] = tb.lay[c0.dir][jj < n0 ? jj : 0];
+            kv[jj] = ky[jj] = 0;
+            kz[jj] = 0;
+            if (jj < n0) {
+                const ChildKey ck = child_key(tb, st, wd, c0, l, ly[jj]);
+                kv[jj] = ck.V;
+                ky[jj] = ck.key;
+                kz[jj] = ck.Z;
+            }
+        }
+        const uint32_t m = hull_min_mask<NAMAX>(ky, ly, n0, lo, hi);
+#pragma unroll
+        for (int jj = 0; jj < NAMAX; ++jj)
+            if ((m >> jj) & 1u)
+                if (eval(min(lo, ly[jj]), max(hi, ly[jj]), kv[jj], kz[jj])) best_sel[0] = (uint8_t)ly[jj];
+        st.sel(c0.cs, j) = best_sel[0];
+    } else if (a.w.w_via > 0 && k == 2) {
+        // ---- two children: hull candidates ------------------------------------------------
         // keys of every child layer decide which tuples are candidates; the few valid
         // tuples then recompute their f-contributions (no run-time register indexing)
         int64_t kk[2][NAMAX];
         int ly[2][NAMAX];
-        int nc[2] = {0, 0};
+        int nc[2];
         ChildIn cin[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            if (q < k) {
-                cin[q] = child_in(st, s, q);
-                nc[q] = tb.nA[cin[q].dir];
+            cin[q] = child_in(st, s, q);
+            nc[q] = tb.nA[cin[q].dir];
 #pragma unroll
-                for (int jj = 0; jj < NAMAX; ++jj) {
-                    ly[q][jj] = tb.lay[cin[q].dir][jj < nc[q] ? jj : 0];
-                    kk[q][jj] = jj < nc[q] ? child_key(tb, st, wd, cin[q], l, ly[q][jj]).key : 0;
-                }
+            for (int jj = 0; jj < NAMAX; ++jj) {
+                ly[q][jj] = tb.lay[cin[q].dir][jj < nc[q] ? jj : 0];
+                kk[q][jj] = jj < nc[q] ? child_key(tb, st, wd, cin[q], l, ly[q][jj]).key : 0;
             }
         }
         // is index jq the lowest key minimum of child q over layers [b, t]?
@@ -274,48 +331,126 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
                     ok = false;
             return ok;
         };
-        if (k == 0) {
-            eval(lo, hi, 0, 0);
-        } else if (k == 1) {
-            uint32_t mask = 0;
+        // a choice that is its child's minimum in the pair's hull is also the minimum in its
+        // own (smaller) hull, so only pairs of single-child candidates are checked
+        const uint32_t m1 = hull_min_mask<NAMAX>(kk[0], ly[0], nc[0], lo, hi);
+        const uint32_t m2 = hull_min_mask<NAMAX>(kk[1], ly[1], nc[1], lo, hi);
+        uint64_t mask = 0;
 #pragma unroll
-            for (int j1 = 0; j1 < NAMAX; ++j1)
-                if (j1 < nc[0] && is_min(0, j1, min(lo, ly[0][j1]), max(hi, ly[0][j1]))) mask |= 1u << j1;
-            while (mask) {
-                const int j1 = __ffs(mask) - 1;
-                mask &= mask - 1;
-                const int L1 = tb.lay[cin[0].dir][j1];
-                const ChildKey c1 = child_key(tb, st, wd, cin[0], l, L1);
-                if (eval(min(lo, L1), max(hi, L1), c1.V, c1.Z)) best_sel[0] = (uint8_t)L1;
+        for (int j1 = 0; j1 < NAMAX; ++j1)
+#pragma unroll
+            for (int j2 = 0; j2 < NAMAX; ++j2)
+                if ((m1 >> j1) & (m2 >> j2) & 1u) {
+                    const int b = min(lo, min(ly[0][j1], ly[1][j2]));
+                    const int t = max(hi, max(ly[0][j1], ly[1][j2]));
+                    if (is_min(0, j1, b, t) && is_min(1, j2, b, t)) mask |= 1ull << (j1 * NAMAX + j2);
+                }
+        while (mask) {
+            const int p = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int j1 = p / NAMAX, j2 = p - (p / NAMAX) * NAMAX;
+            const int L1 = tb.lay[cin[0].dir][j1], L2 = tb.lay[cin[1].dir][j2];
+            const ChildKey c1 = child_key(tb, st, wd, cin[0], l, L1);
+            const ChildKey c2 = child_key(tb, st, wd, cin[1], l, L2);
+            if (eval(min(lo, min(L1, L2)), max(hi, max(L1, L2)), c1.V + c2.V, (int64_t)c1.Z + c2.Z)) {
+                best_sel[0] = (uint8_t)L1;
+                best_sel[1] = (uint8_t)L2;
             }
-        } else {
-            uint64_t mask = 0;
+        }
+        st.sel(cin[0].cs, j) = best_sel[0];
+        st.sel(cin[1].cs, j) = best_sel[1];
+    }
+    // ---- three children: self-hull stacks -------------------------------------------------
+    // Every child's keys are computed once, kept as 32-bit offsets from that child's
+    // smallest key (an item whose offsets do not fit takes the full enumeration).  A stack
+    // [b,t] is costed only when it is the hull of l, the pin layer and the children's key
+    // minima inside it; b and t must then be lo / hi or a child's routable layer.  Child q's
+    // layers are packed 4 bits each, its layer count in bits 28..31; its inputs are re-read
+    // from the state when a candidate is costed.
+    bool done = a.w.w_via > 0 && k <= 2;
+    if (a.w.w_via > 0 && k > 2 && k <= kHullKids) {
+        uint32_t dk[kHullKids][NAMAX];
+        uint32_t lyp[kHullKids];
+        uint32_t lmask = 0;
+        bool fits = true;
 #pragma unroll
-            for (int j1 = 0; j1 < NAMAX; ++j1)
+        for (int q = 0; q < kHullKids; ++q) {
+            lyp[q] = 0;
+            if (q < k) {
+                const ChildIn cq = child_in(st, s, q);
+                const int ncq = tb.nA[cq.dir];
+                lyp[q] = (uint32_t)ncq << 28;
+                int64_t ky[NAMAX];
+                int64_t base = INT64_MAX;
 #pragma unroll
-                for (int j2 = 0; j2 < NAMAX; ++j2)
-                    if (j1 < nc[0] && j2 < nc[1]) {
-                        const int b = min(lo, min(ly[0][j1], ly[1][j2]));
-                        const int t = max(hi, max(ly[0][j1], ly[1][j2]));
-                        if (is_min(0, j1, b, t) && is_min(1, j2, b, t)) mask |= 1ull << (j1 * NAMAX + j2);
+                for (int jj = 0; jj < NAMAX; ++jj) {
+                    const int lq = tb.lay[cq.dir][jj < ncq ? jj : 0];
+                    lyp[q] |= (uint32_t)lq << (4 * jj);
+                    ky[jj] = jj < ncq ? child_key(tb, st, wd, cq, l, lq).key : 0;
+                    if (jj < ncq) {
+                        lmask |= 1u << lq;
+                        base = min(base, ky[jj]);
                     }
-            while (mask) {
-                const int p = __ffsll((unsigned long long)mask) - 1;
-                mask &= mask - 1;
-                const int j1 = p / NAMAX, j2 = p - (p / NAMAX) * NAMAX;
-                const int L1 = tb.lay[cin[0].dir][j1], L2 = tb.lay[cin[1].dir][j2];
-                const ChildKey c1 = child_key(tb, st, wd, cin[0], l, L1);
-                const ChildKey c2 = child_key(tb, st, wd, cin[1], l, L2);
-                if (eval(min(lo, min(L1, L2)), max(hi, max(L1, L2)), c1.V + c2.V, (int64_t)c1.Z + c2.Z)) {
-                    best_sel[0] = (uint8_t)L1;
-                    best_sel[1] = (uint8_t)L2;
+                }
+#pragma unroll
+                for (int jj = 0; jj < NAMAX; ++jj) {
+                    const uint64_t d = (uint64_t)(ky[jj] - base);
+                    fits = fits && (jj >= ncq || d <= 0xffffffffull);
+                    dk[q][jj] = (uint32_t)d;
                 }
             }
         }
+        if (fits) {
+            uint8_t sel_q[kHullKids] = {};
+            for (int b = lo; b >= 0; --b) {
+                if (b != lo && !((lmask >> b) & 1u)) continue;
+                for (int t = hi; t < L; ++t) {
+                    if (t != hi && !((lmask >> t) & 1u)) continue;
+                    bool ok = true;
+                    int hb = lo, ht = hi;
+                    int chosen[kHullKids];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-            if (q < k) st.sel(st.ch_state(s, q), j) = best_sel[q];
-    } else {
+                    for (int q = 0; q < kHullKids; ++q) {
+                        chosen[q] = 0;
+                        if (q < k) {
+                            int bl = -1;
+                            uint32_t bk = 0;
+#pragma unroll
+                            for (int jj = 0; jj < NAMAX; ++jj) {
+                                const int lq = (int)((lyp[q] >> (4 * jj)) & 15u);
+                                if (jj < (int)(lyp[q] >> 28) && lq >= b && lq <= t && (bl < 0 || dk[q][jj] < bk)) {
+                                    bl = lq;
+                                    bk = dk[q][jj];
+                                }
+                            }
+                            ok = ok && bl >= 0;
+                            chosen[q] = bl;
+                            hb = min(hb, bl < 0 ? hb : bl);
+                            ht = max(ht, bl);
+                        }
+                    }
+                    if (!ok || hb != b || ht != t) continue;
+                    int64_t sumV = 0, sumZ = 0;
+#pragma unroll
+                    for (int q = 0; q < kHullKids; ++q)
+                        if (q < k) {
+                            const ChildKey c = child_key(tb, st, wd, child_in(st, s, q), l, chosen[q]);
+                            sumV += c.V;
+                            sumZ += c.Z;
+                        }
+                    if (eval(b, t, sumV, sumZ)) {
+#pragma unroll
+                        for (int q = 0; q < kHullKids; ++q) sel_q[q] = (uint8_t)chosen[q];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kHullKids; ++q)
+                if (q < k) st.sel(st.ch_state(s, q), j) = sel_q[q];
+            done = true;
+        }
+    }
+    if (!done) {
         // ---- full enumeration: every stack, each child rescanned ------------------------
         for (int b = 0; b <= lo; ++b)
             for (int t = hi; t < L; ++t) {
