@@ -127,7 +127,7 @@ __device__ __forceinline__ void block_scan(int32_t *x, int32_t n, int32_t *tmp)
 }
 
 template <int NAMAX>
-__global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPArgs a, BArgs ba)
+__global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
 {
     using TL = Tile<NAMAX>;
     extern __shared__ __align__(16) uint8_t smem[];

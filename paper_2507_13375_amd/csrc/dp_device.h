@@ -37,8 +37,8 @@ struct DPArgs {
     const uint8_t *caps;
     const int32_t *H;
     const uint8_t *prev;
-    int64_t *F;        // [node][NA] subtree cost f of the chosen candidate
-    int32_t *S;        // [node][NA] its downstream capacitance (aF)
+    int64_t *F;        // [node][NA] f' (cost with the node's look-ahead term) of the chosen candidate
+    int32_t *S;        // [node][NA] its X = C + 2S (aF, unsigned)
     uint8_t *bt;       // [node][NA][2] chosen via stack
     uint8_t *sel;      // [node][NA] node's layer for each entering-layer index of its parent
     int32_t NA;
@@ -129,11 +129,6 @@ __device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb
 // children per node handled by the self-hull stack enumeration (more: full enumeration)
 constexpr int kHullKids = 3;
 
-struct ChildKey {
-    int64_t key, V;
-    int32_t Z;
-};
-
 // Per-child inputs that do not depend on the parent's layer.
 struct ChildIn {
     int32_t cs;       // state index
@@ -155,21 +150,35 @@ __device__ __forceinline__ ChildIn child_in(const St &st, int32_t s, int q)
     return c;
 }
 
-// key = f + w_d T(w, Rvia(l, t), X) + look-ahead; V = the part that enters f; Z = C + S
+// The DP state of a (node, entering layer) keeps f' -- the subtree cost f plus the node's
+// look-ahead term (Sec. III-D) -- and X = C + 2S (segment capacitance plus twice the
+// downstream capacitance).  A parent entering on l ranks child layer t by
+// key = f' + w_d T(w, Rvia(l, t), X).
 template <class St>
-__device__ __forceinline__ ChildKey child_key(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
-                                              int t)
+__device__ __forceinline__ int64_t child_key(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
+                                             int t)
 {
     const int jc = tb.jidx[t];
-    const uint32_t Cc = (uint32_t)(tb.c[t] * c.len);
-    const uint32_t Sc = (uint32_t)st.S(c.cs, jc);
-    const uint32_t Z = Cc + Sc;
-    const int64_t tv = wd(Tq(c.w, rvia_d(tb, l, t), Cc + 2 * Sc));
-    const int64_t la = wd((int64_t)(mul_u32(c.lam, 2 * Z) >> 11));
-    ChildKey r;
-    r.V = st.F(c.cs, jc) + tv;
-    r.key = r.V + la;
-    r.Z = (int32_t)Z;
+    return st.F(c.cs, jc) + wd(Tq(c.w, rvia_d(tb, l, t), (uint32_t)st.S(c.cs, jc)));
+}
+
+// What a chosen child layer t contributes to its parent: V, the key without the child's
+// look-ahead term (it enters the parent's f), and Z = C + S, the capacitance it presents.
+struct ChildVZ {
+    int64_t V;
+    uint32_t Z;
+};
+
+template <class St>
+__device__ __forceinline__ ChildVZ child_vz(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
+                                           int t)
+{
+    const int jc = tb.jidx[t];
+    const uint32_t X = (uint32_t)st.S(c.cs, jc);
+    const uint32_t Z = (X + (uint32_t)(tb.c[t] * c.len)) >> 1;   // (C + 2S + C) / 2, exact
+    ChildVZ r;
+    r.V = st.F(c.cs, jc) - wd((int64_t)(mul_u32(c.lam, 2 * Z) >> 11)) + wd(Tq(c.w, rvia_d(tb, l, t), X));
+    r.Z = Z;
     return r;
 }
 
@@ -204,26 +213,40 @@ __device__ __forceinline__ uint32_t hull_min_mask(const int64_t (&ky)[NAMAX], co
     return m;
 }
 
+// For each layer index jj of a child: the highest lower layer whose key is <= its key and the
+// lowest higher layer whose key is smaller (-1 / 16 when there is none), packed 5 bits per
+// index as value + 1.  Layer jj is the child's lowest-layer key minimum inside a window
+// [b, t] that holds it exactly when lower < b and t < upper.
+template <int NAMAX>
+__device__ __forceinline__ void block_bounds(const int64_t (&ky)[NAMAX], const int (&ly)[NAMAX], int n,
+                                             uint64_t &lowp, uint64_t &upp)
+{
+    lowp = 0;
+    upp = 0;
+#pragma unroll
+    for (int jj = 0; jj < NAMAX; ++jj) {
+        int lb = -1, ub = 16;
+#pragma unroll
+        for (int i = 0; i < jj; ++i)
+            if (i < n && ky[i] <= ky[jj]) lb = ly[i];
+#pragma unroll
+        for (int i = NAMAX - 1; i > jj; --i)
+            if (i < n && ky[i] < ky[jj]) ub = ly[i];
+        lowp |= (uint64_t)(lb + 1) << (5 * jj);
+        upp |= (uint64_t)(ub + 1) << (5 * jj);
+    }
+}
+
 // Best candidate so far; `better` applies the (f', b, t) order of the full enumeration.
 struct Best {
-    int64_t fp = INT64_MAX, f = 0, S = 0;
+    int64_t fp = INT64_MAX;
+    uint32_t X = 0;
     int b = 0, t = 0;
     __device__ bool better(int64_t fp_, int b_, int t_) const
     {
         return fp_ < fp || (fp_ == fp && (b_ < b || (b_ == b && t_ < t)));
     }
 };
-
-// value of a register array at a run-time index, without indexing registers dynamically
-template <typename T, int N>
-__device__ __forceinline__ T pick(const T (&arr)[N], int i)
-{
-    T v = arr[0];
-#pragma unroll
-    for (int x = 1; x < N; ++x)
-        if (x == i) v = arr[x];
-    return v;
-}
 
 // DP of node state s for its entering layer l (index j in its direction list; j = 0 and
 // l = 0 at the root).  kap is kappa_n(l) (0 at the root).  NAMAX bounds the routable
@@ -253,20 +276,18 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
     const int k = st.nch(s);
 
     Best best;
-    uint8_t best_sel[2] = {0, 0};
-    // f and f' of stack [b,t] given the children's summed f-contributions and capacitances
+    // f' of stack [b,t] given the children's summed f-contributions and capacitances
     auto eval = [&](int b, int t, int64_t sumV, int64_t sumZ) -> bool {
         const uint32_t Sn = (uint32_t)(cpin + sumZ);
-        int64_t f = a.w.w_via * (t - b) + sumV + pin_term;
-        int64_t fp = f;
+        int64_t fp = a.w.w_via * (t - b) + sumV + pin_term;
+        uint32_t X = 2 * Sn;
         if (!root) {
-            f += own_const + wd(Tq(segw, Rw, Cs + 2 * Sn));
-            fp = f + wd((int64_t)(mul_u32(lam, 2 * (Cs + Sn)) >> 11));
+            X = Cs + 2 * Sn;
+            fp += own_const + wd(Tq(segw, Rw, X)) + wd((int64_t)(mul_u32(lam, 2 * (Cs + Sn)) >> 11));
         }
         if (best.better(fp, b, t)) {
             best.fp = fp;
-            best.f = f;
-            best.S = Sn;
+            best.X = X;
             best.b = b;
             best.t = t;
             return true;
@@ -274,103 +295,93 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
         return false;
     };
 
+    bool done = false;
     if (a.w.w_via > 0 && k == 0) {
         eval(lo, hi, 0, 0);
+        done = true;
     } else if (a.w.w_via > 0 && k == 1) {
         // ---- one child: each of its layers names one hull ---------------------------------
         const ChildIn c0 = child_in(st, s, 0);
         const int n0 = tb.nA[c0.dir];
-        int64_t kv[NAMAX], ky[NAMAX];
-        int32_t kz[NAMAX];
+        int64_t ky[NAMAX];
         int ly[NAMAX];
 #pragma unroll
         for (int jj = 0; jj < NAMAX; ++jj) {
             ly[jj] = tb.lay[c0.dir][jj < n0 ? jj : 0];
-            kv[jj] = ky[jj] = 0;
-            kz[jj] = 0;
-            if (jj < n0) {
-                const ChildKey ck = child_key(tb, st, wd, c0, l, ly[jj]);
-                kv[jj] = ck.V;
-                ky[jj] = ck.key;
-                kz[jj] = ck.Z;
-            }
+            ky[jj] = jj < n0 ? child_key(tb, st, wd, c0, l, ly[jj]) : 0;
         }
-        const uint32_t m = hull_min_mask<NAMAX>(ky, ly, n0, lo, hi);
-#pragma unroll
-        for (int jj = 0; jj < NAMAX; ++jj)
-            if ((m >> jj) & 1u)
-                if (eval(min(lo, ly[jj]), max(hi, ly[jj]), kv[jj], kz[jj])) best_sel[0] = (uint8_t)ly[jj];
-        st.sel(c0.cs, j) = best_sel[0];
+        uint32_t m = hull_min_mask<NAMAX>(ky, ly, n0, lo, hi);
+        int sel0 = 0;
+        while (m) {
+            const int jj = __ffs(m) - 1;
+            m &= m - 1;
+            const int L1 = tb.lay[c0.dir][jj];
+            const ChildVZ v = child_vz(tb, st, wd, c0, l, L1);
+            if (eval(min(lo, L1), max(hi, L1), v.V, v.Z)) sel0 = L1;
+        }
+        st.sel(c0.cs, j) = (uint8_t)sel0;
+        done = true;
     } else if (a.w.w_via > 0 && k == 2) {
         // ---- two children: hull candidates ------------------------------------------------
-        // keys of every child layer decide which tuples are candidates; the few valid
-        // tuples then recompute their f-contributions (no run-time register indexing)
-        int64_t kk[2][NAMAX];
-        int ly[2][NAMAX];
-        int nc[2];
+        // a pair of child layers names one hull; it is a candidate when each choice is its
+        // child's key minimum inside that hull (block bounds make that test O(1))
+        // packs: child q's layers 4 bits each with its layer count at bit 32; bounds 5 bits each
         ChildIn cin[2];
+        uint64_t lyp[2], lowp[2], upp[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             cin[q] = child_in(st, s, q);
-            nc[q] = tb.nA[cin[q].dir];
+            const int nq = tb.nA[cin[q].dir];
+            int64_t ky[NAMAX];
+            int ly[NAMAX];
+            lyp[q] = (uint64_t)nq << 32;
 #pragma unroll
             for (int jj = 0; jj < NAMAX; ++jj) {
-                ly[q][jj] = tb.lay[cin[q].dir][jj < nc[q] ? jj : 0];
-                kk[q][jj] = jj < nc[q] ? child_key(tb, st, wd, cin[q], l, ly[q][jj]).key : 0;
+                ly[jj] = tb.lay[cin[q].dir][jj < nq ? jj : 0];
+                ky[jj] = jj < nq ? child_key(tb, st, wd, cin[q], l, ly[jj]) : 0;
+                lyp[q] |= (uint64_t)ly[jj] << (4 * jj);
             }
+            block_bounds<NAMAX>(ky, ly, nq, lowp[q], upp[q]);
         }
-        // is index jq the lowest key minimum of child q over layers [b, t]?
-        // (q and jq are compile-time after unrolling, so every index stays in registers)
-        auto is_min = [&](int q, int jq, int b, int t) -> bool {
-            bool ok = true;
-            const int64_t mine = kk[q][jq];
-#pragma unroll
-            for (int jj = 0; jj < NAMAX; ++jj)
-                if (jj < nc[q] && jj != jq && ly[q][jj] >= b && ly[q][jj] <= t &&
-                    (kk[q][jj] < mine || (kk[q][jj] == mine && jj < jq)))
-                    ok = false;
-            return ok;
-        };
-        // a choice that is its child's minimum in the pair's hull is also the minimum in its
-        // own (smaller) hull, so only pairs of single-child candidates are checked
-        const uint32_t m1 = hull_min_mask<NAMAX>(kk[0], ly[0], nc[0], lo, hi);
-        const uint32_t m2 = hull_min_mask<NAMAX>(kk[1], ly[1], nc[1], lo, hi);
+        auto fld = [](uint64_t p, int jj, int w) { return (int)((p >> (w * jj)) & ((1u << w) - 1u)); };
         uint64_t mask = 0;
 #pragma unroll
         for (int j1 = 0; j1 < NAMAX; ++j1)
 #pragma unroll
             for (int j2 = 0; j2 < NAMAX; ++j2)
-                if ((m1 >> j1) & (m2 >> j2) & 1u) {
-                    const int b = min(lo, min(ly[0][j1], ly[1][j2]));
-                    const int t = max(hi, max(ly[0][j1], ly[1][j2]));
-                    if (is_min(0, j1, b, t) && is_min(1, j2, b, t)) mask |= 1ull << (j1 * NAMAX + j2);
+                if (j1 < (int)(lyp[0] >> 32) && j2 < (int)(lyp[1] >> 32)) {
+                    const int L1 = fld(lyp[0], j1, 4), L2 = fld(lyp[1], j2, 4);
+                    const int b = min(lo, min(L1, L2)), t = max(hi, max(L1, L2));
+                    // stored bounds are value + 1: lower + 1 <= b and t + 1 < upper + 1
+                    if (fld(lowp[0], j1, 5) <= b && fld(lowp[1], j2, 5) <= b && t + 1 < fld(upp[0], j1, 5) &&
+                        t + 1 < fld(upp[1], j2, 5))
+                        mask |= 1ull << (j1 * NAMAX + j2);
                 }
+        int sel0 = 0, sel1 = 0;
         while (mask) {
             const int p = __ffsll((unsigned long long)mask) - 1;
             mask &= mask - 1;
             const int j1 = p / NAMAX, j2 = p - (p / NAMAX) * NAMAX;
             const int L1 = tb.lay[cin[0].dir][j1], L2 = tb.lay[cin[1].dir][j2];
-            const ChildKey c1 = child_key(tb, st, wd, cin[0], l, L1);
-            const ChildKey c2 = child_key(tb, st, wd, cin[1], l, L2);
+            const ChildVZ c1 = child_vz(tb, st, wd, cin[0], l, L1);
+            const ChildVZ c2 = child_vz(tb, st, wd, cin[1], l, L2);
             if (eval(min(lo, min(L1, L2)), max(hi, max(L1, L2)), c1.V + c2.V, (int64_t)c1.Z + c2.Z)) {
-                best_sel[0] = (uint8_t)L1;
-                best_sel[1] = (uint8_t)L2;
+                sel0 = L1;
+                sel1 = L2;
             }
         }
-        st.sel(cin[0].cs, j) = best_sel[0];
-        st.sel(cin[1].cs, j) = best_sel[1];
-    }
-    // ---- three children: self-hull stacks -------------------------------------------------
-    // Every child's keys are computed once, kept as 32-bit offsets from that child's
-    // smallest key (an item whose offsets do not fit takes the full enumeration).  A stack
-    // [b,t] is costed only when it is the hull of l, the pin layer and the children's key
-    // minima inside it; b and t must then be lo / hi or a child's routable layer.  Child q's
-    // layers are packed 4 bits each, its layer count in bits 28..31; its inputs are re-read
-    // from the state when a candidate is costed.
-    bool done = a.w.w_via > 0 && k <= 2;
-    if (a.w.w_via > 0 && k > 2 && k <= kHullKids) {
+        st.sel(cin[0].cs, j) = (uint8_t)sel0;
+        st.sel(cin[1].cs, j) = (uint8_t)sel1;
+        done = true;
+    } else if (a.w.w_via > 0 && k <= kHullKids) {
+        // ---- three children: self-hull stacks ---------------------------------------------
+        // Every child's keys are computed once, kept as 32-bit offsets from that child's
+        // smallest key (an item whose offsets do not fit takes the full enumeration).  A
+        // stack [b,t] is costed only when it is the hull of l, the pin layer and the
+        // children's key minima inside it; b and t must then be lo / hi or a child's routable
+        // layer.  Child q's layers are packed 4 bits each, its layer count at bit 32.
         uint32_t dk[kHullKids][NAMAX];
-        uint32_t lyp[kHullKids];
+        uint64_t lyp[kHullKids];
         uint32_t lmask = 0;
         bool fits = true;
 #pragma unroll
@@ -379,14 +390,14 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
             if (q < k) {
                 const ChildIn cq = child_in(st, s, q);
                 const int ncq = tb.nA[cq.dir];
-                lyp[q] = (uint32_t)ncq << 28;
+                lyp[q] = (uint64_t)ncq << 32;
                 int64_t ky[NAMAX];
                 int64_t base = INT64_MAX;
 #pragma unroll
                 for (int jj = 0; jj < NAMAX; ++jj) {
                     const int lq = tb.lay[cq.dir][jj < ncq ? jj : 0];
-                    lyp[q] |= (uint32_t)lq << (4 * jj);
-                    ky[jj] = jj < ncq ? child_key(tb, st, wd, cq, l, lq).key : 0;
+                    lyp[q] |= (uint64_t)lq << (4 * jj);
+                    ky[jj] = jj < ncq ? child_key(tb, st, wd, cq, l, lq) : 0;
                     if (jj < ncq) {
                         lmask |= 1u << lq;
                         base = min(base, ky[jj]);
@@ -418,7 +429,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 #pragma unroll
                             for (int jj = 0; jj < NAMAX; ++jj) {
                                 const int lq = (int)((lyp[q] >> (4 * jj)) & 15u);
-                                if (jj < (int)(lyp[q] >> 28) && lq >= b && lq <= t && (bl < 0 || dk[q][jj] < bk)) {
+                                if (jj < (int)(lyp[q] >> 32) && lq >= b && lq <= t && (bl < 0 || dk[q][jj] < bk)) {
                                     bl = lq;
                                     bk = dk[q][jj];
                                 }
@@ -434,7 +445,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 #pragma unroll
                     for (int q = 0; q < kHullKids; ++q)
                         if (q < k) {
-                            const ChildKey c = child_key(tb, st, wd, child_in(st, s, q), l, chosen[q]);
+                            const ChildVZ c = child_vz(tb, st, wd, child_in(st, s, q), l, chosen[q]);
                             sumV += c.V;
                             sumZ += c.Z;
                         }
@@ -458,34 +469,37 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
                 int64_t sumV = 0, sumZ = 0;
                 for (int q = 0; q < k && ok; ++q) {
                     const ChildIn c = child_in(st, s, q);
-                    bool have = false;
-                    ChildKey bestc{0, 0, 0};
+                    int bl = -1;
+                    int64_t bk = 0;
                     for (int lc = b; lc <= t; ++lc) {
                         if (!child_layer_ok(tb, c.dir, lc)) continue;
-                        const ChildKey ck = child_key(tb, st, wd, c, l, lc);
-                        if (!have || ck.key < bestc.key) {
-                            have = true;
-                            bestc = ck;
+                        const int64_t key = child_key(tb, st, wd, c, l, lc);
+                        if (bl < 0 || key < bk) {
+                            bl = lc;
+                            bk = key;
                         }
                     }
-                    ok = have;
-                    sumV += bestc.V;
-                    sumZ += bestc.Z;
+                    ok = bl >= 0;
+                    if (ok) {
+                        const ChildVZ v = child_vz(tb, st, wd, c, l, bl);
+                        sumV += v.V;
+                        sumZ += v.Z;
+                    }
                 }
                 if (ok) eval(b, t, sumV, sumZ);
             }
         // each child's layer at the chosen stack, by the same rule
         for (int q = 0; q < k; ++q) {
             const ChildIn c = child_in(st, s, q);
+            int bl = 0;
             bool have = false;
             int64_t bk = 0;
-            int bl = 0;
             for (int lc = best.b; lc <= best.t; ++lc) {
                 if (!child_layer_ok(tb, c.dir, lc)) continue;
-                const ChildKey ck = child_key(tb, st, wd, c, l, lc);
-                if (!have || ck.key < bk) {
+                const int64_t key = child_key(tb, st, wd, c, l, lc);
+                if (!have || key < bk) {
                     have = true;
-                    bk = ck.key;
+                    bk = key;
                     bl = lc;
                 }
             }
@@ -493,8 +507,8 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
         }
     }
 
-    st.F(s, j) = best.f;
-    st.S(s, j) = (int32_t)best.S;
+    st.F(s, j) = best.fp;
+    st.S(s, j) = (int32_t)best.X;
     uint8_t *bt = st.bt(s, j);
     bt[0] = (uint8_t)best.b;
     bt[1] = (uint8_t)best.t;
