@@ -26,7 +26,7 @@ la_status history_update(la_batch *b, int32_t *H, int32_t inc);
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBook = 320;   // ints of per-claim bookkeeping
+constexpr int kBook = 9 * kClaimNets + 8;   // ints of per-claim bookkeeping
 constexpr int kHB = 32;      // height classes of small nets per batch
 constexpr int kNB = 1 + kHB; // partition buckets per batch
 
@@ -91,6 +91,8 @@ struct BArgs {
     const int32_t *tier_off;    // [2*T+1]: bucket starts; batch t spans [off[2t], off[2t+2])
     int32_t tier;
     int32_t *ctr;               // work-queue counter of this (round, batch)
+    const int32_t *cl_start;    // claim starts (positions in tier_nets); batch t's claims from cl_off[t]
+    const int32_t *cl_off;
     const int32_t *height;
     const int32_t *net_big, *bn_order, *bn_lvl, *bn_lvl_off, *bn_nlev;
     uint8_t *cur, *vlo, *vhi, *out_layers;
@@ -158,30 +160,34 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
     uint8_t *prv = smem + TL::PRV;
     int32_t *lut = (int32_t *)(smem + TL::LUT);
 
-    // bookkeeping: [0] claim base, [1] #tiles, [2] max height of the tile; per tile: first
+    // bookkeeping: [0] claim index, [1] #tiles, [2] max height of the tile; per tile: first
     // and end claim index, node count; per claimed net: node count, first global node,
     // first global child entry, tile-local node base and child base
+    constexpr int Q = kClaimNets;
     int32_t *s_base = book, *s_nsub = book + 1, *s_maxlev = book + 2;
-    int32_t *s_sub0 = book + 32, *s_sub1 = book + 64, *s_tn = book + 96;
-    int32_t *s_nn = book + 128, *s_g0 = book + 160, *s_c0 = book + 192, *s_lb = book + 224, *s_cb = book + 256;
-    static_assert(kClaim <= 32 && kBook >= 288, "bookkeeping layout");
+    int32_t *s_sub0 = book + 8, *s_sub1 = book + 8 + Q, *s_tn = book + 8 + 2 * Q;
+    int32_t *s_nn = book + 8 + 3 * Q, *s_g0 = book + 8 + 4 * Q, *s_c0 = book + 8 + 5 * Q;
+    int32_t *s_lb = book + 8 + 6 * Q, *s_cb = book + 8 + 7 * Q;
+    static_assert(kBook >= 8 + 8 * kClaimNets && kClaimNets <= kThreads, "bookkeeping layout");
+    static_assert(kClaimUnits / (1 + kNetUnits) + 1 <= kClaimNets, "nets per claim");
 
     const int L = tb.L;
     for (int i = threadIdx.x; i < L * 2 * kNDelta; i += blockDim.x) lut[i] = a.w.lut[i];
 
     LdsState<NAMAX> st{F, S, bt, sel, chp, chl, lenp, lam, cpin, segw, pinw, fld};
-    // the batch's small nets (its big nets run in k_batched_big)
-    const int32_t off0 = ba.tier_off[ba.tier * kNB + 1], cnt = ba.tier_off[(ba.tier + 1) * kNB] - off0;
+    // the batch's claims of small nets (its big nets run in k_batched_big)
+    const int32_t coff = ba.cl_off[ba.tier], ncl = ba.cl_off[ba.tier + 1] - coff - 1;
     const int32_t Xl = tb.X * L;
 
     for (;;) {
-        if (threadIdx.x == 0) *s_base = atomicAdd(ba.ctr, kClaim);
+        if (threadIdx.x == 0) *s_base = atomicAdd(ba.ctr, 1);
         __syncthreads();
-        const int32_t base = *s_base;
-        if (base >= cnt) break;
-        const int32_t nclaim = min(kClaim, cnt - base);
+        const int32_t c = *s_base;
+        if (c >= ncl) break;
+        // at most kClaimNets by construction (each net counts >= 1 + kNetUnits units)
+        const int32_t p0 = ba.cl_start[coff + c], nclaim = min(ba.cl_start[coff + c + 1] - p0, kClaimNets);
         if (threadIdx.x < nclaim) {
-            const int32_t net = ba.tier_nets[off0 + base + threadIdx.x];
+            const int32_t net = ba.tier_nets[p0 + threadIdx.x];
             const int32_t g0 = a.T.net_ptr[net];
             s_nn[threadIdx.x] = a.T.net_ptr[net + 1] - g0;
             s_g0[threadIdx.x] = g0;
@@ -189,7 +195,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            // split the claimed nets (each of at most kCap nodes) into tiles of at most kCap
+            // split the claimed nets (each of at most kCap nodes) into tiles of at most kCap;
+            // a claim can be empty (a net longer than one claim's units spans several)
             int32_t ns = 0, nodes = 0, kids = 0;
             for (int32_t i = 0; i < nclaim; ++i) {
                 const int32_t n = s_nn[i];
@@ -207,8 +214,10 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                 nodes += n;
                 kids += n - 1;
             }
-            s_sub1[ns - 1] = nclaim;
-            s_tn[ns - 1] = nodes;
+            if (ns > 0) {
+                s_sub1[ns - 1] = nclaim;
+                s_tn[ns - 1] = nodes;
+            }
             *s_nsub = ns;
         }
         __syncthreads();
@@ -478,6 +487,79 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
     }
 }
 
+// ---- claims: slices of each batch's sorted small nets by units (nodes + kNetUnits) -------
+// pre[0] = 0, pre[i + 1] = units of the net at sorted position i
+__global__ void k_claim_units(const int32_t *tier_nets, int64_t nets, const int32_t *net_ptr, int32_t *pre)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t net = tier_nets[i];
+        pre[i + 1] = net_ptr[net + 1] - net_ptr[net] + kNetUnits;
+        if (i == 0) pre[0] = 0;
+    }
+}
+
+// inclusive scan of each 1024-element chunk in place; the chunk's total to blk[chunk]
+__global__ void k_scan_chunks(int32_t *x, int64_t n, int32_t *blk)
+{
+    __shared__ int32_t tmp[1024 / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * 1024;
+    const int32_t m = (int32_t)std::min<int64_t>(1024, n - c0);
+    block_scan(x + c0, m, tmp);
+    if (threadIdx.x == 0) blk[blockIdx.x] = x[c0 + m - 1];
+}
+
+// inclusive scan of the chunk totals (one workgroup)
+__global__ void k_scan_totals(int32_t *blk, int32_t nblk)
+{
+    __shared__ int32_t tmp[1024 / 64];
+    block_scan(blk, nblk, tmp);
+}
+
+__global__ void k_scan_add(int32_t *x, int64_t n, const int32_t *blk)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t chunk = i / 1024;
+        if (chunk > 0) x[i] += blk[chunk - 1];
+    }
+}
+
+// batch t gets n_t = ceil(units / kClaimUnits) claims and one end slot, from cl_off[t]
+__global__ void k_claim_offsets(const int32_t *tier_off, int32_t ntier, const int32_t *pre, int32_t *cl_off)
+{
+    __shared__ int32_t tmp[1024 / 64];
+    for (int t = threadIdx.x; t < ntier; t += blockDim.x) {
+        const int32_t s0 = tier_off[t * kNB + 1], s1 = tier_off[(t + 1) * kNB];
+        cl_off[t + 1] = s1 > s0 ? (pre[s1] - pre[s0] + kClaimUnits - 1) / kClaimUnits + 1 : 0;
+    }
+    if (threadIdx.x == 0) cl_off[0] = 0;
+    __syncthreads();
+    block_scan(cl_off + 1, ntier, tmp);
+}
+
+// claim c of batch t holds the small nets whose unit prefix, counted from the batch's first
+// small net, lies in [c, c + 1) * kClaimUnits; slot n_t holds the batch's end
+__global__ void k_claim_starts(const int32_t *tier_off, int32_t ntier, int64_t nets, const int32_t *pre,
+                               const int32_t *cl_off, int32_t *cl_start)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = ntier;   // batch of position i: tier_off[t*kNB] <= i < tier_off[(t+1)*kNB]
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (tier_off[mid * kNB] <= i) lo = mid;
+            else hi = mid;
+        }
+        const int32_t t = lo;
+        const int32_t s0 = tier_off[t * kNB + 1], s1 = tier_off[(t + 1) * kNB];
+        if (i < s0 || i >= s1) continue;   // a big net (its own kernel)
+        const int32_t base = cl_off[t], nt = cl_off[t + 1] - base - 1;
+        const int32_t c = (pre[i] - pre[s0]) / kClaimUnits;
+        const int32_t cp = i == s0 ? -1 : (pre[i - 1] - pre[s0]) / kClaimUnits;
+        for (int32_t q = cp + 1; q <= c; ++q) cl_start[base + q] = (int32_t)i;
+        if (i == s1 - 1)
+            for (int32_t q = c + 1; q <= nt; ++q) cl_start[base + q] = s1;
+    }
+}
+
 __global__ void k_zero_counts(int32_t *p, int32_t n)
 {
     for (int32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
@@ -543,6 +625,8 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             ba.tier_off = b->tier_off;
             ba.tier = t;
             ba.ctr = b->claim + r * ntier + t;
+            ba.cl_start = b->cl_start;
+            ba.cl_off = b->cl_off;
             ba.height = b->height;
             ba.net_big = b->net_big;
             ba.bn_order = b->bn_order;
@@ -597,6 +681,20 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     LA_TIMED(b, "k_tier_scatter", b->stream,
              hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
                                 b->nets, b->net_big, b->net_ptr, b->height, b->tier_cur, b->tier_nets));
+    // work-queue claims of each batch's small nets
+    {
+        const int64_t n = b->nets + 1;
+        const int32_t nchunk = (int32_t)((n + 1023) / 1024);
+        hipLaunchKernelGGL(k_claim_units, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, b->tier_nets, b->nets,
+                           b->net_ptr, b->cl_pre);
+        hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(256), 0, b->stream, b->cl_pre, n, b->cl_blk);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, b->stream, b->cl_blk, nchunk);
+        hipLaunchKernelGGL(k_scan_add, dim3(grid1d(n)), dim3(256), 0, b->stream, b->cl_pre, n, b->cl_blk);
+        hipLaunchKernelGGL(k_claim_offsets, dim3(1), dim3(256), 0, b->stream, b->tier_off, ntier, b->cl_pre,
+                           b->cl_off);
+        hipLaunchKernelGGL(k_claim_starts, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, b->tier_off, ntier,
+                           b->nets, b->cl_pre, b->cl_off, b->cl_start);
+    }
     LA_HIP(hipGetLastError());
     std::vector<int32_t> cnt(nb + 1);
     LA_HIP(hipMemcpyAsync(cnt.data(), b->tier_cnt, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));

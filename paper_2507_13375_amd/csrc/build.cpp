@@ -454,6 +454,12 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(alloc(&b->tier_off, 256 * 33 + 2));
     chk(alloc(&b->tier_cur, 256 * 33 + 2));
     chk(alloc(&b->tier_cnt, 256 * 33 + 2));
+    // claims: every claim but the last of a batch covers kClaimUnits units
+    chk(alloc(&b->cl_pre, (size_t)N + 1));
+    chk(alloc(&b->cl_blk, (size_t)N / 1024 + 2));
+    b->cl_start_cap = (M + (int64_t)kNetUnits * N) / kClaimUnits + 2 * 256 + 2;
+    chk(alloc(&b->cl_start, (size_t)b->cl_start_cap));
+    chk(alloc(&b->cl_off, 256 + 2));
     chk(upload(&b->caps, caps));
     chk(alloc(&b->D, b->E));
     chk(alloc(&b->cur_layer, M));

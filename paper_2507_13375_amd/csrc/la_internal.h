@@ -13,7 +13,9 @@ namespace gapla {
 
 constexpr int kMaxL = 16;          // layers supported (4-bit layer ids)
 constexpr int kCap = 224;          // nodes of one batched-form workgroup's LDS tile
-constexpr int kClaim = 32;         // nets claimed per work-queue grab
+constexpr int kClaimUnits = 220;   // work-queue claim size: sum over its nets of (nodes + kNetUnits)
+constexpr int kNetUnits = 3;
+constexpr int kClaimNets = 64;     // bound on the nets of one claim (kClaimUnits / (1 + kNetUnits) + 1)
 constexpr int kMaxA = 8;           // routable layers per direction
 constexpr int kNDelta = 64;        // congestion table entries per (layer, zero-capacity flag)
 constexpr int kDeltaMin = -32;
@@ -119,6 +121,11 @@ struct la_batch {
     int32_t *tier_nets = nullptr, *tier_off = nullptr, *tier_cur = nullptr, *tier_cnt = nullptr;
     int32_t *claim = nullptr;
     int32_t claim_cap = 0;
+    // claims of the batched work queue: prefix of (nodes + kNetUnits) over the batch-sorted nets,
+    // per-block partial sums of that scan, claim starts (positions in tier_nets) and per-batch
+    // claim offsets
+    int32_t *cl_pre = nullptr, *cl_blk = nullptr, *cl_start = nullptr, *cl_off = nullptr;
+    int64_t cl_start_cap = 0;
     int32_t grid_batched = 0;       // persistent workgroups per batched launch
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
