@@ -225,11 +225,11 @@ DPArgs make_dp_args(la_batch *b, const la_weights *w, const int32_t *H, const in
     return a;
 }
 
-la_status commit_changed(la_batch *b)
+la_status commit_changed(la_batch *b, int32_t *D)
 {
     LA_TIMED(b, "k_commit", b->stream,
              hipLaunchKernelGGL(k_commit, dim3(1024), dim3(kBlock), 0, b->stream, tree_view(b), b->tab, b->chg_node,
-                                b->chg_old, b->chg_new, b->chg_count, b->D));
+                                b->chg_old, b->chg_new, b->chg_count, D));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }
@@ -241,10 +241,10 @@ la_status zero_i32(la_batch *b, int32_t *p, int64_t n)
     return LA_OK;
 }
 
-la_status history_update(la_batch *b, int32_t *H, int32_t inc)
+la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t inc)
 {
     LA_TIMED(b, "k_history", b->stream,
-             hipLaunchKernelGGL(k_history, dim3(grid_for(b->E)), dim3(kBlock), 0, b->stream, b->D, b->caps, H, b->E,
+             hipLaunchKernelGGL(k_history, dim3(grid_for(b->E)), dim3(kBlock), 0, b->stream, D, b->caps, H, b->E,
                                 inc));
     LA_HIP(hipGetLastError());
     return LA_OK;
@@ -338,10 +338,10 @@ la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32
                                             out_layers, b->has_prev ? 1 : 0, b->chg_node, b->chg_old, b->chg_new,
                                             b->chg_count));
             }
-            s = commit_changed(b);
+            s = commit_changed(b, b->D);
             if (s != LA_OK) return s;
         }
-        s = history_update(b, H, w->hist_inc);
+        s = history_update(b, b->D, H, w->hist_inc);
         if (s != LA_OK) return s;
         b->has_prev = true;
     }

@@ -20,8 +20,8 @@
 namespace gapla {
 
 DPArgs make_dp_args(la_batch *b, const la_weights *w, const int32_t *H, const int32_t *lut);
-la_status commit_changed(la_batch *b);
-la_status history_update(la_batch *b, int32_t *H, int32_t inc);
+la_status commit_changed(la_batch *b, int32_t *D);
+la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t inc);
 
 namespace {
 
@@ -29,6 +29,7 @@ constexpr int kThreads = 256;
 constexpr int kBook = 9 * kClaimNets + 8;   // ints of per-claim bookkeeping
 constexpr int kHB = 32;      // height classes of small nets per batch
 constexpr int kNB = 1 + kHB; // partition buckets per batch
+constexpr int32_t kFuseNets = 16384;   // batches with this many small nets commit from their DP kernel
 
 // DP state and per-node inputs of one LDS tile, indexed by tile-local node id.
 template <int NAMAX>
@@ -98,6 +99,7 @@ struct BArgs {
     uint8_t *cur, *vlo, *vhi, *out_layers;
     int has_prev;
     ChangeList cl;
+    int32_t *Dw;                // demand moves of the small nets go straight here; NULL: to cl
 };
 
 // In-place inclusive prefix sum of x[0, n) by the whole workgroup (wave scans, then the
@@ -331,15 +333,29 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                     uint8_t old_l = 0;
                     int ln = 0;
                     int32_t n = 0;
+                    int32_t u = 0;
                     if (it < le) {
-                        const int32_t u = order[it];
+                        u = order[it];
                         n = gid[u];
                         const int32_t pu = par[u];
                         const int jp = (pu < 0 || par[pu] < 0) ? 0 : ent[pu];
                         ent[u] = (uint8_t)trace_node(tb, st, u, n, jp, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers,
                                                      ba.has_prev, &ln, &changed, &old_l);
                     }
-                    append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
+                    if (ba.Dw) {
+                        // commit the move along the segment's GCell edges (the DP of this batch
+                        // reads the other demand buffer)
+                        if (changed) {
+                            const int32_t step = (fld[u] >> 4) == 0 ? L : Xl;
+                            int32_t g = g0a[u];
+                            for (int32_t k = lenp[u + 1] - lenp[u]; k > 0; --k, g += step) {
+                                if (old_l != 255) atomicAdd(&ba.Dw[g + old_l], -1);
+                                atomicAdd(&ba.Dw[g + ln], 1);
+                            }
+                        }
+                    } else {
+                        append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
+                    }
                 }
                 __syncthreads();
             }
@@ -560,6 +576,16 @@ __global__ void k_claim_starts(const int32_t *tier_off, int32_t ntier, int64_t n
     }
 }
 
+// dst = src over n ints, 16 bytes per access (both arrays 256-byte aligned)
+__global__ void k_copy_i32(int32_t *__restrict__ dst, const int32_t *__restrict__ src, int64_t n)
+{
+    const int64_t n4 = n / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += stride)
+        ((int4 *)dst)[i] = ((const int4 *)src)[i];
+    for (int64_t i = 4 * n4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_zero_counts(int32_t *p, int32_t n)
 {
     for (int32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
@@ -603,7 +629,9 @@ int32_t small_nets(const std::vector<int32_t> &cnt, int32_t t)
 }
 
 // R rounds over the batches onto stream s: per batch the persistent DP kernels and the
-// commit of the changed segments, then the history update of the round.
+// commit of the changed segments, then the history update of the round.  A batch with many
+// small nets commits them from its DP kernel into a copy of the demand map (its DP reads the
+// map as it was before the batch); the copy then becomes the current map.
 la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
                          const std::vector<int32_t> &cnt, hipStream_t s)
 {
@@ -613,12 +641,19 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
     bool has_prev = b->has_prev;
     const hipStream_t keep = b->stream;
     b->stream = s;   // commit_changed and history_update launch on the batch's stream
+    int32_t *dcur = b->D, *dalt = b->D_alt;
+    const int cgrid = (int)std::min<int64_t>(4096, (b->E / 4 + 255) / 256 + 1);
     for (int32_t r = 0; r < R && st == LA_OK; ++r) {
         DPArgs a = make_dp_args(b, w, H, lut);
         a.w.self_excl = has_prev ? 1 : 0;
         for (int32_t t = 0; t < ntier && st == LA_OK; ++t) {
             const int32_t nbig = cnt[t * kNB], nsmall = small_nets(cnt, t);
             if (nbig + nsmall == 0) continue;
+            const bool fused = nsmall >= kFuseNets;
+            a.D = dcur;
+            if (fused)
+                LA_TIMED(b, "k_copy_i32", s,
+                         hipLaunchKernelGGL(k_copy_i32, dim3(cgrid), dim3(256), 0, s, dalt, dcur, b->E));
             hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, b->chg_count, 1);
             BArgs ba;
             ba.tier_nets = b->tier_nets;
@@ -639,15 +674,20 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             ba.out_layers = out_layers;
             ba.has_prev = has_prev ? 1 : 0;
             ba.cl = ChangeList{b->chg_node, b->chg_old, b->chg_new, b->chg_count};
+            ba.Dw = fused ? dalt : nullptr;
             const int NA = b->NAmax;
             st = NA <= 4   ? launch_batched<4>(b, a, ba, nbig, nsmall, s)
                  : NA <= 6 ? launch_batched<6>(b, a, ba, nbig, nsmall, s)
                            : launch_batched<8>(b, a, ba, nbig, nsmall, s);
-            if (st == LA_OK) st = commit_changed(b);
+            // the change list holds the big nets' moves (and, unfused, the small nets')
+            if (st == LA_OK) st = commit_changed(b, fused ? dalt : dcur);
+            if (fused) std::swap(dcur, dalt);
         }
-        if (st == LA_OK) st = history_update(b, H, w->hist_inc);
+        if (st == LA_OK) st = history_update(b, dcur, H, w->hist_inc);
         has_prev = true;
     }
+    if (st == LA_OK && dcur != b->D)
+        LA_TIMED(b, "k_copy_i32", s, hipLaunchKernelGGL(k_copy_i32, dim3(cgrid), dim3(256), 0, s, b->D, dcur, b->E));
     b->stream = keep;
     return st;
 }

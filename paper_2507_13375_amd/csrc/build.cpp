@@ -462,6 +462,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(alloc(&b->cl_off, 256 + 2));
     chk(upload(&b->caps, caps));
     chk(alloc(&b->D, b->E));
+    chk(alloc(&b->D_alt, b->E));
     chk(alloc(&b->cur_layer, M));
     chk(alloc(&b->vlo, M));
     chk(alloc(&b->vhi, M));

@@ -93,8 +93,8 @@ struct la_batch {
     int32_t *level_nodes = nullptr, *level_ptr = nullptr, *height = nullptr;
     uint8_t *caps = nullptr;
 
-    // negotiation state
-    int32_t *D = nullptr;
+    // negotiation state; D_alt receives a batch's demand moves while its DP reads D (batched form)
+    int32_t *D = nullptr, *D_alt = nullptr;
     uint8_t *cur_layer = nullptr, *vlo = nullptr, *vhi = nullptr;
     bool has_prev = false;
 
@@ -193,8 +193,8 @@ la_status launch_rc_from_layers(la_batch *b);
 la_status launch_rc_pre(la_batch *b);
 la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay);
 la_status elmore_backward(la_batch *b, const float *gbar_neg_dslack, bool from_dslack, float *dR, float *dC);
-la_status commit_changed(la_batch *b);
-la_status history_update(la_batch *b, int32_t *H, int32_t hist_inc);
+la_status commit_changed(la_batch *b, int32_t *D);
+la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t hist_inc);
 la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut);
 
 }  // namespace gapla
