@@ -38,21 +38,19 @@ struct LdsState {
     int32_t *S_;
     uint8_t *bt_, *sel_;
     const int16_t *chp, *chl;
-    const int32_t *lenp, *lam_, *cpin_;
-    const uint16_t *segw_, *pinw_;
-    const uint8_t *fld;   // flags | direction << 4
+    const uint4 *rec;     // len, lam, segw | dir << 16 | flags << 24, cpin
+    const uint16_t *pinw_;
     __device__ int nch(int32_t s) const { return chp[s + 1] - chp[s]; }
     __device__ int32_t ch_state(int32_t s, int q) const { return chl[chp[s] + q]; }
     __device__ int64_t &F(int32_t s, int j) const { return F_[s * NAMAX + j]; }
     __device__ int32_t &S(int32_t s, int j) const { return S_[s * NAMAX + j]; }
     __device__ uint8_t *bt(int32_t s, int j) const { return bt_ + 2 * (s * NAMAX + j); }
     __device__ uint8_t &sel(int32_t s, int jp) const { return sel_[s * NAMAX + jp]; }
-    __device__ uint8_t flags(int32_t s) const { return fld[s] & 15; }
-    __device__ int dir(int32_t s) const { return fld[s] >> 4; }
-    __device__ int32_t len(int32_t s) const { return lenp[s + 1] - lenp[s]; }
-    __device__ uint32_t segw(int32_t s) const { return segw_[s]; }
-    __device__ uint32_t lam(int32_t s) const { return (uint32_t)lam_[s]; }
-    __device__ int32_t cpin(int32_t s) const { return cpin_[s]; }
+    __device__ NodeIn in(int32_t s) const
+    {
+        const uint4 r = rec[s];
+        return NodeIn{(int32_t)r.x, r.y, r.z & 0xffffu, (int)((r.z >> 16) & 1u), (uint8_t)(r.z >> 24), (int32_t)r.w};
+    }
     __device__ uint32_t pinw(int32_t s) const { return pinw_[s]; }
 };
 
@@ -63,21 +61,19 @@ struct Tile {
     static constexpr int nkey = 4 * kCap + 4;                       // (height, child class) buckets
     // F holds kappa_n(l) until the DP item (n, l) reads it and overwrites it with f
     static constexpr size_t F = 0;                                  // int64 [kCap][NAMAX]
-    static constexpr size_t S = F + (size_t)kCap * NAMAX * 8;       // int32 [kCap][NAMAX]
+    static constexpr size_t REC = F + (size_t)kCap * NAMAX * 8;     // uint4 [kCap] per-node inputs
+    static constexpr size_t S = REC + (size_t)kCap * 16;            // int32 [kCap][NAMAX]
     static constexpr size_t GID = S + (size_t)kCap * NAMAX * 4;     // int32 [kCap]
     static constexpr size_t LEN = GID + (size_t)kCap * 4;           // int32 [kCap+1] prefix of segment lengths
     static constexpr size_t G0 = LEN + (size_t)(kCap + 1) * 4;      // int32 [kCap] first GCell edge (layer 0)
-    static constexpr size_t LAM = G0 + (size_t)kCap * 4;            // int32 [kCap]
-    static constexpr size_t CPIN = LAM + (size_t)kCap * 4;          // int32 [kCap]
-    static constexpr size_t KEYS = CPIN + (size_t)kCap * 4;         // int32 [nkey] bucket starts
+    static constexpr size_t KEYS = G0 + (size_t)kCap * 4;           // int32 [nkey] bucket starts
     static constexpr size_t BOOK = KEYS + (size_t)nkey * 4;         // int32 [kBook]
     static constexpr size_t PAR = BOOK + (size_t)kBook * 4;         // int16 [kCap]
     static constexpr size_t CHP = PAR + (size_t)kCap * 2;           // int16 [kCap+2]
     static constexpr size_t CHL = CHP + (size_t)(kCap + 2) * 2;     // int16 [kCap]
     static constexpr size_t ORD = CHL + (size_t)kCap * 2;           // int16 [kCap]
     static constexpr size_t KEY = ORD + (size_t)kCap * 2;           // int16 [kCap] bucket of each node
-    static constexpr size_t SEGW = KEY + (size_t)kCap * 2;          // uint16 [kCap]
-    static constexpr size_t PINW = SEGW + (size_t)kCap * 2;         // uint16 [kCap]
+    static constexpr size_t PINW = KEY + (size_t)kCap * 2;          // uint16 [kCap]
     static constexpr size_t BT = PINW + (size_t)kCap * 2;           // uint8 [kCap][NAMAX][2]
     static constexpr size_t SEL = BT + (size_t)kCap * NAMAX * 2;    // uint8 [kCap][NAMAX]
     static constexpr size_t ENT = SEL + (size_t)kCap * NAMAX;       // uint8 [kCap] entering-layer index
@@ -144,8 +140,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
     int32_t *gid = (int32_t *)(smem + TL::GID);
     int32_t *lenp = (int32_t *)(smem + TL::LEN);
     int32_t *g0a = (int32_t *)(smem + TL::G0);
-    int32_t *lam = (int32_t *)(smem + TL::LAM);
-    int32_t *cpin = (int32_t *)(smem + TL::CPIN);
+    uint4 *rec = (uint4 *)(smem + TL::REC);
     int32_t *kst = (int32_t *)(smem + TL::KEYS);
     int32_t *book = (int32_t *)(smem + TL::BOOK);
     int16_t *par = (int16_t *)(smem + TL::PAR);
@@ -153,7 +148,6 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
     int16_t *chl = (int16_t *)(smem + TL::CHL);
     int16_t *order = (int16_t *)(smem + TL::ORD);
     int16_t *key = (int16_t *)(smem + TL::KEY);
-    uint16_t *segw = (uint16_t *)(smem + TL::SEGW);
     uint16_t *pinw = (uint16_t *)(smem + TL::PINW);
     uint8_t *bt = smem + TL::BT;
     uint8_t *sel = smem + TL::SEL;
@@ -176,7 +170,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
     const int L = tb.L;
     for (int i = threadIdx.x; i < L * 2 * kNDelta; i += blockDim.x) lut[i] = a.w.lut[i];
 
-    LdsState<NAMAX> st{F, S, bt, sel, chp, chl, lenp, lam, cpin, segw, pinw, fld};
+    LdsState<NAMAX> st{F, S, bt, sel, chp, chl, rec, pinw};
     // the batch's claims of small nets (its big nets run in k_batched_big)
     const int32_t coff = ba.cl_off[ba.tier], ncl = ba.cl_off[ba.tier + 1] - coff - 1;
     const int32_t Xl = tb.X * L;
@@ -256,12 +250,13 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
                 key[u] = (int16_t)bk;
                 atomicAdd(&kst[bk + 1], 1);
                 atomicMax(s_maxlev, h);
-                lenp[u + 1] = a.T.len[g];
+                const int32_t len = a.T.len[g];
+                const uint32_t fl = a.T.flags[g], dr = a.T.dir[g];
+                lenp[u + 1] = len;
                 g0a[u] = a.T.g0[g];
-                fld[u] = (uint8_t)(a.T.flags[g] | (a.T.dir[g] << 4));
-                segw[u] = a.w.seg_w[g];
-                lam[u] = a.w.lam[g];
-                cpin[u] = a.T.cpin[g];
+                fld[u] = (uint8_t)(fl | (dr << 4));
+                rec[u] = make_uint4((uint32_t)len, (uint32_t)a.w.lam[g],
+                                    (uint32_t)a.w.seg_w[g] | (dr << 16) | (fl << 24), (uint32_t)a.T.cpin[g]);
                 const int32_t sid = a.T.sink_id[g];
                 pinw[u] = sid >= 0 ? a.w.pin_w[sid] : (uint16_t)0;
                 prv[u] = a.w.self_excl ? a.prev[g] : (uint8_t)255;

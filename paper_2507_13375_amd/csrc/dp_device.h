@@ -54,9 +54,18 @@ __device__ __forceinline__ void load_tab(const LayerTab &src, LayerTab &dst)
     __syncthreads();
 }
 
+// Per-node inputs of the DP: segment length (GCells), look-ahead coefficient, Q10 segment
+// weight, direction, flags and pin capacitance.
+struct NodeIn {
+    int32_t len;
+    uint32_t lam, segw;
+    int dir;
+    uint8_t flags;
+    int32_t cpin;
+};
+
 // DP state in HBM, indexed by global node id (plain form).  Besides the DP state, a state
-// type gives the per-node inputs the DP reads: flags, segment length and direction, Q10
-// segment weight, look-ahead coefficient, pin capacitance and (at sinks) pin weight.
+// type gives the per-node inputs (`in`) and, at sinks, the pin weight.
 struct GlobalState {
     const DPArgs &a;
     __device__ GlobalState(const DPArgs &a_) : a(a_) {}
@@ -66,12 +75,10 @@ struct GlobalState {
     __device__ int32_t &S(int32_t s, int j) const { return a.S[(int64_t)s * a.NA + j]; }
     __device__ uint8_t *bt(int32_t s, int j) const { return a.bt + 2 * ((int64_t)s * a.NA + j); }
     __device__ uint8_t &sel(int32_t s, int jp) const { return a.sel[(int64_t)s * a.NA + jp]; }
-    __device__ uint8_t flags(int32_t s) const { return a.T.flags[s]; }
-    __device__ int32_t len(int32_t s) const { return a.T.len[s]; }
-    __device__ int dir(int32_t s) const { return a.T.dir[s]; }
-    __device__ uint32_t segw(int32_t s) const { return a.w.seg_w[s]; }
-    __device__ uint32_t lam(int32_t s) const { return (uint32_t)a.w.lam[s]; }
-    __device__ int32_t cpin(int32_t s) const { return a.T.cpin[s]; }
+    __device__ NodeIn in(int32_t s) const
+    {
+        return NodeIn{a.T.len[s], (uint32_t)a.w.lam[s], a.w.seg_w[s], a.T.dir[s], a.T.flags[s], a.T.cpin[s]};
+    }
     __device__ uint32_t pinw(int32_t s) const
     {
         const int32_t sid = a.T.sink_id[s];
@@ -143,10 +150,11 @@ __device__ __forceinline__ ChildIn child_in(const St &st, int32_t s, int q)
 {
     ChildIn c;
     c.cs = st.ch_state(s, q);
-    c.len = st.len(c.cs);
-    c.w = st.segw(c.cs);
-    c.lam = st.lam(c.cs);
-    c.dir = st.dir(c.cs);
+    const NodeIn n = st.in(c.cs);
+    c.len = n.len;
+    c.w = n.segw;
+    c.lam = n.lam;
+    c.dir = n.dir;
     return c;
 }
 
@@ -154,12 +162,19 @@ __device__ __forceinline__ ChildIn child_in(const St &st, int32_t s, int q)
 // look-ahead term (Sec. III-D) -- and X = C + 2S (segment capacitance plus twice the
 // downstream capacitance).  A parent entering on l ranks child layer t by
 // key = f' + w_d T(w, Rvia(l, t), X).
+// (jc: t's index in the child's direction list)
+template <class St>
+__device__ __forceinline__ int64_t child_key_j(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
+                                               int t, int jc)
+{
+    return st.F(c.cs, jc) + wd(Tq(c.w, rvia_d(tb, l, t), (uint32_t)st.S(c.cs, jc)));
+}
+
 template <class St>
 __device__ __forceinline__ int64_t child_key(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
                                              int t)
 {
-    const int jc = tb.jidx[t];
-    return st.F(c.cs, jc) + wd(Tq(c.w, rvia_d(tb, l, t), (uint32_t)st.S(c.cs, jc)));
+    return child_key_j(tb, st, wd, c, l, t, tb.jidx[t]);
 }
 
 // What a chosen child layer t contributes to its parent: V, the key without the child's
@@ -170,16 +185,22 @@ struct ChildVZ {
 };
 
 template <class St>
-__device__ __forceinline__ ChildVZ child_vz(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
-                                           int t)
+__device__ __forceinline__ ChildVZ child_vz_j(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
+                                             int t, int jc)
 {
-    const int jc = tb.jidx[t];
     const uint32_t X = (uint32_t)st.S(c.cs, jc);
     const uint32_t Z = (X + (uint32_t)(tb.c[t] * c.len)) >> 1;   // (C + 2S + C) / 2, exact
     ChildVZ r;
     r.V = st.F(c.cs, jc) - wd((int64_t)(mul_u32(c.lam, 2 * Z) >> 11)) + wd(Tq(c.w, rvia_d(tb, l, t), X));
     r.Z = Z;
     return r;
+}
+
+template <class St>
+__device__ __forceinline__ ChildVZ child_vz(const LayerTab &tb, const St &st, const Wd &wd, const ChildIn &c, int l,
+                                           int t)
+{
+    return child_vz_j(tb, st, wd, c, l, t, tb.jidx[t]);
 }
 
 __device__ __forceinline__ bool child_layer_ok(const LayerTab &tab, int cdir, int t)
@@ -257,21 +278,21 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 {
     const int L = tb.L;
     const Wd wd{(uint32_t)a.w.w_d};
-    const uint8_t fl = st.flags(s);
+    const NodeIn me = st.in(s);
+    const uint8_t fl = me.flags;
     const bool pin = fl & (kSink | kDriver);
     const int lo = pin ? 0 : l;
     const int hi = l;
     int64_t own_const = 0;
     uint32_t Cs = 0, Rw = 0, segw = 0, lam = 0;
     if (!root) {
-        const int32_t len = st.len(s);
-        Cs = (uint32_t)(tb.c[l] * len);
-        Rw = (uint32_t)(tb.r[l] * len);
+        Cs = (uint32_t)(tb.c[l] * me.len);
+        Rw = (uint32_t)(tb.r[l] * me.len);
         own_const = a.w.w_cong * kap + a.w.w_cap * (int64_t)Cs;
-        segw = st.segw(s);
-        lam = st.lam(s);
+        segw = me.segw;
+        lam = me.lam;
     }
-    const int32_t cpin = st.cpin(s);
+    const int32_t cpin = me.cpin;
     const int64_t pin_term = (fl & kSink) ? wd(Tq(st.pinw(s), rvia_d(tb, l, 0), 2 * (uint32_t)cpin)) : 0;
     const int k = st.nch(s);
 
@@ -301,24 +322,28 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
         done = true;
     } else if (a.w.w_via > 0 && k == 1) {
         // ---- one child: each of its layers names one hull ---------------------------------
+        // keys and X stay in registers; a candidate's f-part is its key minus the child's
+        // look-ahead term
         const ChildIn c0 = child_in(st, s, 0);
         const int n0 = tb.nA[c0.dir];
         int64_t ky[NAMAX];
+        uint32_t xq[NAMAX];
         int ly[NAMAX];
 #pragma unroll
         for (int jj = 0; jj < NAMAX; ++jj) {
             ly[jj] = tb.lay[c0.dir][jj < n0 ? jj : 0];
-            ky[jj] = jj < n0 ? child_key(tb, st, wd, c0, l, ly[jj]) : 0;
+            xq[jj] = jj < n0 ? (uint32_t)st.S(c0.cs, jj) : 0u;
+            ky[jj] = jj < n0 ? st.F(c0.cs, jj) + wd(Tq(c0.w, rvia_d(tb, l, ly[jj]), xq[jj])) : 0;
         }
-        uint32_t m = hull_min_mask<NAMAX>(ky, ly, n0, lo, hi);
+        const uint32_t m = hull_min_mask<NAMAX>(ky, ly, n0, lo, hi);
         int sel0 = 0;
-        while (m) {
-            const int jj = __ffs(m) - 1;
-            m &= m - 1;
-            const int L1 = tb.lay[c0.dir][jj];
-            const ChildVZ v = child_vz(tb, st, wd, c0, l, L1);
-            if (eval(min(lo, L1), max(hi, L1), v.V, v.Z)) sel0 = L1;
-        }
+#pragma unroll
+        for (int jj = 0; jj < NAMAX; ++jj)
+            if ((m >> jj) & 1u) {
+                const uint32_t Z = (xq[jj] + (uint32_t)(tb.c[ly[jj]] * c0.len)) >> 1;
+                const int64_t V = ky[jj] - wd((int64_t)(mul_u32(c0.lam, 2 * Z) >> 11));
+                if (eval(min(lo, ly[jj]), max(hi, ly[jj]), V, Z)) sel0 = ly[jj];
+            }
         st.sel(c0.cs, j) = (uint8_t)sel0;
         done = true;
     } else if (a.w.w_via > 0 && k == 2) {
@@ -338,7 +363,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 #pragma unroll
             for (int jj = 0; jj < NAMAX; ++jj) {
                 ly[jj] = tb.lay[cin[q].dir][jj < nq ? jj : 0];
-                ky[jj] = jj < nq ? child_key(tb, st, wd, cin[q], l, ly[jj]) : 0;
+                ky[jj] = jj < nq ? child_key_j(tb, st, wd, cin[q], l, ly[jj], jj) : 0;
                 lyp[q] |= (uint64_t)ly[jj] << (4 * jj);
             }
             block_bounds<NAMAX>(ky, ly, nq, lowp[q], upp[q]);
@@ -363,8 +388,8 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
             mask &= mask - 1;
             const int j1 = p / NAMAX, j2 = p - (p / NAMAX) * NAMAX;
             const int L1 = tb.lay[cin[0].dir][j1], L2 = tb.lay[cin[1].dir][j2];
-            const ChildVZ c1 = child_vz(tb, st, wd, cin[0], l, L1);
-            const ChildVZ c2 = child_vz(tb, st, wd, cin[1], l, L2);
+            const ChildVZ c1 = child_vz_j(tb, st, wd, cin[0], l, L1, j1);
+            const ChildVZ c2 = child_vz_j(tb, st, wd, cin[1], l, L2, j2);
             if (eval(min(lo, min(L1, L2)), max(hi, max(L1, L2)), c1.V + c2.V, (int64_t)c1.Z + c2.Z)) {
                 sel0 = L1;
                 sel1 = L2;
@@ -397,7 +422,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
                 for (int jj = 0; jj < NAMAX; ++jj) {
                     const int lq = tb.lay[cq.dir][jj < ncq ? jj : 0];
                     lyp[q] |= (uint64_t)lq << (4 * jj);
-                    ky[jj] = jj < ncq ? child_key(tb, st, wd, cq, l, lq) : 0;
+                    ky[jj] = jj < ncq ? child_key_j(tb, st, wd, cq, l, lq, jj) : 0;
                     if (jj < ncq) {
                         lmask |= 1u << lq;
                         base = min(base, ky[jj]);
