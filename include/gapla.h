@@ -113,7 +113,7 @@ typedef struct {
      * (6 per child + 10), and the compulsory bytes (node inputs, congestion gathers of 9 B per
      * GCell edge and routable layer, outputs).  Elmore: compulsory bytes of one forward and one
      * reverse sweep.  dp_ops_big_per_round: the part of dp_ops_per_round from nets of more than
-     * 224 nodes, which the batched form runs in its own kernel with the DP state in HBM. */
+     * 192 nodes, which the batched form runs in its own kernel with the DP state in HBM. */
     double dp_ops_per_round, dp_bytes_per_round, elmore_fwd_bytes, elmore_bwd_bytes;
     double dp_ops_big_per_round;
 } la_info;

@@ -32,19 +32,32 @@ constexpr int kNB = 1 + kHB; // partition buckets per batch
 constexpr int32_t kFuseNets = 16384;   // batches with this many small nets commit from their DP kernel
 
 // DP state and per-node inputs of one LDS tile, indexed by tile-local node id.
+constexpr int kKeyPool = 16;   // three-child items per tile whose keys get an LDS slot
+
 template <int NAMAX>
 struct LdsState {
+    static constexpr bool kKeyPool = true;
     int64_t *F_;
     int32_t *S_;
     uint8_t *bt_, *sel_;
     const int16_t *chp, *chl;
     const uint4 *rec;     // len, lam, segw | dir << 16 | flags << 24, cpin
     const uint16_t *pinw_;
+    int64_t *keys_;       // [kKeyPool][kHullKids][NAMAX]
+    uint64_t *lays_;      // [kKeyPool][kHullKids]
+    int32_t *pool_;       // slots handed out in this tile
+    __device__ int grab_key_slot() const
+    {
+        const int q = atomicAdd(pool_, 1);
+        return q < gapla::kKeyPool ? q : -1;
+    }
+    __device__ int64_t *key_slot(int q) const { return keys_ + q * kHullKids * NAMAX; }
+    __device__ uint64_t *lay_slot(int q) const { return lays_ + q * kHullKids; }
     __device__ int nch(int32_t s) const { return chp[s + 1] - chp[s]; }
     __device__ int32_t ch_state(int32_t s, int q) const { return chl[chp[s] + q]; }
     __device__ int64_t &F(int32_t s, int j) const { return F_[s * NAMAX + j]; }
     __device__ int32_t &S(int32_t s, int j) const { return S_[s * NAMAX + j]; }
-    __device__ uint8_t *bt(int32_t s, int j) const { return bt_ + 2 * (s * NAMAX + j); }
+    __device__ uint8_t &bt(int32_t s, int j) const { return bt_[s * NAMAX + j]; }
     __device__ uint8_t &sel(int32_t s, int jp) const { return sel_[s * NAMAX + jp]; }
     __device__ NodeIn in(int32_t s) const
     {
@@ -61,7 +74,9 @@ struct Tile {
     static constexpr int nkey = 4 * kCap + 4;                       // (height, child class) buckets
     // F holds kappa_n(l) until the DP item (n, l) reads it and overwrites it with f
     static constexpr size_t F = 0;                                  // int64 [kCap][NAMAX]
-    static constexpr size_t REC = F + (size_t)kCap * NAMAX * 8;     // uint4 [kCap] per-node inputs
+    static constexpr size_t KPOOL = F + (size_t)kCap * NAMAX * 8;   // int64 [kKeyPool][kHullKids][NAMAX]
+    static constexpr size_t LPOOL = KPOOL + (size_t)kKeyPool * kHullKids * NAMAX * 8;   // uint64 [kKeyPool][3]
+    static constexpr size_t REC = LPOOL + (size_t)kKeyPool * kHullKids * 8;   // uint4 [kCap] per-node inputs
     static constexpr size_t S = REC + (size_t)kCap * 16;            // int32 [kCap][NAMAX]
     static constexpr size_t GID = S + (size_t)kCap * NAMAX * 4;     // int32 [kCap]
     static constexpr size_t LEN = GID + (size_t)kCap * 4;           // int32 [kCap+1] prefix of segment lengths
@@ -74,8 +89,8 @@ struct Tile {
     static constexpr size_t ORD = CHL + (size_t)kCap * 2;           // int16 [kCap]
     static constexpr size_t KEY = ORD + (size_t)kCap * 2;           // int16 [kCap] bucket of each node
     static constexpr size_t PINW = KEY + (size_t)kCap * 2;          // uint16 [kCap]
-    static constexpr size_t BT = PINW + (size_t)kCap * 2;           // uint8 [kCap][NAMAX][2]
-    static constexpr size_t SEL = BT + (size_t)kCap * NAMAX * 2;    // uint8 [kCap][NAMAX]
+    static constexpr size_t BT = PINW + (size_t)kCap * 2;           // uint8 [kCap][NAMAX] b << 4 | t
+    static constexpr size_t SEL = BT + (size_t)kCap * NAMAX;        // uint8 [kCap][NAMAX]
     static constexpr size_t ENT = SEL + (size_t)kCap * NAMAX;       // uint8 [kCap] entering-layer index
     static constexpr size_t FLD = ENT + (size_t)kCap;               // uint8 [kCap] flags | dir << 4
     static constexpr size_t PRV = FLD + (size_t)kCap;               // uint8 [kCap] previous layer (255: none)
@@ -127,7 +142,7 @@ __device__ __forceinline__ void block_scan(int32_t *x, int32_t n, int32_t *tmp)
 }
 
 template <int NAMAX>
-__global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
+__global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPArgs a, BArgs ba)
 {
     using TL = Tile<NAMAX>;
     extern __shared__ __align__(16) uint8_t smem[];
@@ -156,7 +171,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
     uint8_t *prv = smem + TL::PRV;
     int32_t *lut = (int32_t *)(smem + TL::LUT);
 
-    // bookkeeping: [0] claim index, [1] #tiles, [2] max height of the tile; per tile: first
+    // bookkeeping: [0] claim index, [1] #tiles, [2] max height of the tile, [3] key-pool slots
+    // handed out in the tile; per tile: first
     // and end claim index, node count; per claimed net: node count, first global node,
     // first global child entry, tile-local node base and child base
     constexpr int Q = kClaimNets;
@@ -170,7 +186,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
     const int L = tb.L;
     for (int i = threadIdx.x; i < L * 2 * kNDelta; i += blockDim.x) lut[i] = a.w.lut[i];
 
-    LdsState<NAMAX> st{F, S, bt, sel, chp, chl, rec, pinw};
+    LdsState<NAMAX> st{F,   S,   bt,  sel, chp, chl, rec, pinw, (int64_t *)(smem + TL::KPOOL),
+                       (uint64_t *)(smem + TL::LPOOL), book + 3};
     // the batch's claims of small nets (its big nets run in k_batched_big)
     const int32_t coff = ba.cl_off[ba.tier], ncl = ba.cl_off[ba.tier + 1] - coff - 1;
     const int32_t Xl = tb.X * L;
@@ -224,6 +241,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_batched_dp(DPArgs a, BArgs ba)
             for (int32_t i = threadIdx.x; i < TL::nkey; i += blockDim.x) kst[i] = 0;
             if (threadIdx.x == 0) {
                 *s_maxlev = 0;
+                book[3] = 0;   // key pool of this tile
                 lenp[0] = 0;
                 chp[nn] = (int16_t)(s_cb[i1 - 1] + s_nn[i1 - 1] - 1);
             }

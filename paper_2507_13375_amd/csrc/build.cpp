@@ -468,7 +468,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(alloc(&b->vhi, M));
     chk(alloc(&b->F, M * b->NAmax));
     chk(alloc(&b->S, M * b->NAmax));
-    chk(alloc(&b->bt, M * b->NAmax * 2));
+    chk(alloc(&b->bt, M * b->NAmax));
     chk(alloc(&b->sel, M * b->NAmax + kMaxA));   // rows of NAmax, padded for the clamped index
     chk(alloc(&b->chg_node, M));
     chk(alloc(&b->chg_old, M));
@@ -499,7 +499,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     LA_HIP(hipMemcpy(b->lut, lut.data(), lut.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     LA_HIP(hipMemsetAsync(b->F, 0, M * b->NAmax * sizeof(int64_t), b->stream));
     LA_HIP(hipMemsetAsync(b->S, 0, M * b->NAmax * sizeof(int32_t), b->stream));
-    LA_HIP(hipMemsetAsync(b->bt, 0, M * b->NAmax * 2, b->stream));
+    LA_HIP(hipMemsetAsync(b->bt, 0, M * b->NAmax, b->stream));
     LA_HIP(hipMemsetAsync(b->sel, 0, M * b->NAmax + kMaxA, b->stream));
     LA_HIP(hipMemsetAsync(b->D, 0, b->E * sizeof(int32_t), b->stream));
     LA_HIP(hipMemsetAsync(b->cur_layer, 0, M, b->stream));

@@ -39,7 +39,7 @@ struct DPArgs {
     const uint8_t *prev;
     int64_t *F;        // [node][NA] f' (cost with the node's look-ahead term) of the chosen candidate
     int32_t *S;        // [node][NA] its X = C + 2S (aF, unsigned)
-    uint8_t *bt;       // [node][NA][2] chosen via stack
+    uint8_t *bt;       // [node][NA] chosen via stack, b << 4 | t
     uint8_t *sel;      // [node][NA] node's layer for each entering-layer index of its parent
     int32_t NA;
 };
@@ -67,13 +67,17 @@ struct NodeIn {
 // DP state in HBM, indexed by global node id (plain form).  Besides the DP state, a state
 // type gives the per-node inputs (`in`) and, at sinks, the pin weight.
 struct GlobalState {
+    static constexpr bool kKeyPool = false;   // three-child keys live in registers
+    __device__ int grab_key_slot() const { return -1; }
+    __device__ int64_t *key_slot(int) const { return nullptr; }
+    __device__ uint64_t *lay_slot(int) const { return nullptr; }
     const DPArgs &a;
     __device__ GlobalState(const DPArgs &a_) : a(a_) {}
     __device__ int nch(int32_t s) const { return a.T.ch_ptr[s + 1] - a.T.ch_ptr[s]; }
     __device__ int32_t ch_state(int32_t s, int q) const { return a.T.ch[a.T.ch_ptr[s] + q]; }
     __device__ int64_t &F(int32_t s, int j) const { return a.F[(int64_t)s * a.NA + j]; }
     __device__ int32_t &S(int32_t s, int j) const { return a.S[(int64_t)s * a.NA + j]; }
-    __device__ uint8_t *bt(int32_t s, int j) const { return a.bt + 2 * ((int64_t)s * a.NA + j); }
+    __device__ uint8_t &bt(int32_t s, int j) const { return a.bt[(int64_t)s * a.NA + j]; }
     __device__ uint8_t &sel(int32_t s, int jp) const { return a.sel[(int64_t)s * a.NA + jp]; }
     __device__ NodeIn in(int32_t s) const
     {
@@ -398,6 +402,72 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
         st.sel(cin[0].cs, j) = (uint8_t)sel0;
         st.sel(cin[1].cs, j) = (uint8_t)sel1;
         done = true;
+    } else if (a.w.w_via > 0 && k <= kHullKids && St::kKeyPool) {
+        // ---- three children, keys in a pool slot of the state (LDS) ----------------------
+        // Same stacks as below, with every child's keys and packed layers held in a slot of
+        // the workgroup's pool instead of registers; a full pool leaves the item to the full
+        // enumeration.
+        const int slot = st.grab_key_slot();
+        if (slot >= 0) {
+            int64_t *kq = st.key_slot(slot);   // [kHullKids][NAMAX]
+            uint64_t *lq = st.lay_slot(slot);  // [kHullKids]
+            uint32_t lmask = 0;
+            for (int q = 0; q < k; ++q) {
+                const ChildIn cq = child_in(st, s, q);
+                const int nq = tb.nA[cq.dir];
+                uint64_t pk = (uint64_t)nq << 32;
+                for (int jj = 0; jj < nq; ++jj) {
+                    const int lc = tb.lay[cq.dir][jj];
+                    pk |= (uint64_t)lc << (4 * jj);
+                    kq[q * NAMAX + jj] = child_key_j(tb, st, wd, cq, l, lc, jj);
+                    lmask |= 1u << lc;
+                }
+                lq[q] = pk;
+            }
+            uint32_t sel_pack = 0;
+            for (int b = lo; b >= 0; --b) {
+                if (b != lo && !((lmask >> b) & 1u)) continue;
+                for (int t = hi; t < L; ++t) {
+                    if (t != hi && !((lmask >> t) & 1u)) continue;
+                    bool ok = true;
+                    int hb = lo, ht = hi;
+                    uint32_t chosen = 0;   // per child: layer index (bits 4q..4q+3)
+                    for (int q = 0; q < k && ok; ++q) {
+                        const uint64_t pk = lq[q];
+                        const int nq = (int)(pk >> 32);
+                        int bl = -1, bj = 0;
+                        int64_t bk = 0;
+                        for (int jj = 0; jj < nq; ++jj) {
+                            const int lc = (int)((pk >> (4 * jj)) & 15u);
+                            const int64_t key = kq[q * NAMAX + jj];
+                            if (lc >= b && lc <= t && (bl < 0 || key < bk)) {
+                                bl = lc;
+                                bj = jj;
+                                bk = key;
+                            }
+                        }
+                        ok = bl >= 0;
+                        chosen |= (uint32_t)bj << (4 * q);
+                        hb = min(hb, bl < 0 ? hb : bl);
+                        ht = max(ht, bl);
+                    }
+                    if (!ok || hb != b || ht != t) continue;
+                    int64_t sumV = 0, sumZ = 0;
+                    uint32_t layers = 0;
+                    for (int q = 0; q < k; ++q) {
+                        const int jq = (int)((chosen >> (4 * q)) & 15u);
+                        const int lc = (int)((lq[q] >> (4 * jq)) & 15u);
+                        const ChildVZ c = child_vz_j(tb, st, wd, child_in(st, s, q), l, lc, jq);
+                        sumV += c.V;
+                        sumZ += c.Z;
+                        layers |= (uint32_t)lc << (4 * q);
+                    }
+                    if (eval(b, t, sumV, sumZ)) sel_pack = layers;
+                }
+            }
+            for (int q = 0; q < k; ++q) st.sel(st.ch_state(s, q), j) = (uint8_t)((sel_pack >> (4 * q)) & 15u);
+            done = true;
+        }
     } else if (a.w.w_via > 0 && k <= kHullKids) {
         // ---- three children: self-hull stacks ---------------------------------------------
         // Every child's keys are computed once, kept as 32-bit offsets from that child's
@@ -534,9 +604,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 
     st.F(s, j) = best.fp;
     st.S(s, j) = (int32_t)best.X;
-    uint8_t *bt = st.bt(s, j);
-    bt[0] = (uint8_t)best.b;
-    bt[1] = (uint8_t)best.t;
+    st.bt(s, j) = (uint8_t)(best.b << 4 | best.t);
 }
 
 // Commit list of the current batch: segments whose layer changed (old = 255 when the
@@ -585,9 +653,9 @@ __device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int3
         ln = ln < tb.L ? ln : 0;
         j = tb.jidx[ln] < 0 ? 0 : tb.jidx[ln];
     }
-    const uint8_t *bt = st.bt(s, j);
-    vlo[n] = bt[0];
-    vhi[n] = bt[1];
+    const uint8_t bt = st.bt(s, j);
+    vlo[n] = bt >> 4;
+    vhi[n] = bt & 15;
     const uint8_t old = cur[n];
     cur[n] = (uint8_t)ln;
     if (out_layers) out_layers[n] = (uint8_t)ln;

@@ -12,7 +12,7 @@
 namespace gapla {
 
 constexpr int kMaxL = 16;          // layers supported (4-bit layer ids)
-constexpr int kCap = 224;          // nodes of one batched-form workgroup's LDS tile
+constexpr int kCap = 192;          // nodes of one batched-form workgroup's LDS tile
 constexpr int kClaimUnits = 220;   // work-queue claim size: sum over its nets of (nodes + kNetUnits)
 constexpr int kNetUnits = 3;
 constexpr int kClaimNets = 64;     // bound on the nets of one claim (kClaimUnits / (1 + kNetUnits) + 1)
