@@ -177,7 +177,7 @@ def elmore_rate(b, kernels):
             "ms_per_sweep": ms / sweeps}
 
 
-def cpu_baseline(inst, n_max=300000):
+def cpu_baseline(inst, n_max=1000000):
     """The oracle (as it stands) on a bounded sample: the plain form's whole schedule (I
     iterations of Elmore -> Eq. 4/5 weights -> R rounds, then Elmore) over the first nets of
     the same workload, timed on the host threads."""
