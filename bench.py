@@ -35,6 +35,8 @@ def main():
     ap.add_argument("--nets", type=int, default=None, help="truncate the workload (testing only)")
     ap.add_argument("--forms", default="batched,plain")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -48,6 +50,13 @@ def main():
     import paper_2507_13375_amd as la
 
     torch.cuda.set_device(0)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     inst = gen.config(args.config, num_nets=args.nets)
     log("generated c%d: %d nets %d input nodes in %.1fs" % (args.config, inst.num_nets, inst.num_nodes,
@@ -145,6 +154,37 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+KERNEL_SOURCES = ("batched.hip", "dp_device.h", "la_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batched_dp_c4_2M_traffic.md")
+
+
+def kernel_sources_sha256():
+    """Hash of the sources of the batched DP kernel (the traffic figures hold for these only)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_13375_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_batched_dp launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
+    when it is missing or was taken on other kernel sources."""
+    try:
+        vals = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(("|", "#", "`")):
+                    k, v = line.split(":", 1)
+                    vals[k.strip()] = v.strip()
+        if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 # MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes, one int32 op per lane per clock at 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -161,8 +201,9 @@ def roofline(b, form, kernels):
     ops = ops_round * R_ROUNDS * I_ITERS
     achieved = ops / (ms * 1e-3) / 1e12
     return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "launches": n, "avg_launch_us": 1e3 * ms / n,
-            "ops_per_launch": ops / n}
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic() if form == "batched" else None,
+            "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": b.dp_bytes_per_round * R_ROUNDS * I_ITERS / n,
+            "launches": n, "avg_launch_us": 1e3 * ms / n, "ops_per_launch": ops / n}
 
 
 def elmore_rate(b, kernels):
