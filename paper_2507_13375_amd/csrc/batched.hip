@@ -317,12 +317,37 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             }
             __syncthreads();
             // ---- DP bottom-up, one height level at a time ----------------------------------
+            // A level of at most kThreads / kGroup items (tall trees) is bound by one item's
+            // latency: it takes a group of kGroup lanes per item (node, entering layer), items
+            // with one or two children lane-parallel, the others on the group's first lane.
+            // Larger levels take one lane per item.
             for (int32_t h = 0; h <= maxlev; ++h) {
                 const int32_t lb = h == 0 ? 0 : kst[4 * h - 1], le = kst[4 * h + 3];
                 const int32_t items = (le - lb) * NAMAX;
-                for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
-                    const int32_t u = order[lb + it / NAMAX];
-                    const int j = it % NAMAX;
+                if (items > kThreads / kGroup) {
+                    for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
+                        const int32_t u = order[lb + it / NAMAX];
+                        const int j = it % NAMAX;
+                        const bool root = par[u] < 0;
+                        int l;
+                        if (root) {
+                            if (j != 0) continue;
+                            l = 0;
+                        } else {
+                            const int d = fld[u] >> 4;
+                            if (j >= tb.nA[d]) continue;
+                            l = tb.lay[d][j];
+                        }
+                        dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, root ? 0 : kap[u * NAMAX + j]);
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                for (int32_t it = threadIdx.x; it < items * kGroup; it += blockDim.x) {
+                    const int32_t gi = it / kGroup;
+                    const int sub = it % kGroup;
+                    const int32_t u = order[lb + gi / NAMAX];
+                    const int j = gi % NAMAX;
                     const bool root = par[u] < 0;
                     int l;
                     if (root) {
@@ -333,7 +358,12 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                         if (j >= tb.nA[d]) continue;
                         l = tb.lay[d][j];
                     }
-                    dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, root ? 0 : kap[u * NAMAX + j]);
+                    const int64_t kp = root ? 0 : kap[u * NAMAX + j];
+                    const int k = st.nch(u);
+                    if (a.w.w_via > 0 && (k == 1 || k == 2))
+                        dp_group<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp, sub);
+                    else if (sub == 0)
+                        dp_node<LdsState<NAMAX>, NAMAX, false>(a, tb, st, u, l, j, root, kp);
                 }
                 __syncthreads();
             }

@@ -275,8 +275,9 @@ struct Best {
 
 // DP of node state s for its entering layer l (index j in its direction list; j = 0 and
 // l = 0 at the root).  kap is kappa_n(l) (0 at the root).  NAMAX bounds the routable
-// layers per direction.
-template <class St, int NAMAX>
+// layers per direction.  SMALLK = false leaves out the one- and two-child orders (callers
+// that run those items with dp_group).
+template <class St, int NAMAX, bool SMALLK = true>
 __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int l, int j,
                                         bool root, int64_t kap)
 {
@@ -324,7 +325,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
     if (a.w.w_via > 0 && k == 0) {
         eval(lo, hi, 0, 0);
         done = true;
-    } else if (a.w.w_via > 0 && k == 1) {
+    } else if (SMALLK && a.w.w_via > 0 && k == 1) {
         // ---- one child: each of its layers names one hull ---------------------------------
         // keys and X stay in registers; a candidate's f-part is its key minus the child's
         // look-ahead term
@@ -350,7 +351,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
             }
         st.sel(c0.cs, j) = (uint8_t)sel0;
         done = true;
-    } else if (a.w.w_via > 0 && k == 2) {
+    } else if (SMALLK && a.w.w_via > 0 && k == 2) {
         // ---- two children: hull candidates ------------------------------------------------
         // a pair of child layers names one hull; it is a candidate when each choice is its
         // child's key minimum inside that hull (block bounds make that test O(1))
@@ -605,6 +606,150 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
     st.F(s, j) = best.fp;
     st.S(s, j) = (int32_t)best.X;
     st.bt(s, j) = (uint8_t)(best.b << 4 | best.t);
+}
+
+// ---- lane-parallel DP of one item ---------------------------------------------------------
+// The 8 lanes of an aligned group (sub = lane & 7) share one item (node state s, entering
+// layer l, index j) with one or two children and a positive via weight: lane sub takes the
+// children's layer index sub.  Candidate tests use minima across the group (prefix/suffix
+// scans, broadcasts) and the best candidate is a group argmin over (f', b, t), so the result
+// equals dp_node's.  Every lane of the group must call it; lane 0 writes the state.
+constexpr int kGroup = 8;
+
+__device__ __forceinline__ int64_t grp_min_up(int64_t x, int sub)
+{
+#pragma unroll
+    for (int d = 1; d < kGroup; d <<= 1) {
+        const int64_t o = __shfl_up(x, d, kGroup);
+        if (sub >= d) x = o < x ? o : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int64_t grp_min_down(int64_t x, int sub)
+{
+#pragma unroll
+    for (int d = 1; d < kGroup; d <<= 1) {
+        const int64_t o = __shfl_down(x, d, kGroup);
+        if (sub + d < kGroup) x = o < x ? o : x;
+    }
+    return x;
+}
+
+template <class St, int NAMAX>
+__device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int l, int j,
+                                         bool root, int64_t kap, int sub)
+{
+    static_assert(NAMAX <= kGroup, "one lane per layer index");
+    const Wd wd{(uint32_t)a.w.w_d};
+    const NodeIn me = st.in(s);
+    const bool pin = me.flags & (kSink | kDriver);
+    const int lo = pin ? 0 : l;
+    const int hi = l;
+    int64_t own_const = 0;
+    uint32_t Cs = 0, Rw = 0;
+    if (!root) {
+        Cs = (uint32_t)(tb.c[l] * me.len);
+        Rw = (uint32_t)(tb.r[l] * me.len);
+        own_const = a.w.w_cong * kap + a.w.w_cap * (int64_t)Cs;
+    }
+    const int64_t pin_term =
+        (me.flags & kSink) ? wd(Tq(st.pinw(s), rvia_d(tb, l, 0), 2 * (uint32_t)me.cpin)) : 0;
+    // f' and X of stack [b,t] for the children's summed f-parts and capacitances
+    auto value = [&](int b, int t, int64_t sumV, int64_t sumZ, uint32_t &X) -> int64_t {
+        const uint32_t Sn = (uint32_t)(me.cpin + sumZ);
+        int64_t fp = a.w.w_via * (t - b) + sumV + pin_term;
+        X = 2 * Sn;
+        if (!root) {
+            X = Cs + 2 * Sn;
+            fp += own_const + wd(Tq(me.segw, Rw, X)) + wd((int64_t)(mul_u32(me.lam, 2 * (Cs + Sn)) >> 11));
+        }
+        return fp;
+    };
+    const int k = st.nch(s);
+    // this lane's candidate: f', stack b << 4 | t, X and the children's layers (4 bits each)
+    int64_t fp = INT64_MAX;
+    uint32_t bt = 0xff, X = 0, sel = 0;
+    const ChildIn c0 = child_in(st, s, 0);
+    const int n0 = tb.nA[c0.dir];
+    const bool v0 = sub < n0;
+    const int l0 = tb.lay[c0.dir][v0 ? sub : 0];
+    const int64_t k0 = v0 ? child_key_j(tb, st, wd, c0, l, l0, sub) : INT64_MAX;
+    if (k == 1) {
+        // layer l0 is a candidate when no lower layer inside its hull has a key <= its key
+        // and no higher one a smaller key (exclusive scans over the lanes in layer order)
+        const int64_t below = __shfl_up(grp_min_up(v0 && l0 >= lo ? k0 : INT64_MAX, sub), 1, kGroup);
+        const int64_t above = __shfl_down(grp_min_down(v0 && l0 <= hi ? k0 : INT64_MAX, sub), 1, kGroup);
+        const bool ok = v0 && (l0 < lo || sub == 0 || k0 < below) && (l0 > hi || sub == kGroup - 1 || k0 <= above);
+        if (ok) {
+            const ChildVZ v = child_vz_j(tb, st, wd, c0, l, l0, sub);
+            const int b = min(lo, l0), t = max(hi, l0);
+            fp = value(b, t, v.V, v.Z, X);
+            bt = (uint32_t)(b << 4 | t);
+            sel = (uint32_t)l0;
+        }
+    } else {
+        // two children: a pair is a candidate when each choice is its child's key minimum in
+        // the pair's hull; per child and layer, the highest lower layer with a key <= and the
+        // lowest higher layer with a smaller key bound the hulls where it stays the minimum
+        const ChildIn c1 = child_in(st, s, 1);
+        const int n1 = tb.nA[c1.dir];
+        const bool v1 = sub < n1;
+        const int l1 = tb.lay[c1.dir][v1 ? sub : 0];
+        const int64_t k1 = v1 ? child_key_j(tb, st, wd, c1, l, l1, sub) : INT64_MAX;
+        int lb0 = -1, ub0 = 16, lb1 = -1, ub1 = 16;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+            const int64_t ki0 = __shfl(k0, i, kGroup), ki1 = __shfl(k1, i, kGroup);
+            const int li0 = __shfl(l0, i, kGroup), li1 = __shfl(l1, i, kGroup);
+            if (i < n0 && i < sub && ki0 <= k0) lb0 = li0;
+            if (i < n1 && i < sub && ki1 <= k1) lb1 = li1;
+            if (i < n0 && i > sub && ki0 < k0 && ub0 == 16) ub0 = li0;
+            if (i < n1 && i > sub && ki1 < k1 && ub1 == 16) ub1 = li1;
+        }
+        // child 1's layer, bounds and validity of every index, for the pairs of this lane
+        const uint32_t pack1 = (uint32_t)l1 | (uint32_t)(lb1 + 1) << 4 | (uint32_t)(ub1 + 1) << 9 | (v1 ? 1u << 14 : 0u);
+        ChildVZ z0{0, 0};
+        if (v0) z0 = child_vz_j(tb, st, wd, c0, l, l0, sub);
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+            const uint32_t p = __shfl(pack1, i, kGroup);
+            if (!v0 || !((p >> 14) & 1u)) continue;
+            const int L2 = (int)(p & 15u), lb2 = (int)((p >> 4) & 31u) - 1, ub2 = (int)((p >> 9) & 31u) - 1;
+            const int b = min(lo, min(l0, L2)), t = max(hi, max(l0, L2));
+            if (lb0 < b && t < ub0 && lb2 < b && t < ub2) {
+                const ChildVZ z1 = child_vz_j(tb, st, wd, c1, l, L2, i);
+                uint32_t Xc;
+                const int64_t f = value(b, t, z0.V + z1.V, (int64_t)z0.Z + z1.Z, Xc);
+                const uint32_t btc = (uint32_t)(b << 4 | t);
+                if (f < fp || (f == fp && btc < bt)) {
+                    fp = f;
+                    bt = btc;
+                    X = Xc;
+                    sel = (uint32_t)l0 | (uint32_t)L2 << 4;
+                }
+            }
+        }
+    }
+    // group argmin over (f', b, t)
+#pragma unroll
+    for (int m = 1; m < kGroup; m <<= 1) {
+        const int64_t ofp = __shfl_xor(fp, m, kGroup);
+        const uint32_t obt = __shfl_xor(bt, m, kGroup), oX = __shfl_xor(X, m, kGroup), osel = __shfl_xor(sel, m, kGroup);
+        if (ofp < fp || (ofp == fp && obt < bt)) {
+            fp = ofp;
+            bt = obt;
+            X = oX;
+            sel = osel;
+        }
+    }
+    if (sub == 0) {
+        st.F(s, j) = fp;
+        st.S(s, j) = (int32_t)X;
+        st.bt(s, j) = (uint8_t)bt;
+        st.sel(c0.cs, j) = (uint8_t)(sel & 15u);
+        if (k == 2) st.sel(st.ch_state(s, 1), j) = (uint8_t)(sel >> 4);
+    }
 }
 
 // Commit list of the current batch: segments whose layer changed (old = 255 when the
