@@ -7,8 +7,9 @@ nets/s = nets x R x I / step time.  Inputs are resident in HBM before timing.
 
 The batched+adjoint form (persistent per-batch DP kernels in a hipGraph,
 weights from the Elmore reverse sweep) is the reported value; the plain
-per-level-launch form with Eq. 4/5 weights runs the same schedule beside it.
-The CPU oracle is timed on a bounded sample on the host cores.
+per-level-launch form with Eq. 4/5 weights runs the same schedule beside it,
+and so does the batched form with the plain form's weights (the batching gain
+alone).  The CPU oracle is timed on a bounded sample on the host cores.
 """
 import argparse
 import json
@@ -33,7 +34,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--nets", type=int, default=None, help="truncate the workload (testing only)")
-    ap.add_argument("--forms", default="batched,plain")
+    ap.add_argument("--forms", default="batched,plain,batched_plainw",
+                    help="batched (adjoint weights), plain (Eq. 4/5 weights), batched_plainw (batched, Eq. 4/5 weights)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (calibrates HBM counters)")
@@ -76,10 +78,9 @@ def main():
     lam = torch.zeros(b.nodes, dtype=torch.int32, device=dev)
     tier = torch.zeros(b.nets, dtype=torch.uint8, device=dev)
 
-    def step(form):
+    def step(form, mode):
         la.la_reset(b)
         H.zero_()
-        mode = la.LA_WEIGHTS_ADJOINT if form == la.LA_FORM_BATCHED else la.LA_WEIGHTS_PLAIN
         for _ in range(I_ITERS):
             la.la_elmore(b, delay)
             la.la_timing_weights(b, delay, mode, sw, pw, lam, tier)
@@ -88,10 +89,11 @@ def main():
 
     results = {}
     for name in args.forms.split(","):
-        form = la.LA_FORM_BATCHED if name == "batched" else la.LA_FORM_PLAIN
+        form = la.LA_FORM_PLAIN if name == "plain" else la.LA_FORM_BATCHED
+        mode = la.LA_WEIGHTS_ADJOINT if name == "batched" else la.LA_WEIGHTS_PLAIN
         try:
             for _ in range(args.warmup):
-                step(form)
+                step(form, mode)
             torch.cuda.synchronize()
         except la.LAError as e:
             log("form %s unavailable: %s" % (name, e))
@@ -101,7 +103,7 @@ def main():
         torch.cuda.synchronize()
         ev0.record()
         for _ in range(args.steps):
-            step(form)
+            step(form, mode)
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.steps
@@ -112,7 +114,7 @@ def main():
         # one more step on the same stream with every hot launch bracketed by HIP events
         # (the batched form then launches its kernels directly instead of replaying its graph)
         la.la_profile_begin(b)
-        step(form)
+        step(form, mode)
         results[name]["kernels"] = la.la_profile_end(b)
         for k, (n, t) in sorted(results[name]["kernels"].items(), key=lambda kv: -kv[1][1]):
             log("  %-16s %6d launches %10.3f ms/step %9.2f us/launch" % (k, n, t, 1e3 * t / n))
@@ -151,6 +153,10 @@ def main():
     }
     if "batched" in results and "plain" in results:
         out["batched_over_plain"] = results["batched"]["nets_per_s"] / results["plain"]["nets_per_s"]
+    if "batched_plainw" in results and "plain" in results:
+        # same weights as the plain form: the gain of the batched orchestration alone
+        out["batched_over_plain_same_weights"] = (results["batched_plainw"]["nets_per_s"] /
+                                                  results["plain"]["nets_per_s"])
     print(json.dumps(out), flush=True)
 
 
@@ -193,11 +199,12 @@ def roofline(b, form, kernels):
     """The DP enumeration kernel against the vector-ALU peak.  Algorithmic work = stacks x
     (6 ops per child + 10) over every node and entering layer (la_info.dp_ops_per_round),
     times the rounds the step runs; divided by that kernel's summed launch time."""
-    name = "k_batched_dp" if form == "batched" else "k_dp_level"
+    batched = form.startswith("batched")
+    name = "k_batched_dp" if batched else "k_dp_level"
     if name not in kernels:
         return None
     n, ms = kernels[name]
-    ops_round = b.dp_ops_per_round - (b.dp_ops_big_per_round if form == "batched" else 0.0)
+    ops_round = b.dp_ops_per_round - (b.dp_ops_big_per_round if batched else 0.0)
     ops = ops_round * R_ROUNDS * I_ITERS
     achieved = ops / (ms * 1e-3) / 1e12
     return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
