@@ -285,19 +285,32 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             const int32_t maxlev = *s_maxlev;
             block_scan(kst, 4 * maxlev + 5, scan_tmp);   // bucket starts
             block_scan(lenp, nn + 1, scan_tmp);          // lenp[u]: first GCell step of u
-            // (height, class) order; kst[q] ends as the end of bucket q = start of q+1
-            for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) order[atomicAdd(&kst[key[u]], 1)] = (int16_t)u;
+            // (height, class) order; kst[q] ends as the end of bucket q = start of q+1.  The
+            // step -> segment map of the gather borrows sel, which the DP fills only later.
+            const int32_t steps = lenp[nn];
+            uint8_t *smap = sel;
+            const bool mapped = steps <= kCap * NAMAX;
+            for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
+                order[atomicAdd(&kst[key[u]], 1)] = (int16_t)u;
+                if (mapped)
+                    for (int32_t q = lenp[u]; q < lenp[u + 1]; ++q) smap[q] = (uint8_t)u;
+            }
+            if (mapped) __syncthreads();
             // congestion costs: one thread per GCell edge of the tile's segments, every
             // routable layer of the segment's direction at once
-            const int32_t steps = lenp[nn];
             for (int32_t pidx = threadIdx.x; pidx < steps; pidx += blockDim.x) {
-                int32_t lo_ = 0, hi_ = nn;      // last u with lenp[u] <= pidx
-                while (hi_ - lo_ > 1) {
-                    const int32_t mid = (lo_ + hi_) >> 1;
-                    if (lenp[mid] <= pidx) lo_ = mid;
-                    else hi_ = mid;
+                int32_t u;
+                if (mapped) {
+                    u = smap[pidx];
+                } else {
+                    int32_t lo_ = 0, hi_ = nn;      // last u with lenp[u] <= pidx
+                    while (hi_ - lo_ > 1) {
+                        const int32_t mid = (lo_ + hi_) >> 1;
+                        if (lenp[mid] <= pidx) lo_ = mid;
+                        else hi_ = mid;
+                    }
+                    u = lo_;
                 }
-                const int32_t u = lo_;
                 const int d = fld[u] >> 4;
                 const int32_t g = g0a[u] + (pidx - lenp[u]) * (d == 0 ? L : Xl);
                 const int self = prv[u];
@@ -382,8 +395,9 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                         n = gid[u];
                         const int32_t pu = par[u];
                         const int jp = (pu < 0 || par[pu] < 0) ? 0 : ent[pu];
+                        // the previous layer was staged (prv) when this round has one
                         ent[u] = (uint8_t)trace_node(tb, st, u, n, jp, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers,
-                                                     ba.has_prev, &ln, &changed, &old_l);
+                                                     ba.has_prev, &ln, &changed, &old_l, ba.has_prev ? prv[u] : 0);
                     }
                     if (ba.Dw) {
                         // commit the move along the segment's GCell edges (the DP of this batch

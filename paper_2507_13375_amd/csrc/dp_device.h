@@ -783,12 +783,13 @@ __device__ __forceinline__ void append_change(const ChangeList &cl, bool pred, i
 // Alg. 4 at node n (state s): its layer is the one its parent recorded for the parent's
 // entering layer; its via span is the stack recorded for its own entering layer.
 // jp: the index of the parent's entering layer in the parent's direction list (0 when
-// the parent is the root).  Returns n's entering-layer index (0 at the root), sets *ln to
-// the layer and *changed / *old_l for the commit list.
+// the parent is the root).  old: n's layer before this pass when the caller has it, else
+// -1 (read from cur).  Returns n's entering-layer index (0 at the root), sets *ln to the
+// layer and *changed / *old_l for the commit list.
 template <class St>
 __device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int32_t s, int32_t n, int jp, bool root,
                                           uint8_t *cur, uint8_t *vlo, uint8_t *vhi, uint8_t *out_layers,
-                                          int has_prev, int *ln_out, bool *changed, uint8_t *old_l)
+                                          int has_prev, int *ln_out, bool *changed, uint8_t *old_l, int old_in = -1)
 {
     int ln = 0, j = 0;
     if (!root) {
@@ -801,7 +802,7 @@ __device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int3
     const uint8_t bt = st.bt(s, j);
     vlo[n] = bt >> 4;
     vhi[n] = bt & 15;
-    const uint8_t old = cur[n];
+    const uint8_t old = old_in >= 0 ? (uint8_t)old_in : cur[n];
     cur[n] = (uint8_t)ln;
     if (out_layers) out_layers[n] = (uint8_t)ln;
     *changed = !root && (!has_prev || old != ln);
