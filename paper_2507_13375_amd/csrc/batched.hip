@@ -30,6 +30,7 @@ constexpr int kBook = 9 * kClaimNets + 8;   // ints of per-claim bookkeeping
 constexpr int kHB = 32;      // height classes of small nets per batch
 constexpr int kNB = 1 + kHB; // partition buckets per batch
 constexpr int32_t kFuseNets = 16384;   // batches with this many small nets commit from their DP kernel
+constexpr int32_t kMergeNets = 64;     // batches of at most this many small nets may share a launch
 
 // DP state and per-node inputs of one LDS tile, indexed by tile-local node id.
 constexpr int kKeyPool = 16;   // three-child items per tile whose keys get an LDS slot
@@ -101,8 +102,8 @@ struct Tile {
 struct BArgs {
     const int32_t *tier_nets;
     const int32_t *tier_off;    // [2*T+1]: bucket starts; batch t spans [off[2t], off[2t+2])
-    int32_t tier;
-    int32_t *ctr;               // work-queue counter of this (round, batch)
+    int32_t tier, tier_hi;      // batches tier..tier_hi run together (tier_hi > tier: merged small batches)
+    int32_t *ctr;               // work-queue counter of this (round, batch group)
     const int32_t *cl_start;    // claim starts (positions in tier_nets); batch t's claims from cl_off[t]
     const int32_t *cl_off;
     const int32_t *height;
@@ -188,15 +189,21 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
 
     LdsState<NAMAX> st{F,   S,   bt,  sel, chp, chl, rec, pinw, (int64_t *)(smem + TL::KPOOL),
                        (uint64_t *)(smem + TL::LPOOL), book + 3};
-    // the batch's claims of small nets (its big nets run in k_batched_big)
-    const int32_t coff = ba.cl_off[ba.tier], ncl = ba.cl_off[ba.tier + 1] - coff - 1;
+    // the claims of the small nets of batches tier..tier_hi (big nets run in k_batched_big);
+    // batch t lists n_t claims and an end slot from cl_off[t]
+    auto nclaims = [&](int32_t t) { return max(0, ba.cl_off[t + 1] - ba.cl_off[t] - 1); };
+    int32_t ncl = 0;
+    for (int32_t t = ba.tier; t <= ba.tier_hi; ++t) ncl += nclaims(t);
     const int32_t Xl = tb.X * L;
 
     for (;;) {
         if (threadIdx.x == 0) *s_base = atomicAdd(ba.ctr, 1);
         __syncthreads();
-        const int32_t c = *s_base;
+        int32_t c = *s_base;
         if (c >= ncl) break;
+        int32_t t = ba.tier;
+        while (c >= nclaims(t)) c -= nclaims(t++);
+        const int32_t coff = ba.cl_off[t];
         // at most kClaimNets by construction (each net counts >= 1 + kNetUnits units)
         const int32_t p0 = ba.cl_start[coff + c], nclaim = min(ba.cl_start[coff + c + 1] - p0, kClaimNets);
         if (threadIdx.x < nclaim) {
@@ -690,9 +697,10 @@ int32_t small_nets(const std::vector<int32_t> &cnt, int32_t t)
 // small nets commits them from its DP kernel into a copy of the demand map (its DP reads the
 // map as it was before the batch); the copy then becomes the current map.
 la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
-                         const std::vector<int32_t> &cnt, hipStream_t s)
+                         const std::vector<int32_t> &cnt, const std::vector<int32_t> &groups, hipStream_t s)
 {
     const int32_t ntier = w->net_tier ? w->num_tiers : 1;
+    const int32_t ngroup = (int32_t)groups.size() / 2;
     const int32_t R = w->rounds;
     la_status st = LA_OK;
     bool has_prev = b->has_prev;
@@ -703,8 +711,13 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
     for (int32_t r = 0; r < R && st == LA_OK; ++r) {
         DPArgs a = make_dp_args(b, w, H, lut);
         a.w.self_excl = has_prev ? 1 : 0;
-        for (int32_t t = 0; t < ntier && st == LA_OK; ++t) {
-            const int32_t nbig = cnt[t * kNB], nsmall = small_nets(cnt, t);
+        for (int32_t gi = 0; gi < ngroup && st == LA_OK; ++gi) {
+            const int32_t t = groups[2 * gi], t_hi = groups[2 * gi + 1];
+            int32_t nbig = 0, nsmall = 0;
+            for (int32_t q = t; q <= t_hi; ++q) {
+                nbig += cnt[q * kNB];
+                nsmall += small_nets(cnt, q);
+            }
             if (nbig + nsmall == 0) continue;
             const bool fused = nsmall >= kFuseNets;
             a.D = dcur;
@@ -716,7 +729,8 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             ba.tier_nets = b->tier_nets;
             ba.tier_off = b->tier_off;
             ba.tier = t;
-            ba.ctr = b->claim + r * ntier + t;
+            ba.tier_hi = t_hi;
+            ba.ctr = b->claim + r * ntier + gi;
             ba.cl_start = b->cl_start;
             ba.cl_off = b->cl_off;
             ba.height = b->height;
@@ -798,11 +812,67 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     LA_HIP(hipStreamSynchronize(b->stream));
     if (cnt[nb]) return set_error(LA_ERR_INVALID_ARG, "net_tier holds a batch index >= num_tiers");
 
+    // Consecutive batches of at most kMergeNets small nets whose bounding boxes are pairwise
+    // disjoint run as one launch: no net of a later batch reads a GCell edge that an earlier
+    // one commits to, so the result equals running the batches one after another.
+    std::vector<int32_t> groups;
+    {
+        std::vector<int64_t> off(nb + 1, 0);
+        for (int32_t q = 0; q < nb; ++q) off[q + 1] = off[q] + cnt[q];
+        auto mergeable = [&](int32_t t) {
+            const int32_t n = small_nets(cnt, t);
+            return cnt[t * kNB] == 0 && n >= 1 && n <= kMergeNets;
+        };
+        std::vector<std::vector<int32_t>> nets_of(ntier);
+        int32_t cand = 0;
+        for (int32_t t = 0; t < ntier; ++t) cand += mergeable(t) ? 1 : 0;
+        if (cand >= 2) {
+            for (int32_t t = 0; t < ntier; ++t) {
+                if (!mergeable(t)) continue;
+                const int64_t p0 = off[t * kNB + 1], n = off[(t + 1) * kNB] - p0;
+                nets_of[t].resize(n);
+                LA_HIP(hipMemcpyAsync(nets_of[t].data(), b->tier_nets + p0, n * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      b->stream));
+            }
+            LA_HIP(hipStreamSynchronize(b->stream));
+        }
+        auto overlap = [&](int32_t a, int32_t c) {
+            const int16_t *p = &b->h_bbox[(size_t)4 * a], *q = &b->h_bbox[(size_t)4 * c];
+            return p[0] <= q[1] && q[0] <= p[1] && p[2] <= q[3] && q[2] <= p[3];
+        };
+        int32_t lo = -1, hi = -1;
+        bool open = false;                 // the current group still takes batches
+        std::vector<int32_t> members;      // nets of the current group
+        for (int32_t t = 0; t < ntier; ++t) {
+            if (cnt[t * kNB] + small_nets(cnt, t) == 0) continue;
+            bool join = open && cand >= 2 && mergeable(t);
+            for (size_t i = 0; join && i < nets_of[t].size(); ++i)
+                for (size_t k = 0; join && k < members.size(); ++k)
+                    if (overlap(nets_of[t][i], members[k])) join = false;
+            if (join) {
+                hi = t;
+                members.insert(members.end(), nets_of[t].begin(), nets_of[t].end());
+                continue;
+            }
+            if (lo >= 0) {
+                groups.push_back(lo);
+                groups.push_back(hi);
+            }
+            lo = hi = t;
+            open = cand >= 2 && mergeable(t);
+            members = nets_of[t];
+        }
+        if (lo >= 0) {
+            groups.push_back(lo);
+            groups.push_back(hi);
+        }
+    }
+
     // the rounds, as one graph: per batch the persistent DP, then the commit; history per round.
     // While kernels are being timed the same launches go straight to the batch's stream.
     if (b->prof_on) {
         hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->claim, R * ntier);
-        la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, b->stream);
+        la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, groups, b->stream);
         if (st != LA_OK) return st;
         b->has_prev = true;
         return LA_OK;
@@ -814,13 +884,14 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         key.push_back(cnt[t * kNB]);
         key.push_back(small_nets(cnt, t) > 0);
     }
+    key.insert(key.end(), groups.begin(), groups.end());
     if (!b->gexec || key != b->gkey) {
         if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
         if (!b->cap_stream) LA_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         hipStream_t s = b->cap_stream;
         LA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, s);
+        const la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, groups, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
         if (st != LA_OK) {

@@ -416,6 +416,21 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     b->bnd_d = bd;
     b->h_level_ptr = level_ptr;
     b->h_net_ptr = net_ptr;
+    b->h_bbox.resize((size_t)4 * N);
+    for (int32_t i = 0; i < N; ++i) {
+        int32_t x0 = INT32_MAX, x1 = -1, y0 = INT32_MAX, y1 = -1;
+        for (int32_t v = net_ptr[i]; v < net_ptr[i + 1]; ++v) {
+            x0 = std::min(x0, xs[v]);
+            x1 = std::max(x1, xs[v]);
+            y0 = std::min(y0, ys[v]);
+            y1 = std::max(y1, ys[v]);
+        }
+        int16_t *bb = &b->h_bbox[(size_t)4 * i];
+        bb[0] = (int16_t)x0;
+        bb[1] = (int16_t)x1;
+        bb[2] = (int16_t)y0;
+        bb[3] = (int16_t)y1;
+    }
     std::vector<int32_t> budget(nets->net_budget_fs, nets->net_budget_fs + N);
     std::vector<int32_t> rdrv(nets->net_rdrv_mohm, nets->net_rdrv_mohm + N);
     std::vector<uint8_t> caps(edge_caps, edge_caps + b->E);

@@ -84,6 +84,7 @@ struct la_batch {
     // host copies
     std::vector<int32_t> h_level_ptr;   // [levels+1]
     std::vector<int32_t> h_net_ptr;
+    std::vector<int16_t> h_bbox;        // [nets][4] x min, x max, y min, y max of the net's nodes
 
     // device tree
     int32_t *parent = nullptr, *ch_ptr = nullptr, *ch = nullptr, *net = nullptr, *net_ptr = nullptr;

@@ -224,3 +224,24 @@ def test_out_of_range_batch_index_is_rejected():
         with pytest.raises(la.LAError) as e:
             g.assign(np.zeros(n), np.zeros(g.b.sinks), np.zeros(n), np.full(g.b.nets, 5), num_tiers=3, form=form)
         assert e.value.code == la.LA_ERR_INVALID_ARG
+
+
+def test_merged_single_net_batches():
+    # forty batches of one net each, then one large batch: disjoint tiny batches share a
+    # launch, and the result still equals the oracle's one-batch-after-another schedule
+    inst = gen.config(3, num_nets=6000)
+    T = oracle.Tree(inst)
+    sw = gen.synthetic_weights(T.nodes, T.sinks, T.nets, seed=21)
+    tiers = np.full(T.nets, 40, np.uint8)
+    tiers[:40] = np.arange(40)
+    say("merged batches: %d nets" % T.nets)
+    o = oracle_assign(inst, sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], tiers, rounds=2)
+    run = GpuRun(inst)
+    la.la_profile_begin(run.b)
+    g = run.assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], tiers, num_tiers=41, rounds=2,
+                   form=la.LA_FORM_BATCHED)
+    stats = la.la_profile_end(run.b)
+    assert_assign_equal(g, o, "merged")
+    launches = stats["k_batched_dp"][0]
+    say("k_batched_dp launches: %d for 2 rounds of 41 batches" % launches)
+    assert launches < 2 * 41
