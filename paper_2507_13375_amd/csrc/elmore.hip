@@ -126,12 +126,9 @@ __global__ void k_rc(TreeDev T, LayerTab targ, const uint8_t *lay, float *R, flo
 // Forward: S(v) = sum over RC children of (C + S), bottom-up by height;
 // t(v) = t(parent) + R_v (C_v/2 + S_v), top-down; delay at sink pins.
 // ---------------------------------------------------------------------------
-__global__ void k_elmore_up(TreeDev T, const int32_t *nodes, int32_t cnt, const float *R, const float *C, float *S,
-                            float *Slo)
+__device__ __forceinline__ void elm_up(const TreeDev &T, int32_t v, const float *R, const float *C, float *S,
+                                       float *Slo)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int32_t v = nodes[i];
     ff s{0.f, 0.f};
     const int32_t k = T.sink_id[v];
     if (k >= 0) {
@@ -148,12 +145,10 @@ __global__ void k_elmore_up(TreeDev T, const int32_t *nodes, int32_t cnt, const 
     Slo[v] = s.lo;
 }
 
-__global__ void k_elmore_down(TreeDev T, const int32_t *nodes, int32_t cnt, const float *R, const float *C,
-                              const float *S, const float *Slo, float *t, float *tlo, float *delay)
+__device__ __forceinline__ void elm_down(const TreeDev &T, int32_t v, const float *R, const float *C, const float *S,
+                                         const float *Slo, float *t, float *tlo, float *delay)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int32_t v = nodes[i], p = T.parent[v];
+    const int32_t p = T.parent[v];
     ff up = p < 0 ? ff{0.f, 0.f} : ff{t[p], tlo[p]};
     ff load = ff_add(ff{S[v], Slo[v]}, 0.5f * C[v]);
     ff tv = ff_norm(ff_add(up, ff_mul(R[v], load)));
@@ -172,11 +167,8 @@ __global__ void k_elmore_down(TreeDev T, const int32_t *nodes, int32_t cnt, cons
 // Sig(v) = Sig(parent) + R_v G(v) (top-down), dR_v = G(v)(C_v/2 + S_v),
 // dC_v = R_v G(v)/2 + Sig(parent).
 // ---------------------------------------------------------------------------
-__global__ void k_adj_up(TreeDev T, const int32_t *nodes, int32_t cnt, const float *gbar, float *G, float *Glo)
+__device__ __forceinline__ void adj_up(const TreeDev &T, int32_t v, const float *gbar, float *G, float *Glo)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int32_t v = nodes[i];
     ff g{0.f, 0.f};
     const int32_t k = T.sink_id[v];
     if (k >= 0) g = ff_add(g, gbar[k]);
@@ -189,13 +181,11 @@ __global__ void k_adj_up(TreeDev T, const int32_t *nodes, int32_t cnt, const flo
     Glo[v] = g.lo;
 }
 
-__global__ void k_adj_down(TreeDev T, const int32_t *nodes, int32_t cnt, const float *R, const float *C,
-                           const float *S, const float *Slo, const float *G, const float *Glo, const float *gbar,
-                           float *Sig, float *Siglo, float *dR, float *dC)
+__device__ __forceinline__ void adj_down(const TreeDev &T, int32_t v, const float *R, const float *C, const float *S,
+                                         const float *Slo, const float *G, const float *Glo, const float *gbar,
+                                         float *Sig, float *Siglo, float *dR, float *dC)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int32_t v = nodes[i], p = T.parent[v];
+    const int32_t p = T.parent[v];
     const ff up = p < 0 ? ff{0.f, 0.f} : ff{Sig[p], Siglo[p]};
     const ff g{G[v], Glo[v]};
     const ff sv = ff_norm(ff_add(up, ff_mul(R[v], g)));
@@ -211,6 +201,70 @@ __global__ void k_adj_down(TreeDev T, const int32_t *nodes, int32_t cnt, const f
         if (dC) dC[e] = ff_val(ff_add(sv, 0.5f * R[e] * gk));
     }
 }
+
+// Eq. 5: the edge weight is the largest pin weight in the downstream subtree.
+__device__ __forceinline__ void edge_w(const TreeDev &T, int32_t v, const uint16_t *pin_w, uint16_t *seg_w)
+{
+    uint16_t w = T.sink_id[v] >= 0 ? pin_w[T.sink_id[v]] : 0;
+    for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) w = max(w, seg_w[T.ch[q]]);
+    seg_w[v] = w;
+}
+
+// One launch per dense level (one thread per node), and one single-workgroup launch that
+// walks the sparse levels [h0, h1) in sweep order with barriers between levels (the nodes
+// of a level read what the previous level wrote).
+struct Levels {
+    const int32_t *nodes;   // nodes grouped by height
+    const int32_t *ptr;     // [levels + 1] group starts
+    int32_t h0, h1;
+    bool down;              // top-down: from h1 - 1 to h0
+};
+
+template <class F>
+__device__ __forceinline__ void each_node(const Levels &lv, int32_t cnt, F f)
+{
+    if (lv.h1 < 0) {   // one level: `nodes` points at it
+        const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+        if (i < cnt) f(lv.nodes[i]);
+        return;
+    }
+    for (int32_t q = 0; q < lv.h1 - lv.h0; ++q) {
+        const int32_t h = lv.down ? lv.h1 - 1 - q : lv.h0 + q;
+        for (int32_t i = lv.ptr[h] + threadIdx.x; i < lv.ptr[h + 1]; i += blockDim.x) f(lv.nodes[i]);
+        __syncthreads();
+    }
+}
+
+__global__ void k_elmore_up(TreeDev T, Levels lv, int32_t cnt, const float *R, const float *C, float *S, float *Slo)
+{
+    each_node(lv, cnt, [&](int32_t v) { elm_up(T, v, R, C, S, Slo); });
+}
+
+__global__ void k_elmore_down(TreeDev T, Levels lv, int32_t cnt, const float *R, const float *C, const float *S,
+                              const float *Slo, float *t, float *tlo, float *delay)
+{
+    each_node(lv, cnt, [&](int32_t v) { elm_down(T, v, R, C, S, Slo, t, tlo, delay); });
+}
+
+__global__ void k_adj_up(TreeDev T, Levels lv, int32_t cnt, const float *gbar, float *G, float *Glo)
+{
+    each_node(lv, cnt, [&](int32_t v) { adj_up(T, v, gbar, G, Glo); });
+}
+
+__global__ void k_adj_down(TreeDev T, Levels lv, int32_t cnt, const float *R, const float *C, const float *S,
+                           const float *Slo, const float *G, const float *Glo, const float *gbar, float *Sig,
+                           float *Siglo, float *dR, float *dC)
+{
+    each_node(lv, cnt, [&](int32_t v) { adj_down(T, v, R, C, S, Slo, G, Glo, gbar, Sig, Siglo, dR, dC); });
+}
+
+__global__ void k_edge_w(TreeDev T, Levels lv, int32_t cnt, const uint16_t *pin_w, uint16_t *seg_w)
+{
+    each_node(lv, cnt, [&](int32_t v) { edge_w(T, v, pin_w, seg_w); });
+}
+
+constexpr int kTailBlock = 1024;
+constexpr int32_t kTailNodes = 4096;   // levels this sparse run in the single-workgroup launch
 
 __global__ void k_neg(const float *x, float *y, int64_t n)
 {
@@ -287,17 +341,6 @@ __global__ void k_tiers(TreeDev T, const float *slack, const uint32_t *wns_ord, 
         }
         tier[i] = tr;
     }
-}
-
-// Eq. 5: the edge weight is the largest pin weight in the downstream subtree.
-__global__ void k_edge_w(TreeDev T, const int32_t *nodes, int32_t cnt, const uint16_t *pin_w, uint16_t *seg_w)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    const int32_t v = nodes[i];
-    uint16_t w = T.sink_id[v] >= 0 ? pin_w[T.sink_id[v]] : 0;
-    for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) w = max(w, seg_w[T.ch[q]]);
-    seg_w[v] = w;
 }
 
 __global__ void k_lambda_plain(TreeDev T, const uint16_t *seg_w, int32_t *lam)
@@ -439,25 +482,53 @@ la_status launch_rc_from_layers(la_batch *b)
     return LA_OK;
 }
 
+// Start of the run of top levels that each hold at most kTailNodes nodes; those levels go to one
+// single-workgroup launch when there are at least two of them.
+static int32_t tail_start(const la_batch *b)
+{
+    const auto &lp = b->h_level_ptr;
+    int32_t h0 = b->levels;
+    while (h0 > 0 && lp[h0] - lp[h0 - 1] <= kTailNodes) --h0;
+    return b->levels - h0 >= 2 ? h0 : b->levels;
+}
+
+// Visits the levels bottom-up (down = false) or top-down.  `launch(lv, grid, block, cnt)` issues
+// one kernel over the nodes that `lv` names.
+template <class Launch>
+static void sweep_levels(la_batch *b, bool down, Launch launch)
+{
+    const auto &lp = b->h_level_ptr;
+    const int32_t h0 = tail_start(b);
+    auto dense = [&](int32_t h) {
+        const int32_t cnt = lp[h + 1] - lp[h];
+        if (cnt) launch(Levels{b->level_nodes + lp[h], nullptr, 0, -1, false}, dim3((cnt + kBlock - 1) / kBlock),
+                        dim3(kBlock), cnt);
+    };
+    auto tail = [&]() {
+        if (h0 < b->levels)
+            launch(Levels{b->level_nodes, b->level_ptr, h0, b->levels, down}, dim3(1), dim3(kTailBlock), 0);
+    };
+    if (!down) {
+        for (int32_t h = 0; h < h0; ++h) dense(h);
+        tail();
+    } else {
+        tail();
+        for (int32_t h = h0 - 1; h >= 0; --h) dense(h);
+    }
+}
+
 la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay)
 {
     const TreeDev T = tree_view(b);
-    const auto &lp = b->h_level_ptr;
-    for (int h = 0; h < b->levels; ++h) {
-        const int32_t cnt = lp[h + 1] - lp[h];
-        if (!cnt) continue;
+    sweep_levels(b, false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
         LA_TIMED(b, "k_elmore_up", b->stream,
-                 hipLaunchKernelGGL(k_elmore_up, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                                    b->level_nodes + lp[h], cnt, R, C, b->el_S, b->el_Slo));
-    }
-    for (int h = b->levels - 1; h >= 0; --h) {
-        const int32_t cnt = lp[h + 1] - lp[h];
-        if (!cnt) continue;
+                 hipLaunchKernelGGL(k_elmore_up, g, t, 0, b->stream, T, lv, cnt, R, C, b->el_S, b->el_Slo));
+    });
+    sweep_levels(b, true, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
         LA_TIMED(b, "k_elmore_down", b->stream,
-                 hipLaunchKernelGGL(k_elmore_down, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                                    b->level_nodes + lp[h], cnt, R, C, b->el_S, b->el_Slo, b->el_t, b->el_tlo,
-                                    delay));
-    }
+                 hipLaunchKernelGGL(k_elmore_down, g, t, 0, b->stream, T, lv, cnt, R, C, b->el_S, b->el_Slo, b->el_t,
+                                    b->el_tlo, delay));
+    });
     LA_HIP(hipGetLastError());
     b->fwd_R = R;
     b->fwd_C = C;
@@ -477,23 +548,16 @@ la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *
                                     b->sinks));
         gbar = b->scratch_f;
     }
-    const auto &lp = b->h_level_ptr;
     float *Glo = b->el_Glo, *Siglo = b->el_Siglo;
-    for (int h = 0; h < b->levels; ++h) {
-        const int32_t cnt = lp[h + 1] - lp[h];
-        if (!cnt) continue;
+    sweep_levels(b, false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
         LA_TIMED(b, "k_adj_up", b->stream,
-                 hipLaunchKernelGGL(k_adj_up, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                                    b->level_nodes + lp[h], cnt, gbar, b->el_G, Glo));
-    }
-    for (int h = b->levels - 1; h >= 0; --h) {
-        const int32_t cnt = lp[h + 1] - lp[h];
-        if (!cnt) continue;
+                 hipLaunchKernelGGL(k_adj_up, g, t, 0, b->stream, T, lv, cnt, gbar, b->el_G, Glo));
+    });
+    sweep_levels(b, true, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
         LA_TIMED(b, "k_adj_down", b->stream,
-                 hipLaunchKernelGGL(k_adj_down, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                                    b->level_nodes + lp[h], cnt, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, b->el_G, Glo,
-                                    gbar, b->el_Sig, Siglo, dR, dC));
-    }
+                 hipLaunchKernelGGL(k_adj_down, g, t, 0, b->stream, T, lv, cnt, b->fwd_R, b->fwd_C, b->el_S,
+                                    b->el_Slo, b->el_G, Glo, gbar, b->el_Sig, Siglo, dR, dC));
+    });
     LA_HIP(hipGetLastError());
     b->bwd_done = true;
     return LA_OK;
@@ -514,14 +578,10 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
              hipLaunchKernelGGL(k_tiers, dim3(grid_for(b->nets)), dim3(kBlock), 0, b->stream, T, b->slack,
                                 b->wns_bits, tier));
     if (mode == LA_WEIGHTS_PLAIN) {
-        const auto &lp = b->h_level_ptr;
-        for (int h = 0; h < b->levels; ++h) {
-            const int32_t cnt = lp[h + 1] - lp[h];
-            if (!cnt) continue;
+        sweep_levels(b, false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
             LA_TIMED(b, "k_edge_w", b->stream,
-                     hipLaunchKernelGGL(k_edge_w, dim3((cnt + kBlock - 1) / kBlock), dim3(kBlock), 0, b->stream, T,
-                                        b->level_nodes + lp[h], cnt, pin_w, seg_w));
-        }
+                     hipLaunchKernelGGL(k_edge_w, g, t, 0, b->stream, T, lv, cnt, pin_w, seg_w));
+        });
         LA_TIMED(b, "k_lambda_plain", b->stream,
                  hipLaunchKernelGGL(k_lambda_plain, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, seg_w,
                                     lam));
