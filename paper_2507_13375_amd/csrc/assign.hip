@@ -24,7 +24,7 @@ inline int grid_for(int64_t n)
 
 // one thread per (node of this level and batch, entering-layer index)
 template <int NAMAX>
-__global__ void k_dp_level(DPArgs a, const int32_t *nodes, int32_t cnt)
+__global__ void __launch_bounds__(kBlock, NAMAX > 6 ? 4 : 5) k_dp_level(DPArgs a, const int32_t *nodes, int32_t cnt)
 {
     __shared__ LayerTab tb;
     load_tab(a.tab, tb);

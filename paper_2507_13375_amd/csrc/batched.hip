@@ -33,27 +33,15 @@ constexpr int32_t kFuseNets = 16384;   // batches with this many small nets comm
 constexpr int32_t kMergeNets = 64;     // batches of at most this many small nets may share a launch
 
 // DP state and per-node inputs of one LDS tile, indexed by tile-local node id.
-constexpr int kKeyPool = 16;   // three-child items per tile whose keys get an LDS slot
 
 template <int NAMAX>
 struct LdsState {
-    static constexpr bool kKeyPool = true;
     int64_t *F_;
     int32_t *S_;
     uint8_t *bt_, *sel_;
     const int16_t *chp, *chl;
     const uint4 *rec;     // len, lam, segw | dir << 16 | flags << 24, cpin
     const uint16_t *pinw_;
-    int64_t *keys_;       // [kKeyPool][kHullKids][NAMAX]
-    uint64_t *lays_;      // [kKeyPool][kHullKids]
-    int32_t *pool_;       // slots handed out in this tile
-    __device__ int grab_key_slot() const
-    {
-        const int q = atomicAdd(pool_, 1);
-        return q < gapla::kKeyPool ? q : -1;
-    }
-    __device__ int64_t *key_slot(int q) const { return keys_ + q * kHullKids * NAMAX; }
-    __device__ uint64_t *lay_slot(int q) const { return lays_ + q * kHullKids; }
     __device__ int nch(int32_t s) const { return chp[s + 1] - chp[s]; }
     __device__ int32_t ch_state(int32_t s, int q) const { return chl[chp[s] + q]; }
     __device__ int64_t &F(int32_t s, int j) const { return F_[s * NAMAX + j]; }
@@ -75,9 +63,7 @@ struct Tile {
     static constexpr int nkey = 4 * kCap + 4;                       // (height, child class) buckets
     // F holds kappa_n(l) until the DP item (n, l) reads it and overwrites it with f
     static constexpr size_t F = 0;                                  // int64 [kCap][NAMAX]
-    static constexpr size_t KPOOL = F + (size_t)kCap * NAMAX * 8;   // int64 [kKeyPool][kHullKids][NAMAX]
-    static constexpr size_t LPOOL = KPOOL + (size_t)kKeyPool * kHullKids * NAMAX * 8;   // uint64 [kKeyPool][3]
-    static constexpr size_t REC = LPOOL + (size_t)kKeyPool * kHullKids * 8;   // uint4 [kCap] per-node inputs
+    static constexpr size_t REC = F + (size_t)kCap * NAMAX * 8;     // uint4 [kCap] per-node inputs
     static constexpr size_t S = REC + (size_t)kCap * 16;            // int32 [kCap][NAMAX]
     static constexpr size_t GID = S + (size_t)kCap * NAMAX * 4;     // int32 [kCap]
     static constexpr size_t LEN = GID + (size_t)kCap * 4;           // int32 [kCap+1] prefix of segment lengths
@@ -172,8 +158,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
     uint8_t *prv = smem + TL::PRV;
     int32_t *lut = (int32_t *)(smem + TL::LUT);
 
-    // bookkeeping: [0] claim index, [1] #tiles, [2] max height of the tile, [3] key-pool slots
-    // handed out in the tile; per tile: first
+    // bookkeeping: [0] claim index, [1] #tiles, [2] max height of the tile; per tile: first
     // and end claim index, node count; per claimed net: node count, first global node,
     // first global child entry, tile-local node base and child base
     constexpr int Q = kClaimNets;
@@ -187,8 +172,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
     const int L = tb.L;
     for (int i = threadIdx.x; i < L * 2 * kNDelta; i += blockDim.x) lut[i] = a.w.lut[i];
 
-    LdsState<NAMAX> st{F,   S,   bt,  sel, chp, chl, rec, pinw, (int64_t *)(smem + TL::KPOOL),
-                       (uint64_t *)(smem + TL::LPOOL), book + 3};
+    LdsState<NAMAX> st{F, S, bt, sel, chp, chl, rec, pinw};
     // the claims of the small nets of batches tier..tier_hi (big nets run in k_batched_big);
     // batch t lists n_t claims and an end slot from cl_off[t]
     auto nclaims = [&](int32_t t) { return max(0, ba.cl_off[t + 1] - ba.cl_off[t] - 1); };
@@ -248,7 +232,6 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             for (int32_t i = threadIdx.x; i < TL::nkey; i += blockDim.x) kst[i] = 0;
             if (threadIdx.x == 0) {
                 *s_maxlev = 0;
-                book[3] = 0;   // key pool of this tile
                 lenp[0] = 0;
                 chp[nn] = (int16_t)(s_cb[i1 - 1] + s_nn[i1 - 1] - 1);
             }

@@ -67,10 +67,6 @@ struct NodeIn {
 // DP state in HBM, indexed by global node id (plain form).  Besides the DP state, a state
 // type gives the per-node inputs (`in`) and, at sinks, the pin weight.
 struct GlobalState {
-    static constexpr bool kKeyPool = false;   // three-child keys live in registers
-    __device__ int grab_key_slot() const { return -1; }
-    __device__ int64_t *key_slot(int) const { return nullptr; }
-    __device__ uint64_t *lay_slot(int) const { return nullptr; }
     const DPArgs &a;
     __device__ GlobalState(const DPArgs &a_) : a(a_) {}
     __device__ int nch(int32_t s) const { return a.T.ch_ptr[s + 1] - a.T.ch_ptr[s]; }
@@ -137,7 +133,7 @@ __device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb
     return s;
 }
 
-// children per node handled by the self-hull stack enumeration (more: full enumeration)
+// children per node handled by the hull-candidate order (more: full enumeration)
 constexpr int kHullKids = 3;
 
 // Per-child inputs that do not depend on the parent's layer.
@@ -238,28 +234,27 @@ __device__ __forceinline__ uint32_t hull_min_mask(const int64_t (&ky)[NAMAX], co
     return m;
 }
 
-// For each layer index jj of a child: the highest lower layer whose key is <= its key and the
-// lowest higher layer whose key is smaller (-1 / 16 when there is none), packed 5 bits per
-// index as value + 1.  Layer jj is the child's lowest-layer key minimum inside a window
-// [b, t] that holds it exactly when lower < b and t < upper.
+// For each layer index jj of a child (layers ascending, n of them), 8 bits at bit 8*jj: the
+// highest lower layer whose key is <= its key, plus one (0: none), and at bit 8*jj + 4 the
+// lowest higher layer whose key is smaller, minus one (15: none).  Layer jj is the child's
+// lowest-layer key minimum inside a window [b, t] that holds it exactly when the first field
+// is <= b and t <= the second.
 template <int NAMAX>
-__device__ __forceinline__ void block_bounds(const int64_t (&ky)[NAMAX], const int (&ly)[NAMAX], int n,
-                                             uint64_t &lowp, uint64_t &upp)
+__device__ __forceinline__ uint64_t block_bounds(const int64_t (&ky)[NAMAX], const int (&ly)[NAMAX], int n)
 {
-    lowp = 0;
-    upp = 0;
+    uint64_t p = 0;
 #pragma unroll
     for (int jj = 0; jj < NAMAX; ++jj) {
-        int lb = -1, ub = 16;
+        int lb = 0, ub = 15;
 #pragma unroll
         for (int i = 0; i < jj; ++i)
-            if (i < n && ky[i] <= ky[jj]) lb = ly[i];
+            if (i < n && ky[i] <= ky[jj]) lb = ly[i] + 1;
 #pragma unroll
         for (int i = NAMAX - 1; i > jj; --i)
-            if (i < n && ky[i] < ky[jj]) ub = ly[i];
-        lowp |= (uint64_t)(lb + 1) << (5 * jj);
-        upp |= (uint64_t)(ub + 1) << (5 * jj);
+            if (i < n && ky[i] < ky[jj]) ub = ly[i] - 1;
+        p |= (uint64_t)(lb | ub << 4) << (8 * jj);
     }
+    return p;
 }
 
 // Best candidate so far; `better` applies the (f', b, t) order of the full enumeration.
@@ -302,15 +297,17 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
     const int k = st.nch(s);
 
     Best best;
-    // f' of stack [b,t] given the children's summed f-contributions and capacitances
-    auto eval = [&](int b, int t, int64_t sumV, int64_t sumZ) -> bool {
+    // f' and X of stack [b,t] given the children's summed f-contributions and capacitances
+    // (at the root every segment term is zero)
+    auto price = [&](int b, int t, int64_t sumV, int64_t sumZ, uint32_t &X) -> int64_t {
         const uint32_t Sn = (uint32_t)(cpin + sumZ);
-        int64_t fp = a.w.w_via * (t - b) + sumV + pin_term;
-        uint32_t X = 2 * Sn;
-        if (!root) {
-            X = Cs + 2 * Sn;
-            fp += own_const + wd(Tq(segw, Rw, X)) + wd((int64_t)(mul_u32(lam, 2 * (Cs + Sn)) >> 11));
-        }
+        X = Cs + 2 * Sn;
+        return a.w.w_via * (t - b) + sumV + pin_term + own_const + wd(Tq(segw, Rw, X)) +
+               wd((int64_t)(mul_u32(lam, 2 * (Cs + Sn)) >> 11));
+    };
+    auto eval = [&](int b, int t, int64_t sumV, int64_t sumZ) -> bool {
+        uint32_t X;
+        const int64_t fp = price(b, t, sumV, sumZ, X);
         if (best.better(fp, b, t)) {
             best.fp = fp;
             best.X = X;
@@ -341,221 +338,109 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
             ky[jj] = jj < n0 ? st.F(c0.cs, jj) + wd(Tq(c0.w, rvia_d(tb, l, ly[jj]), xq[jj])) : 0;
         }
         const uint32_t m = hull_min_mask<NAMAX>(ky, ly, n0, lo, hi);
+        // every layer is priced (independent chains, no branches), then the (f', b, t)
+        // minimum over the candidates is kept
         int sel0 = 0;
 #pragma unroll
-        for (int jj = 0; jj < NAMAX; ++jj)
-            if ((m >> jj) & 1u) {
-                const uint32_t Z = (xq[jj] + (uint32_t)(tb.c[ly[jj]] * c0.len)) >> 1;
-                const int64_t V = ky[jj] - wd((int64_t)(mul_u32(c0.lam, 2 * Z) >> 11));
-                if (eval(min(lo, ly[jj]), max(hi, ly[jj]), V, Z)) sel0 = ly[jj];
+        for (int jj = 0; jj < NAMAX; ++jj) {
+            const uint32_t Z = (xq[jj] + (uint32_t)(tb.c[ly[jj]] * c0.len)) >> 1;
+            const int64_t V = ky[jj] - wd((int64_t)(mul_u32(c0.lam, 2 * Z) >> 11));
+            const int b = min(lo, ly[jj]), t = max(hi, ly[jj]);
+            uint32_t X;
+            const int64_t fp = price(b, t, V, Z, X);
+            if (((m >> jj) & 1u) && best.better(fp, b, t)) {
+                best.fp = fp;
+                best.X = X;
+                best.b = b;
+                best.t = t;
+                sel0 = ly[jj];
             }
+        }
         st.sel(c0.cs, j) = (uint8_t)sel0;
         done = true;
-    } else if (SMALLK && a.w.w_via > 0 && k == 2) {
-        // ---- two children: hull candidates ------------------------------------------------
-        // a pair of child layers names one hull; it is a candidate when each choice is its
-        // child's key minimum inside that hull (block bounds make that test O(1))
-        // packs: child q's layers 4 bits each with its layer count at bit 32; bounds 5 bits each
-        ChildIn cin[2];
-        uint64_t lyp[2], lowp[2], upp[2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            cin[q] = child_in(st, s, q);
-            const int nq = tb.nA[cin[q].dir];
-            int64_t ky[NAMAX];
-            int ly[NAMAX];
-            lyp[q] = (uint64_t)nq << 32;
-#pragma unroll
-            for (int jj = 0; jj < NAMAX; ++jj) {
-                ly[jj] = tb.lay[cin[q].dir][jj < nq ? jj : 0];
-                ky[jj] = jj < nq ? child_key_j(tb, st, wd, cin[q], l, ly[jj], jj) : 0;
-                lyp[q] |= (uint64_t)ly[jj] << (4 * jj);
-            }
-            block_bounds<NAMAX>(ky, ly, nq, lowp[q], upp[q]);
-        }
-        auto fld = [](uint64_t p, int jj, int w) { return (int)((p >> (w * jj)) & ((1u << w) - 1u)); };
-        uint64_t mask = 0;
-#pragma unroll
-        for (int j1 = 0; j1 < NAMAX; ++j1)
-#pragma unroll
-            for (int j2 = 0; j2 < NAMAX; ++j2)
-                if (j1 < (int)(lyp[0] >> 32) && j2 < (int)(lyp[1] >> 32)) {
-                    const int L1 = fld(lyp[0], j1, 4), L2 = fld(lyp[1], j2, 4);
-                    const int b = min(lo, min(L1, L2)), t = max(hi, max(L1, L2));
-                    // stored bounds are value + 1: lower + 1 <= b and t + 1 < upper + 1
-                    if (fld(lowp[0], j1, 5) <= b && fld(lowp[1], j2, 5) <= b && t + 1 < fld(upp[0], j1, 5) &&
-                        t + 1 < fld(upp[1], j2, 5))
-                        mask |= 1ull << (j1 * NAMAX + j2);
-                }
-        int sel0 = 0, sel1 = 0;
-        while (mask) {
-            const int p = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            const int j1 = p / NAMAX, j2 = p - (p / NAMAX) * NAMAX;
-            const int L1 = tb.lay[cin[0].dir][j1], L2 = tb.lay[cin[1].dir][j2];
-            const ChildVZ c1 = child_vz_j(tb, st, wd, cin[0], l, L1, j1);
-            const ChildVZ c2 = child_vz_j(tb, st, wd, cin[1], l, L2, j2);
-            if (eval(min(lo, min(L1, L2)), max(hi, max(L1, L2)), c1.V + c2.V, (int64_t)c1.Z + c2.Z)) {
-                sel0 = L1;
-                sel1 = L2;
-            }
-        }
-        st.sel(cin[0].cs, j) = (uint8_t)sel0;
-        st.sel(cin[1].cs, j) = (uint8_t)sel1;
-        done = true;
-    } else if (a.w.w_via > 0 && k <= kHullKids && St::kKeyPool) {
-        // ---- three children, keys in a pool slot of the state (LDS) ----------------------
-        // Same stacks as below, with every child's keys and packed layers held in a slot of
-        // the workgroup's pool instead of registers; a full pool leaves the item to the full
-        // enumeration.
-        const int slot = st.grab_key_slot();
-        if (slot >= 0) {
-            int64_t *kq = st.key_slot(slot);   // [kHullKids][NAMAX]
-            uint64_t *lq = st.lay_slot(slot);  // [kHullKids]
-            uint32_t lmask = 0;
-            for (int q = 0; q < k; ++q) {
-                const ChildIn cq = child_in(st, s, q);
-                const int nq = tb.nA[cq.dir];
-                uint64_t pk = (uint64_t)nq << 32;
-                for (int jj = 0; jj < nq; ++jj) {
-                    const int lc = tb.lay[cq.dir][jj];
-                    pk |= (uint64_t)lc << (4 * jj);
-                    kq[q * NAMAX + jj] = child_key_j(tb, st, wd, cq, l, lc, jj);
-                    lmask |= 1u << lc;
-                }
-                lq[q] = pk;
-            }
-            uint32_t sel_pack = 0;
-            for (int b = lo; b >= 0; --b) {
-                if (b != lo && !((lmask >> b) & 1u)) continue;
-                for (int t = hi; t < L; ++t) {
-                    if (t != hi && !((lmask >> t) & 1u)) continue;
-                    bool ok = true;
-                    int hb = lo, ht = hi;
-                    uint32_t chosen = 0;   // per child: layer index (bits 4q..4q+3)
-                    for (int q = 0; q < k && ok; ++q) {
-                        const uint64_t pk = lq[q];
-                        const int nq = (int)(pk >> 32);
-                        int bl = -1, bj = 0;
-                        int64_t bk = 0;
-                        for (int jj = 0; jj < nq; ++jj) {
-                            const int lc = (int)((pk >> (4 * jj)) & 15u);
-                            const int64_t key = kq[q * NAMAX + jj];
-                            if (lc >= b && lc <= t && (bl < 0 || key < bk)) {
-                                bl = lc;
-                                bj = jj;
-                                bk = key;
-                            }
-                        }
-                        ok = bl >= 0;
-                        chosen |= (uint32_t)bj << (4 * q);
-                        hb = min(hb, bl < 0 ? hb : bl);
-                        ht = max(ht, bl);
-                    }
-                    if (!ok || hb != b || ht != t) continue;
-                    int64_t sumV = 0, sumZ = 0;
-                    uint32_t layers = 0;
-                    for (int q = 0; q < k; ++q) {
-                        const int jq = (int)((chosen >> (4 * q)) & 15u);
-                        const int lc = (int)((lq[q] >> (4 * jq)) & 15u);
-                        const ChildVZ c = child_vz_j(tb, st, wd, child_in(st, s, q), l, lc, jq);
-                        sumV += c.V;
-                        sumZ += c.Z;
-                        layers |= (uint32_t)lc << (4 * q);
-                    }
-                    if (eval(b, t, sumV, sumZ)) sel_pack = layers;
-                }
-            }
-            for (int q = 0; q < k; ++q) st.sel(st.ch_state(s, q), j) = (uint8_t)((sel_pack >> (4 * q)) & 15u);
-            done = true;
-        }
-    } else if (a.w.w_via > 0 && k <= kHullKids) {
-        // ---- three children: self-hull stacks ---------------------------------------------
-        // Every child's keys are computed once, kept as 32-bit offsets from that child's
-        // smallest key (an item whose offsets do not fit takes the full enumeration).  A
-        // stack [b,t] is costed only when it is the hull of l, the pin layer and the
-        // children's key minima inside it; b and t must then be lo / hi or a child's routable
-        // layer.  Child q's layers are packed 4 bits each, its layer count at bit 32.
-        uint32_t dk[kHullKids][NAMAX];
-        uint64_t lyp[kHullKids];
-        uint32_t lmask = 0;
-        bool fits = true;
+    } else if (a.w.w_via > 0 && k >= 2 && k <= kHullKids && (SMALLK || k > 2)) {
+        // ---- two or three children: hull candidates ---------------------------------------
+        // A winning stack is the hull of lo, hi and the children's choices, each choice being
+        // its child's key minimum inside that hull.  Such a choice is also the minimum inside
+        // the smaller hull of lo, hi and itself alone, so each child's candidates are its
+        // single-child mask; the block bounds then test a combination in O(1) per child.
+        // per child: layers 4 bits per index, block bounds 8 bits per index, candidate mask
+        uint32_t lyp[kHullKids], cand[kHullKids];
+        uint64_t bnd[kHullKids];
+        ChildIn cin[kHullKids];
 #pragma unroll
         for (int q = 0; q < kHullKids; ++q) {
             lyp[q] = 0;
+            bnd[q] = 0;
+            cand[q] = 1;   // children beyond k: one pass that tests nothing
+            cin[q] = ChildIn{};
             if (q < k) {
                 const ChildIn cq = child_in(st, s, q);
-                const int ncq = tb.nA[cq.dir];
-                lyp[q] = (uint64_t)ncq << 32;
+                cin[q] = cq;
+                const int nq = tb.nA[cq.dir];
                 int64_t ky[NAMAX];
-                int64_t base = INT64_MAX;
+                int ly[NAMAX];
 #pragma unroll
                 for (int jj = 0; jj < NAMAX; ++jj) {
-                    const int lq = tb.lay[cq.dir][jj < ncq ? jj : 0];
-                    lyp[q] |= (uint64_t)lq << (4 * jj);
-                    ky[jj] = jj < ncq ? child_key_j(tb, st, wd, cq, l, lq, jj) : 0;
-                    if (jj < ncq) {
-                        lmask |= 1u << lq;
-                        base = min(base, ky[jj]);
-                    }
+                    ly[jj] = tb.lay[cq.dir][jj < nq ? jj : 0];
+                    ky[jj] = jj < nq ? child_key_j(tb, st, wd, cq, l, ly[jj], jj) : 0;
+                    lyp[q] |= (uint32_t)ly[jj] << (4 * jj);
                 }
-#pragma unroll
-                for (int jj = 0; jj < NAMAX; ++jj) {
-                    const uint64_t d = (uint64_t)(ky[jj] - base);
-                    fits = fits && (jj >= ncq || d <= 0xffffffffull);
-                    dk[q][jj] = (uint32_t)d;
-                }
+                bnd[q] = block_bounds<NAMAX>(ky, ly, nq);
+                cand[q] = hull_min_mask<NAMAX>(ky, ly, nq, lo, hi);
             }
         }
-        if (fits) {
-            uint8_t sel_q[kHullKids] = {};
-            for (int b = lo; b >= 0; --b) {
-                if (b != lo && !((lmask >> b) & 1u)) continue;
-                for (int t = hi; t < L; ++t) {
-                    if (t != hi && !((lmask >> t) & 1u)) continue;
-                    bool ok = true;
-                    int hb = lo, ht = hi;
-                    int chosen[kHullKids];
+        auto lay_of = [&](int q, int jj) { return (int)((lyp[q] >> (4 * jj)) & 15u); };
+        // child q's choice jj passes inside [b, t]
+        auto inside = [&](int q, int jj, int b, int t) {
+            const uint32_t f = (uint32_t)(bnd[q] >> (8 * jj));
+            return (int)(f & 15u) <= b && t <= (int)((f >> 4) & 15u);
+        };
+        // Pairs of the first two children's candidates that pass inside their own hull with
+        // lo and hi.  For two children that is the whole test; a third child can only widen
+        // the hull, and a minimum inside the wider hull is one inside the narrower, so for
+        // three it is a necessary condition, completed per third choice below.
+        static_assert(kHullKids == 3 && NAMAX * NAMAX <= 64, "pair mask");
+        uint64_t pm = 0;
+        for (uint32_t m0 = cand[0]; m0; m0 &= m0 - 1) {
+            const int j0 = __ffs(m0) - 1;
+            const int L0 = lay_of(0, j0);
 #pragma unroll
-                    for (int q = 0; q < kHullKids; ++q) {
-                        chosen[q] = 0;
-                        if (q < k) {
-                            int bl = -1;
-                            uint32_t bk = 0;
-#pragma unroll
-                            for (int jj = 0; jj < NAMAX; ++jj) {
-                                const int lq = (int)((lyp[q] >> (4 * jj)) & 15u);
-                                if (jj < (int)(lyp[q] >> 32) && lq >= b && lq <= t && (bl < 0 || dk[q][jj] < bk)) {
-                                    bl = lq;
-                                    bk = dk[q][jj];
-                                }
-                            }
-                            ok = ok && bl >= 0;
-                            chosen[q] = bl;
-                            hb = min(hb, bl < 0 ? hb : bl);
-                            ht = max(ht, bl);
-                        }
-                    }
-                    if (!ok || hb != b || ht != t) continue;
-                    int64_t sumV = 0, sumZ = 0;
-#pragma unroll
-                    for (int q = 0; q < kHullKids; ++q)
-                        if (q < k) {
-                            const ChildVZ c = child_vz(tb, st, wd, child_in(st, s, q), l, chosen[q]);
-                            sumV += c.V;
-                            sumZ += c.Z;
-                        }
-                    if (eval(b, t, sumV, sumZ)) {
-#pragma unroll
-                        for (int q = 0; q < kHullKids; ++q) sel_q[q] = (uint8_t)chosen[q];
-                    }
-                }
+            for (int j1 = 0; j1 < NAMAX; ++j1) {
+                const int L1 = lay_of(1, j1);
+                const int b = min(lo, min(L0, L1)), t = max(hi, max(L0, L1));
+                const bool ok = ((cand[1] >> j1) & 1u) && inside(0, j0, b, t) && inside(1, j1, b, t);
+                pm |= (uint64_t)ok << (j0 * NAMAX + j1);
+            }
+        }
+        uint32_t sel_pack = 0;   // chosen child layers, 4 bits per child
+        while (pm) {
+            const int p = __ffsll((unsigned long long)pm) - 1;
+            pm &= pm - 1;
+            const int j0 = p / NAMAX, j1 = p - (p / NAMAX) * NAMAX;
+            const int L0 = lay_of(0, j0), L1 = lay_of(1, j1);
+            const int b01 = min(lo, min(L0, L1)), t01 = max(hi, max(L0, L1));
+            const ChildVZ c0 = child_vz_j(tb, st, wd, cin[0], l, L0, j0);
+            const ChildVZ c1 = child_vz_j(tb, st, wd, cin[1], l, L1, j1);
+            if (k == 2) {
+                if (eval(b01, t01, c0.V + c1.V, (int64_t)c0.Z + c1.Z)) sel_pack = (uint32_t)(L0 | L1 << 4);
+                continue;
             }
 #pragma unroll
-            for (int q = 0; q < kHullKids; ++q)
-                if (q < k) st.sel(st.ch_state(s, q), j) = sel_q[q];
-            done = true;
+            for (int j2 = 0; j2 < NAMAX; ++j2) {
+                const int L2 = lay_of(2, j2);
+                const int b = min(b01, L2), t = max(t01, L2);
+                if (!((cand[2] >> j2) & 1u) || !inside(0, j0, b, t) || !inside(1, j1, b, t) || !inside(2, j2, b, t))
+                    continue;
+                const ChildVZ c2 = child_vz_j(tb, st, wd, cin[2], l, L2, j2);
+                if (eval(b, t, c0.V + c1.V + c2.V, (int64_t)c0.Z + c1.Z + c2.Z))
+                    sel_pack = (uint32_t)(L0 | L1 << 4 | L2 << 8);
+            }
         }
+#pragma unroll
+        for (int q = 0; q < kHullKids; ++q)
+            if (q < k) st.sel(st.ch_state(s, q), j) = (uint8_t)((sel_pack >> (4 * q)) & 15u);
+        done = true;
     }
     if (!done) {
         // ---- full enumeration: every stack, each child rescanned ------------------------
