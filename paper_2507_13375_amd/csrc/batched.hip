@@ -278,6 +278,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             // (height, class) order; kst[q] ends as the end of bucket q = start of q+1.  The
             // step -> segment map of the gather borrows sel, which the DP fills only later.
             const int32_t steps = lenp[nn];
+            static_assert(kCap <= 256, "the step map holds tile-local node ids in one byte");
             uint8_t *smap = sel;
             const bool mapped = steps <= kCap * NAMAX;
             for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
