@@ -150,8 +150,13 @@ la_status la_assign(la_batch *b, const la_weights *w, int32_t *history, uint8_t 
     if (s != LA_OK) return s;
     const int32_t *lut = w->cong_lut ? w->cong_lut : b->lut;
     if (b->nodes == 0) return LA_OK;
-    s = (w->form == LA_FORM_PLAIN) ? assign_plain(b, w, history, lut, out_layers)
-                                   : assign_batched(b, w, history, lut, out_layers);
+    // the kernels read and update the history in the plane layout
+    s = grid_to_planes(b, history, b->Hi);
+    if (s != LA_OK) return s;
+    s = (w->form == LA_FORM_PLAIN) ? assign_plain(b, w, b->Hi, lut, out_layers)
+                                   : assign_batched(b, w, b->Hi, lut, out_layers);
+    if (s != LA_OK) return s;
+    s = planes_to_grid(b, b->Hi, history);
     if (s != LA_OK) return s;
     return launch_rc_from_layers(b);
 }
@@ -165,8 +170,7 @@ la_status la_vias(la_batch *b, uint8_t *out)
 la_status la_demand(la_batch *b, int32_t *out)
 {
     if (!b || !out) return set_error(LA_ERR_INVALID_ARG, "la_demand: NULL argument");
-    LA_HIP(hipMemcpyAsync(out, b->D, b->E * sizeof(int32_t), hipMemcpyDeviceToDevice, b->stream));
-    return LA_OK;
+    return planes_to_grid(b, b->D, out);
 }
 
 la_status la_reset(la_batch *b)
@@ -317,7 +321,7 @@ void la_free_batch(la_batch *b)
                     b->el_Slo, b->el_t, b->el_tlo, b->el_G, b->el_Glo, b->el_Sig, b->el_Siglo, b->slack,
                     b->scratch_f, b->wns_bits, b->red, b->net_big, b->bn_order, b->bn_lvl, b->bn_lvl_off,
                     b->bn_nlev, b->tier_nets, b->tier_off, b->tier_cur, b->tier_cnt, b->claim,
-                    b->cl_pre, b->cl_blk, b->cl_start, b->cl_off, b->D_alt};
+                    b->cl_pre, b->cl_blk, b->cl_start, b->cl_off, b->D_alt, b->Hi};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);

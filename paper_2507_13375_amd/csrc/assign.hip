@@ -70,6 +70,20 @@ __global__ void k_trace_level(DPArgs a, const int32_t *nodes, int32_t cnt, uint8
     append_change(ChangeList{chg_node, chg_old, chg_new, chg_count}, changed, n, old_l, (uint8_t)ln);
 }
 
+// API grid order ((y * X + x) * L + l) <-> the plane layout of grid_index
+__global__ void k_grid_perm(LayerTab tab, const int32_t *src, int32_t *dst, int64_t E, int to_planes)
+{
+    __shared__ LayerTab tb;
+    load_tab(tab, tb);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(e % tb.L);
+        const int32_t cell = (int32_t)(e / tb.L);
+        const int32_t i = grid_index(tb, l, plane_pos(tb, tb.dir[l], cell % tb.X, cell / tb.X));
+        if (to_planes) dst[i] = src[e];
+        else dst[e] = src[i];
+    }
+}
+
 __global__ void k_zero_i32(int32_t *p, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -84,11 +98,10 @@ __global__ void k_commit(TreeDev T, LayerTab tab, const int32_t *chg_node, const
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
         const int32_t n = chg_node[i];
         const int o = chg_old[i], nw = chg_new[i];
-        const int32_t step = T.dir[n] == 0 ? tab.L : tab.X * tab.L;
-        int32_t g = T.g0[n];
-        for (int32_t k = 0; k < T.len[n]; ++k, g += step) {
-            if (o != 255) atomicAdd(&D[g + o], -1);
-            atomicAdd(&D[g + nw], 1);
+        const int32_t q = T.g0[n];
+        for (int32_t k = 0; k < T.len[n]; ++k) {
+            if (o != 255) atomicAdd(&D[grid_index(tab, o, q + k)], -1);
+            atomicAdd(&D[grid_index(tab, nw, q + k)], 1);
         }
     }
 }
@@ -230,6 +243,24 @@ la_status commit_changed(la_batch *b, int32_t *D)
     LA_TIMED(b, "k_commit", b->stream,
              hipLaunchKernelGGL(k_commit, dim3(1024), dim3(kBlock), 0, b->stream, tree_view(b), b->tab, b->chg_node,
                                 b->chg_old, b->chg_new, b->chg_count, D));
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+la_status grid_to_planes(la_batch *b, const int32_t *api, int32_t *planes)
+{
+    LA_TIMED(b, "k_grid_perm", b->stream,
+             hipLaunchKernelGGL(k_grid_perm, dim3(grid_for(b->E)), dim3(kBlock), 0, b->stream, b->tab, api, planes,
+                                b->E, 1));
+    LA_HIP(hipGetLastError());
+    return LA_OK;
+}
+
+la_status planes_to_grid(la_batch *b, const int32_t *planes, int32_t *api)
+{
+    LA_TIMED(b, "k_grid_perm", b->stream,
+             hipLaunchKernelGGL(k_grid_perm, dim3(grid_for(b->E)), dim3(kBlock), 0, b->stream, b->tab, planes, api,
+                                b->E, 0));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }

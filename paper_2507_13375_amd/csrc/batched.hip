@@ -67,7 +67,7 @@ struct Tile {
     static constexpr size_t S = REC + (size_t)kCap * 16;            // int32 [kCap][NAMAX]
     static constexpr size_t GID = S + (size_t)kCap * NAMAX * 4;     // int32 [kCap]
     static constexpr size_t LEN = GID + (size_t)kCap * 4;           // int32 [kCap+1] prefix of segment lengths
-    static constexpr size_t G0 = LEN + (size_t)(kCap + 1) * 4;      // int32 [kCap] first GCell edge (layer 0)
+    static constexpr size_t G0 = LEN + (size_t)(kCap + 1) * 4;      // int32 [kCap] in-plane position of the first edge
     static constexpr size_t KEYS = G0 + (size_t)kCap * 4;           // int32 [nkey] bucket starts
     static constexpr size_t BOOK = KEYS + (size_t)nkey * 4;         // int32 [kBook]
     static constexpr size_t PAR = BOOK + (size_t)kBook * 4;         // int16 [kCap]
@@ -178,7 +178,6 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
     auto nclaims = [&](int32_t t) { return max(0, ba.cl_off[t + 1] - ba.cl_off[t] - 1); };
     int32_t ncl = 0;
     for (int32_t t = ba.tier; t <= ba.tier_hi; ++t) ncl += nclaims(t);
-    const int32_t Xl = tb.X * L;
 
     for (;;) {
         if (threadIdx.x == 0) *s_base = atomicAdd(ba.ctr, 1);
@@ -303,18 +302,19 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                     u = lo_;
                 }
                 const int d = fld[u] >> 4;
-                const int32_t g = g0a[u] + (pidx - lenp[u]) * (d == 0 ? L : Xl);
+                const int32_t q = g0a[u] + (pidx - lenp[u]);   // in-plane position of this edge
                 const int self = prv[u];
                 const int na = tb.nA[d];
 #pragma unroll
                 for (int jj = 0; jj < NAMAX; ++jj) {
                     if (jj < na) {
                         const int l = tb.lay[d][jj];
-                        const int32_t cap = a.caps[g + l];
-                        int32_t dd = a.D[g + l] - (self == l ? 1 : 0) - cap;
+                        const int32_t g = grid_index(tb, l, q);
+                        const int32_t cap = a.caps[g];
+                        int32_t dd = a.D[g] - (self == l ? 1 : 0) - cap;
                         dd = dd < kDeltaMin ? kDeltaMin : (dd > kDeltaMin + kNDelta - 1 ? kDeltaMin + kNDelta - 1 : dd);
                         const int64_t v = (int64_t)lut[(l * 2 + (cap > 0 ? 0 : 1)) * kNDelta + dd - kDeltaMin] +
-                                          (int64_t)a.H[g + l];
+                                          (int64_t)a.H[g];
                         atomicAdd((unsigned long long *)&kap[u * NAMAX + jj], (unsigned long long)v);
                     }
                 }
@@ -394,11 +394,10 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                         // commit the move along the segment's GCell edges (the DP of this batch
                         // reads the other demand buffer)
                         if (changed) {
-                            const int32_t step = (fld[u] >> 4) == 0 ? L : Xl;
-                            int32_t g = g0a[u];
-                            for (int32_t k = lenp[u + 1] - lenp[u]; k > 0; --k, g += step) {
-                                if (old_l != 255) atomicAdd(&ba.Dw[g + old_l], -1);
-                                atomicAdd(&ba.Dw[g + ln], 1);
+                            const int32_t q = g0a[u], len = lenp[u + 1] - lenp[u];
+                            for (int32_t k = 0; k < len; ++k) {
+                                if (old_l != 255) atomicAdd(&ba.Dw[grid_index(tb, old_l, q + k)], -1);
+                                atomicAdd(&ba.Dw[grid_index(tb, ln, q + k)], 1);
                             }
                         }
                     } else {

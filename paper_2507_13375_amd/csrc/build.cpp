@@ -305,7 +305,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
                 max_len = std::max<int64_t>(max_len, len[u]);
                 const int32_t xl = dir[u] == 0 ? std::min(xs[p], xs[u]) : xs[u];
                 const int32_t yl = dir[u] == 0 ? ys[u] : std::min(ys[p], ys[u]);
-                g0[u] = (int32_t)(((int64_t)yl * X + xl) * L);
+                g0[u] = plane_pos(tab, dir[u], xl, yl);
             }
             sum_cpin += cpin[u];
         }
@@ -433,7 +433,12 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     }
     std::vector<int32_t> budget(nets->net_budget_fs, nets->net_budget_fs + N);
     std::vector<int32_t> rdrv(nets->net_rdrv_mohm, nets->net_rdrv_mohm + N);
-    std::vector<uint8_t> caps(edge_caps, edge_caps + b->E);
+    // capacities in the plane layout
+    std::vector<uint8_t> caps(b->E);
+    for (int32_t y = 0; y < Y; ++y)
+        for (int32_t x = 0; x < X; ++x)
+            for (int l = 0; l < L; ++l)
+                caps[grid_index(tab, l, plane_pos(tab, tab.dir[l], x, y))] = edge_caps[((int64_t)y * X + x) * L + l];
     la_status s = LA_OK;
     auto chk = [&](la_status r) {
         if (s == LA_OK && r != LA_OK) s = r;
@@ -478,6 +483,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->caps, caps));
     chk(alloc(&b->D, b->E));
     chk(alloc(&b->D_alt, b->E));
+    chk(alloc(&b->Hi, b->E));
     chk(alloc(&b->cur_layer, M));
     chk(alloc(&b->vlo, M));
     chk(alloc(&b->vhi, M));

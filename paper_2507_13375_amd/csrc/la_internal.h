@@ -37,6 +37,18 @@ struct LayerTab {
     int32_t r_avg[2], c_avg[2];     // integer averages over routable layers per direction
 };
 
+// Grid arrays inside the library are stored one plane per layer, each plane ordered along
+// the layer's direction: horizontal layers row by row (x fastest), vertical layers column by
+// column (y fastest).  The GCell edges a segment covers on one layer are then consecutive
+// words.  The API's arrays use (y * X + x) * L + l; la_assign and la_demand convert.
+// index in the plane layout of the edge at in-plane position q of layer l
+__host__ __device__ inline int32_t grid_index(const LayerTab &t, int l, int32_t q) { return l * t.X * t.Y + q; }
+// in-plane position of GCell (x, y) on a layer of direction d
+__host__ __device__ inline int32_t plane_pos(const LayerTab &t, int d, int32_t x, int32_t y)
+{
+    return d == 0 ? y * t.X + x : x * t.Y + y;
+}
+
 // Integer weights handed to the DP kernels.
 struct DPWeights {
     int64_t w_cong, w_cap, w_d, w_via;
@@ -55,7 +67,8 @@ struct TreeDev {
     const int32_t *net;             // node -> net
     const int32_t *net_ptr;         // [nets+1]
     const int32_t *len;             // segment length (GCells), 0 at roots
-    const int32_t *g0;              // grid index (layer 0) of the first GCell edge covered
+    const int32_t *g0;              // in-plane index of the first GCell edge covered: the edge at
+                                    // step k on layer l is grid_index(l, g0 + k)
     const uint8_t *dir;             // 0 H, 1 V (root: 0)
     const uint8_t *flags;
     const int32_t *cpin;            // aF, sinks only
@@ -94,8 +107,9 @@ struct la_batch {
     int32_t *level_nodes = nullptr, *level_ptr = nullptr, *height = nullptr;
     uint8_t *caps = nullptr;
 
-    // negotiation state; D_alt receives a batch's demand moves while its DP reads D (batched form)
-    int32_t *D = nullptr, *D_alt = nullptr;
+    // negotiation state; D_alt receives a batch's demand moves while its DP reads D (batched form).
+    // caps, D, D_alt and Hi (the history during la_assign) use the plane layout of grid_index.
+    int32_t *D = nullptr, *D_alt = nullptr, *Hi = nullptr;
     uint8_t *cur_layer = nullptr, *vlo = nullptr, *vhi = nullptr;
     bool has_prev = false;
 
@@ -195,6 +209,9 @@ la_status launch_rc_pre(la_batch *b);
 la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay);
 la_status elmore_backward(la_batch *b, const float *gbar_neg_dslack, bool from_dslack, float *dR, float *dC);
 la_status commit_changed(la_batch *b, int32_t *D);
+// conversions between the API's grid order and the plane layout (E int32 each)
+la_status grid_to_planes(la_batch *b, const int32_t *api, int32_t *planes);
+la_status planes_to_grid(la_batch *b, const int32_t *planes, int32_t *api);
 la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t hist_inc);
 la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut);
 
