@@ -371,41 +371,47 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                 }
                 __syncthreads();
             }
-            // ---- trace-back top-down -------------------------------------------------------
+            // ---- trace-back top-down: entering-layer indices, in LDS -------------------------
             for (int32_t h = maxlev; h >= 0; --h) {
                 const int32_t lb = h == 0 ? 0 : kst[4 * h - 1], le = kst[4 * h + 3];
-                for (int32_t it0 = lb; it0 < le; it0 += blockDim.x) {
-                    const int32_t it = it0 + threadIdx.x;
-                    bool changed = false;
-                    uint8_t old_l = 0;
-                    int ln = 0;
-                    int32_t n = 0;
-                    int32_t u = 0;
-                    if (it < le) {
-                        u = order[it];
-                        n = gid[u];
-                        const int32_t pu = par[u];
-                        const int jp = (pu < 0 || par[pu] < 0) ? 0 : ent[pu];
-                        // the previous layer was staged (prv) when this round has one
-                        ent[u] = (uint8_t)trace_node(tb, st, u, n, jp, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers,
-                                                     ba.has_prev, &ln, &changed, &old_l, ba.has_prev ? prv[u] : 0);
-                    }
-                    if (ba.Dw) {
-                        // commit the move along the segment's GCell edges (the DP of this batch
-                        // reads the other demand buffer)
-                        if (changed) {
-                            const int32_t q = g0a[u], len = lenp[u + 1] - lenp[u];
-                            for (int32_t k = 0; k < len; ++k) {
-                                if (old_l != 255) atomicAdd(&ba.Dw[grid_index(tb, old_l, q + k)], -1);
-                                atomicAdd(&ba.Dw[grid_index(tb, ln, q + k)], 1);
-                            }
-                        }
-                    } else {
-                        append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
-                    }
+                for (int32_t it = lb + threadIdx.x; it < le; it += blockDim.x) {
+                    const int32_t u = order[it];
+                    const int32_t pu = par[u];
+                    int ln;
+                    ent[u] = (uint8_t)trace_choice(tb, st, u, (pu < 0 || par[pu] < 0) ? 0 : ent[pu], pu < 0, &ln);
                 }
                 __syncthreads();
             }
+            // ---- layers, via spans and demand moves of the tile, in node order --------------
+            for (int32_t u0 = 0; u0 < nn; u0 += blockDim.x) {
+                const int32_t u = u0 + threadIdx.x;
+                bool changed = false;
+                uint8_t old_l = 0;
+                int ln = 0;
+                int32_t n = 0;
+                if (u < nn) {
+                    n = gid[u];
+                    const int32_t pu = par[u];
+                    const int j = trace_choice(tb, st, u, (pu < 0 || par[pu] < 0) ? 0 : ent[pu], pu < 0, &ln);
+                    // the previous layer was staged (prv) when this round has one
+                    trace_write(st, u, n, j, ln, pu < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev, &changed,
+                                &old_l, ba.has_prev ? prv[u] : 0);
+                }
+                if (ba.Dw) {
+                    // commit the move along the segment's GCell edges (the DP of this batch
+                    // reads the other demand buffer)
+                    if (changed) {
+                        const int32_t q = g0a[u], len = lenp[u + 1] - lenp[u];
+                        for (int32_t k = 0; k < len; ++k) {
+                            if (old_l != 255) atomicAdd(&ba.Dw[grid_index(tb, old_l, q + k)], -1);
+                            atomicAdd(&ba.Dw[grid_index(tb, ln, q + k)], 1);
+                        }
+                    }
+                } else {
+                    append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
+                }
+            }
+            __syncthreads();   // the next tile restages the LDS this pass reads
         }
         __syncthreads();
     }

@@ -664,25 +664,33 @@ __device__ __forceinline__ void append_change(const ChangeList &cl, bool pred, i
     }
 }
 
-// Alg. 4 at node n (state s): its layer is the one its parent recorded for the parent's
-// entering layer; its via span is the stack recorded for its own entering layer.
-// jp: the index of the parent's entering layer in the parent's direction list (0 when
-// the parent is the root).  old: n's layer before this pass when the caller has it, else
-// -1 (read from cur).  Returns n's entering-layer index (0 at the root), sets *ln to the
-// layer and *changed / *old_l for the commit list.
+// Alg. 4 at node state s: its layer is the one its parent recorded for the parent's entering
+// layer.  jp: the index of the parent's entering layer in the parent's direction list (0 when
+// the parent is the root).  Sets *ln to the layer (0 at the root) and returns s's own
+// entering-layer index.
 template <class St>
-__device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int32_t s, int32_t n, int jp, bool root,
-                                          uint8_t *cur, uint8_t *vlo, uint8_t *vhi, uint8_t *out_layers,
-                                          int has_prev, int *ln_out, bool *changed, uint8_t *old_l, int old_in = -1)
+__device__ __forceinline__ int trace_choice(const LayerTab &tb, const St &st, int32_t s, int jp, bool root, int *ln_out)
 {
     int ln = 0, j = 0;
     if (!root) {
         // jp < the parent's routable-layer count and the parent's DP recorded a routable
-        // layer of n's direction; the clamps only keep every index inside its array
+        // layer of s's direction; the clamps only keep every index inside its array
         ln = st.sel(s, (jp >= 0 && jp < kMaxA) ? jp : 0);
         ln = ln < tb.L ? ln : 0;
         j = tb.jidx[ln] < 0 ? 0 : tb.jidx[ln];
     }
+    *ln_out = ln;
+    return j;
+}
+
+// Writes node n's layer ln and the via span recorded for its entering index j.  old: n's
+// layer before this pass when the caller has it, else -1 (read from cur).  Sets *changed /
+// *old_l for the commit list.
+template <class St>
+__device__ __forceinline__ void trace_write(const St &st, int32_t s, int32_t n, int j, int ln, bool root, uint8_t *cur,
+                                            uint8_t *vlo, uint8_t *vhi, uint8_t *out_layers, int has_prev,
+                                            bool *changed, uint8_t *old_l, int old_in = -1)
+{
     const uint8_t bt = st.bt(s, j);
     vlo[n] = bt >> 4;
     vhi[n] = bt & 15;
@@ -691,7 +699,16 @@ __device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int3
     if (out_layers) out_layers[n] = (uint8_t)ln;
     *changed = !root && (!has_prev || old != ln);
     *old_l = has_prev ? old : (uint8_t)255;
-    *ln_out = ln;
+}
+
+// Both steps at node n (state s); returns n's entering-layer index.
+template <class St>
+__device__ __forceinline__ int trace_node(const LayerTab &tb, const St &st, int32_t s, int32_t n, int jp, bool root,
+                                          uint8_t *cur, uint8_t *vlo, uint8_t *vhi, uint8_t *out_layers,
+                                          int has_prev, int *ln_out, bool *changed, uint8_t *old_l, int old_in = -1)
+{
+    const int j = trace_choice(tb, st, s, jp, root, ln_out);
+    trace_write(st, s, n, j, *ln_out, root, cur, vlo, vhi, out_layers, has_prev, changed, old_l, old_in);
     return j;
 }
 
