@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                 for (int jj = 0; jj < NAMAX; ++jj) {
                     if (jj < na) {
                         const int l = tb.lay[d][jj];
-                        const int32_t g = grid_index(tb, l, q);
+                        const int32_t g = route_index(tb, d, jj, q);
                         const int32_t cap = a.caps[g];
                         int32_t dd = a.D[g] - (self == l ? 1 : 0) - cap;
                         dd = dd < kDeltaMin ? kDeltaMin : (dd > kDeltaMin + kNDelta - 1 ? kDeltaMin + kNDelta - 1 : dd);

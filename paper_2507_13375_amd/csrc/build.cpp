@@ -111,6 +111,12 @@ la_status build_tab(const la_grid *g, const la_layer_rc *rc, LayerTab &t)
         t.r_avg[d] = t.nA[d] ? (int32_t)(sr / t.nA[d]) : 0;
         t.c_avg[d] = t.nA[d] ? (int32_t)(sc / t.nA[d]) : 0;
     }
+    const int32_t P = t.X * t.Y;   // X * Y * L < 2^31 is checked before
+    t.goff[0] = 0;
+    t.goff[1] = t.nA[0] * P;
+    t.goff[2] = (t.nA[0] + t.nA[1]) * P;
+    int nr = 0;
+    for (int l = 0; l < g->L; ++l) t.nrk[l] = (int8_t)(t.jidx[l] < 0 ? nr++ : 0);
     return LA_OK;
 }
 

@@ -119,11 +119,13 @@ __device__ __forceinline__ uint32_t rvia_d(const LayerTab &t, int a, int b)
 __device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb, int32_t n, int l)
 {
     const int32_t len = a.T.len[n];
-    int32_t g = grid_index(tb, l, a.T.g0[n]);
+    const int d = a.T.dir[n];
+    const int32_t step = tb.nA[d];
+    int32_t g = route_index(tb, d, tb.jidx[l], a.T.g0[n]);
     const int32_t self = (a.w.self_excl && a.prev[n] == l) ? 1 : 0;
     const int32_t *lut = a.w.lut + l * 2 * kNDelta;
     int64_t s = 0;
-    for (int32_t k = 0; k < len; ++k, ++g) {
+    for (int32_t k = 0; k < len; ++k, g += step) {
         const int32_t cap = a.caps[g];
         int32_t d = a.D[g] - self - cap;
         d = d < kDeltaMin ? kDeltaMin : (d > kDeltaMin + kNDelta - 1 ? kDeltaMin + kNDelta - 1 : d);

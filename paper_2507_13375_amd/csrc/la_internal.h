@@ -35,18 +35,30 @@ struct LayerTab {
     int32_t r[kMaxL], c[kMaxL];     // mOhm / aF per GCell
     int32_t pv[kMaxL + 1];          // prefix sums of via R: Rvia(a,b) = |pv[a]-pv[b]|
     int32_t r_avg[2], c_avg[2];     // integer averages over routable layers per direction
+    int32_t goff[3];                // grid-array regions: routable layers of direction 0, of 1, the rest
+    int8_t nrk[kMaxL];              // rank of a layer among the non-routable ones
 };
 
-// Grid arrays inside the library are stored one plane per layer, each plane ordered along
-// the layer's direction: horizontal layers row by row (x fastest), vertical layers column by
-// column (y fastest).  The GCell edges a segment covers on one layer are then consecutive
-// words.  The API's arrays use (y * X + x) * L + l; la_assign and la_demand convert.
-// index in the plane layout of the edge at in-plane position q of layer l
-__host__ __device__ inline int32_t grid_index(const LayerTab &t, int l, int32_t q) { return l * t.X * t.Y + q; }
-// in-plane position of GCell (x, y) on a layer of direction d
+// Grid arrays inside the library are stored by direction: for each direction one record per
+// GCell holding its routable layers of that direction (ascending), records ordered along the
+// direction -- horizontal row by row (x fastest), vertical column by column (y fastest) -- so
+// a segment's GCell edges on all its candidate layers are consecutive words.  Non-routable
+// layers follow, one plane each.  The API's arrays use (y * X + x) * L + l; la_assign and
+// la_demand convert.
+// position of GCell (x, y) along direction d
 __host__ __device__ inline int32_t plane_pos(const LayerTab &t, int d, int32_t x, int32_t y)
 {
     return d == 0 ? y * t.X + x : x * t.Y + y;
+}
+// index of the edge at position q of routable layer index jj of direction d
+__host__ __device__ inline int32_t route_index(const LayerTab &t, int d, int jj, int32_t q)
+{
+    return t.goff[d] + q * t.nA[d] + jj;
+}
+// index of the edge at position q (along layer l's direction) of any layer l
+__host__ __device__ inline int32_t grid_index(const LayerTab &t, int l, int32_t q)
+{
+    return t.jidx[l] >= 0 ? route_index(t, t.dir[l], t.jidx[l], q) : t.goff[2] + t.nrk[l] * t.X * t.Y + q;
 }
 
 // Integer weights handed to the DP kernels.
