@@ -323,19 +323,19 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             // ---- DP bottom-up, one height level at a time ----------------------------------
             // A level of at most kThreads / kGroup items (tall trees) is bound by one item's
             // latency: it takes a group of kGroup lanes per item (node, entering layer), items
-            // with one or two children lane-parallel, the others on the group's first lane.
-            // Larger levels take one lane per item, except that items of two-child nodes (the
-            // slowest, and few) take a group each; the group items start and end on wavefront
-            // boundaries, so no wavefront runs both code paths.
+            // with one to three children lane-parallel, the others on the group's first lane.
+            // Larger levels take one lane per item, except that items of nodes with two or more
+            // children (the slowest, and few) take a group each; the group items start and end
+            // on wavefront boundaries, so no wavefront runs both code paths.
             for (int32_t h = 0; h <= maxlev; ++h) {
                 const int32_t lb = h == 0 ? 0 : kst[4 * h - 1], le = kst[4 * h + 3];
                 const int32_t items = (le - lb) * NAMAX;
                 if (items > kThreads / kGroup) {
                     const bool g2 = a.w.w_via > 0;
-                    const int32_t c2b = g2 ? kst[4 * h + 1] : le, c2e = g2 ? kst[4 * h + 2] : le;
-                    const int32_t nA = (c2b - lb) * NAMAX, nB = (c2e - c2b) * NAMAX * kGroup;
-                    const int32_t pA = (nA + 63) & ~63, pB = (nB + 63) & ~63;
-                    const int32_t total = pA + pB + (le - c2e) * NAMAX;
+                    const int32_t c2b = g2 ? kst[4 * h + 1] : le;   // first node with >= 2 children
+                    const int32_t nA = (c2b - lb) * NAMAX, nB = (le - c2b) * NAMAX * kGroup;
+                    const int32_t pA = (nA + 63) & ~63;
+                    const int32_t total = pA + nB;
                     for (int32_t it = threadIdx.x; it < total; it += blockDim.x) {
                         int32_t pos;
                         int j, sub = -1;
@@ -343,17 +343,12 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                             if (it >= nA) continue;
                             pos = lb + it / NAMAX;
                             j = it % NAMAX;
-                        } else if (it < pA + pB) {
+                        } else {
                             const int32_t r = it - pA;
-                            if (r >= nB) continue;   // whole groups: nB is a multiple of kGroup
                             const int32_t gi = r / kGroup;
                             sub = r % kGroup;
                             pos = c2b + gi / NAMAX;
                             j = gi % NAMAX;
-                        } else {
-                            const int32_t r = it - pA - pB;
-                            pos = c2e + r / NAMAX;
-                            j = r % NAMAX;
                         }
                         const int32_t u = order[pos];
                         const bool root = par[u] < 0;
@@ -367,10 +362,12 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                             l = tb.lay[d][j];
                         }
                         const int64_t kp = root ? 0 : kap[u * NAMAX + j];
-                        if (sub >= 0)
-                            dp_group<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp, sub);
-                        else
+                        if (sub < 0)
                             dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp);
+                        else if (st.nch(u) <= 3)
+                            dp_group<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp, sub);
+                        else if (sub == 0)
+                            dp_node<LdsState<NAMAX>, NAMAX, false>(a, tb, st, u, l, j, root, kp);
                     }
                     __syncthreads();
                     continue;
@@ -392,7 +389,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                     }
                     const int64_t kp = root ? 0 : kap[u * NAMAX + j];
                     const int k = st.nch(u);
-                    if (a.w.w_via > 0 && (k == 1 || k == 2))
+                    if (a.w.w_via > 0 && k >= 1 && k <= 3)
                         dp_group<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp, sub);
                     else if (sub == 0)
                         dp_node<LdsState<NAMAX>, NAMAX, false>(a, tb, st, u, l, j, root, kp);

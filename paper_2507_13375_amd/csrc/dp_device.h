@@ -496,7 +496,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 
 // ---- lane-parallel DP of one item ---------------------------------------------------------
 // The 8 lanes of an aligned group (sub = lane & 7) share one item (node state s, entering
-// layer l, index j) with one or two children and a positive via weight: lane sub takes the
+// layer l, index j) with one to three children and a positive via weight: lane sub takes the
 // children's layer index sub.  Candidate tests use minima across the group (prefix/suffix
 // scans, broadcasts) and the best candidate is a group argmin over (f', b, t), so the result
 // equals dp_node's.  Every lane of the group must call it; lane 0 writes the state.
@@ -574,7 +574,7 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
             bt = (uint32_t)(b << 4 | t);
             sel = (uint32_t)l0;
         }
-    } else {
+    } else if (k == 2) {
         // two children: a pair is a candidate when each choice is its child's key minimum in
         // the pair's hull; per child and layer, the highest lower layer with a key <= and the
         // lowest higher layer with a smaller key bound the hulls where it stays the minimum
@@ -616,6 +616,66 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
                 }
             }
         }
+    } else {
+        // three children: every lane builds each child's key row from the group (one key per
+        // lane), its block bounds and single-child candidates, as the serial hull order does;
+        // lane sub then takes the combinations whose first choice is index sub
+        uint32_t lyp[3], cand[3];
+        uint64_t bnd[3];
+        ChildIn cq[3];
+        int nq[3];
+        cq[0] = c0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (q > 0) cq[q] = child_in(st, s, q);
+            nq[q] = tb.nA[cq[q].dir];
+            const bool vq = sub < nq[q];
+            const int lq = tb.lay[cq[q].dir][vq ? sub : 0];
+            const int64_t kq = q == 0 ? k0 : (vq ? child_key_j(tb, st, wd, cq[q], l, lq, sub) : INT64_MAX);
+            int64_t ky[NAMAX];
+            int ly[NAMAX];
+            lyp[q] = 0;
+#pragma unroll
+            for (int i = 0; i < NAMAX; ++i) {
+                ky[i] = __shfl(kq, i, kGroup);
+                ly[i] = __shfl(lq, i, kGroup);
+                lyp[q] |= (uint32_t)ly[i] << (4 * i);
+            }
+            bnd[q] = block_bounds<NAMAX>(ky, ly, nq[q]);
+            cand[q] = hull_min_mask<NAMAX>(ky, ly, nq[q], lo, hi);
+        }
+        auto lay_of = [&](int q, int jj) { return (int)((lyp[q] >> (4 * jj)) & 15u); };
+        auto inside = [&](int q, int jj, int b, int t) {
+            const uint32_t f = (uint32_t)(bnd[q] >> (8 * jj));
+            return (int)(f & 15u) <= b && t <= (int)((f >> 4) & 15u);
+        };
+        if ((cand[0] >> sub) & 1u) {
+            const ChildVZ z0 = child_vz_j(tb, st, wd, cq[0], l, l0, sub);
+            for (uint32_t m1 = cand[1]; m1; m1 &= m1 - 1) {
+                const int j1 = __ffs(m1) - 1;
+                const int L1 = lay_of(1, j1);
+                const int b01 = min(lo, min(l0, L1)), t01 = max(hi, max(l0, L1));
+                // necessary inside the pair's hull (a third choice can only widen it)
+                if (!inside(0, sub, b01, t01) || !inside(1, j1, b01, t01)) continue;
+                const ChildVZ z1 = child_vz_j(tb, st, wd, cq[1], l, L1, j1);
+                for (uint32_t m2 = cand[2]; m2; m2 &= m2 - 1) {
+                    const int j2 = __ffs(m2) - 1;
+                    const int L2 = lay_of(2, j2);
+                    const int b = min(b01, L2), t = max(t01, L2);
+                    if (!inside(0, sub, b, t) || !inside(1, j1, b, t) || !inside(2, j2, b, t)) continue;
+                    const ChildVZ z2 = child_vz_j(tb, st, wd, cq[2], l, L2, j2);
+                    uint32_t Xc;
+                    const int64_t f = value(b, t, z0.V + z1.V + z2.V, (int64_t)z0.Z + z1.Z + z2.Z, Xc);
+                    const uint32_t btc = (uint32_t)(b << 4 | t);
+                    if (f < fp || (f == fp && btc < bt)) {
+                        fp = f;
+                        bt = btc;
+                        X = Xc;
+                        sel = (uint32_t)l0 | (uint32_t)L1 << 4 | (uint32_t)L2 << 8;
+                    }
+                }
+            }
+        }
     }
     // group argmin over (f', b, t)
 #pragma unroll
@@ -634,7 +694,8 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
         st.S(s, j) = (int32_t)X;
         st.bt(s, j) = (uint8_t)bt;
         st.sel(c0.cs, j) = (uint8_t)(sel & 15u);
-        if (k == 2) st.sel(st.ch_state(s, 1), j) = (uint8_t)(sel >> 4);
+        if (k >= 2) st.sel(st.ch_state(s, 1), j) = (uint8_t)((sel >> 4) & 15u);
+        if (k == 3) st.sel(st.ch_state(s, 2), j) = (uint8_t)((sel >> 8) & 15u);
     }
 }
 
