@@ -176,7 +176,7 @@ la_status la_demand(la_batch *b, int32_t *out)
 la_status la_reset(la_batch *b)
 {
     if (!b) return set_error(LA_ERR_INVALID_ARG, "la_reset: NULL batch");
-    la_status s = zero_i32(b, b->D, b->E);
+    la_status s = zero_i32(b, b->D, b->Eg);
     if (s != LA_OK) return s;
     LA_HIP(hipMemsetAsync(b->cur_layer, 0, b->nodes, b->stream));
     b->has_prev = false;
@@ -231,17 +231,17 @@ static const uint32_t kStateMagic = 0x4c415354u;   // "LAST"
 la_status la_save_state(la_batch *b, void *host_buf, size_t *bytes)
 {
     if (!b || !bytes) return set_error(LA_ERR_INVALID_ARG, "la_save_state: NULL argument");
-    const size_t need = 16 + (size_t)b->E * sizeof(int32_t) + (size_t)b->nodes;
+    const size_t need = 16 + (size_t)b->Eg * sizeof(int32_t) + (size_t)b->nodes;
     if (!host_buf) {
         *bytes = need;
         return LA_OK;
     }
     if (*bytes < need) return set_error(LA_ERR_INVALID_ARG, "la_save_state: buffer too small");
     uint8_t *p = (uint8_t *)host_buf;
-    uint32_t hdr[4] = {kStateMagic, (uint32_t)b->has_prev, (uint32_t)b->E, (uint32_t)b->nodes};
+    uint32_t hdr[4] = {kStateMagic, (uint32_t)b->has_prev, (uint32_t)b->Eg, (uint32_t)b->nodes};
     memcpy(p, hdr, 16);
-    LA_HIP(hipMemcpyAsync(p + 16, b->D, b->E * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
-    LA_HIP(hipMemcpyAsync(p + 16 + b->E * sizeof(int32_t), b->cur_layer, b->nodes, hipMemcpyDeviceToHost, b->stream));
+    LA_HIP(hipMemcpyAsync(p + 16, b->D, b->Eg * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    LA_HIP(hipMemcpyAsync(p + 16 + b->Eg * sizeof(int32_t), b->cur_layer, b->nodes, hipMemcpyDeviceToHost, b->stream));
     LA_HIP(hipStreamSynchronize(b->stream));
     *bytes = need;
     return LA_OK;
@@ -250,15 +250,15 @@ la_status la_save_state(la_batch *b, void *host_buf, size_t *bytes)
 la_status la_load_state(la_batch *b, const void *host_buf, size_t bytes)
 {
     if (!b || !host_buf) return set_error(LA_ERR_INVALID_ARG, "la_load_state: NULL argument");
-    const size_t need = 16 + (size_t)b->E * sizeof(int32_t) + (size_t)b->nodes;
+    const size_t need = 16 + (size_t)b->Eg * sizeof(int32_t) + (size_t)b->nodes;
     const uint8_t *p = (const uint8_t *)host_buf;
     uint32_t hdr[4];
     if (bytes < need) return set_error(LA_ERR_INVALID_ARG, "la_load_state: buffer too small");
     memcpy(hdr, p, 16);
-    if (hdr[0] != kStateMagic || hdr[2] != (uint32_t)b->E || hdr[3] != (uint32_t)b->nodes)
+    if (hdr[0] != kStateMagic || hdr[2] != (uint32_t)b->Eg || hdr[3] != (uint32_t)b->nodes)
         return set_error(LA_ERR_INVALID_ARG, "la_load_state: state of a different batch");
-    LA_HIP(hipMemcpyAsync(b->D, p + 16, b->E * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
-    LA_HIP(hipMemcpyAsync(b->cur_layer, p + 16 + b->E * sizeof(int32_t), b->nodes, hipMemcpyHostToDevice, b->stream));
+    LA_HIP(hipMemcpyAsync(b->D, p + 16, b->Eg * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    LA_HIP(hipMemcpyAsync(b->cur_layer, p + 16 + b->Eg * sizeof(int32_t), b->nodes, hipMemcpyHostToDevice, b->stream));
     LA_HIP(hipStreamSynchronize(b->stream));
     b->has_prev = hdr[1] != 0;
     return b->has_prev ? launch_rc_from_layers(b) : launch_rc_pre(b);

@@ -275,7 +275,7 @@ la_status zero_i32(la_batch *b, int32_t *p, int64_t n)
 la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t inc)
 {
     LA_TIMED(b, "k_history", b->stream,
-             hipLaunchKernelGGL(k_history, dim3(grid_for(b->E)), dim3(kBlock), 0, b->stream, D, b->caps, H, b->E,
+             hipLaunchKernelGGL(k_history, dim3(grid_for(b->Eg)), dim3(kBlock), 0, b->stream, D, b->caps, H, b->Eg,
                                 inc));
     LA_HIP(hipGetLastError());
     return LA_OK;

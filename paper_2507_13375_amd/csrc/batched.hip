@@ -305,17 +305,30 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                 const int32_t q = g0a[u] + (pidx - lenp[u]);   // in-plane position of this edge
                 const int self = prv[u];
                 const int na = tb.nA[d];
+                // the edge's record: its routable layers in pairs (8-byte aligned; a record of
+                // odd length ends in a padding word)
+                const int32_t g = route_index(tb, d, 0, q);
+                const int2 *dr = (const int2 *)(a.D + g), *hr = (const int2 *)(a.H + g);
+                const uint16_t *cr = (const uint16_t *)(a.caps + g);
 #pragma unroll
-                for (int jj = 0; jj < NAMAX; ++jj) {
-                    if (jj < na) {
-                        const int l = tb.lay[d][jj];
-                        const int32_t g = route_index(tb, d, jj, q);
-                        const int32_t cap = a.caps[g];
-                        int32_t dd = a.D[g] - (self == l ? 1 : 0) - cap;
-                        dd = dd < kDeltaMin ? kDeltaMin : (dd > kDeltaMin + kNDelta - 1 ? kDeltaMin + kNDelta - 1 : dd);
-                        const int64_t v = (int64_t)lut[(l * 2 + (cap > 0 ? 0 : 1)) * kNDelta + dd - kDeltaMin] +
-                                          (int64_t)a.H[g];
-                        atomicAdd((unsigned long long *)&kap[u * NAMAX + jj], (unsigned long long)v);
+                for (int jp = 0; jp < NAMAX; jp += 2) {
+                    if (jp < na) {
+                        const int2 dv = dr[jp / 2], hv = hr[jp / 2];
+                        const uint32_t cv = cr[jp / 2];
+#pragma unroll
+                        for (int h2 = 0; h2 < 2; ++h2) {
+                            const int jj = jp + h2;
+                            if (jj < na) {
+                                const int l = tb.lay[d][jj];
+                                const int32_t cap = (int32_t)((cv >> (8 * h2)) & 0xffu);
+                                int32_t dd = (h2 ? dv.y : dv.x) - (self == l ? 1 : 0) - cap;
+                                dd = dd < kDeltaMin ? kDeltaMin
+                                                    : (dd > kDeltaMin + kNDelta - 1 ? kDeltaMin + kNDelta - 1 : dd);
+                                const int64_t v = (int64_t)lut[(l * 2 + (cap > 0 ? 0 : 1)) * kNDelta + dd - kDeltaMin] +
+                                                  (int64_t)(h2 ? hv.y : hv.x);
+                                atomicAdd((unsigned long long *)&kap[u * NAMAX + jj], (unsigned long long)v);
+                            }
+                        }
                     }
                 }
             }
@@ -721,7 +734,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
     const hipStream_t keep = b->stream;
     b->stream = s;   // commit_changed and history_update launch on the batch's stream
     int32_t *dcur = b->D, *dalt = b->D_alt;
-    const int cgrid = (int)std::min<int64_t>(4096, (b->E / 4 + 255) / 256 + 1);
+    const int cgrid = (int)std::min<int64_t>(4096, (b->Eg / 4 + 255) / 256 + 1);
     for (int32_t r = 0; r < R && st == LA_OK; ++r) {
         DPArgs a = make_dp_args(b, w, H, lut);
         a.w.self_excl = has_prev ? 1 : 0;
@@ -737,7 +750,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             a.D = dcur;
             if (fused)
                 LA_TIMED(b, "k_copy_i32", s,
-                         hipLaunchKernelGGL(k_copy_i32, dim3(cgrid), dim3(256), 0, s, dalt, dcur, b->E));
+                         hipLaunchKernelGGL(k_copy_i32, dim3(cgrid), dim3(256), 0, s, dalt, dcur, b->Eg));
             hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, b->chg_count, 1);
             BArgs ba;
             ba.tier_nets = b->tier_nets;
@@ -772,7 +785,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
         has_prev = true;
     }
     if (st == LA_OK && dcur != b->D)
-        LA_TIMED(b, "k_copy_i32", s, hipLaunchKernelGGL(k_copy_i32, dim3(cgrid), dim3(256), 0, s, b->D, dcur, b->E));
+        LA_TIMED(b, "k_copy_i32", s, hipLaunchKernelGGL(k_copy_i32, dim3(cgrid), dim3(256), 0, s, b->D, dcur, b->Eg));
     b->stream = keep;
     return st;
 }

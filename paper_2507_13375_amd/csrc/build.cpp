@@ -111,12 +111,15 @@ la_status build_tab(const la_grid *g, const la_layer_rc *rc, LayerTab &t)
         t.r_avg[d] = t.nA[d] ? (int32_t)(sr / t.nA[d]) : 0;
         t.c_avg[d] = t.nA[d] ? (int32_t)(sc / t.nA[d]) : 0;
     }
-    const int32_t P = t.X * t.Y;   // X * Y * L < 2^31 is checked before
-    t.goff[0] = 0;
-    t.goff[1] = t.nA[0] * P;
-    t.goff[2] = (t.nA[0] + t.nA[1]) * P;
+    const int64_t P = (int64_t)t.X * t.Y;
     int nr = 0;
     for (int l = 0; l < g->L; ++l) t.nrk[l] = (int8_t)(t.jidx[l] < 0 ? nr++ : 0);
+    for (int d = 0; d < 2; ++d) t.nAp[d] = (t.nA[d] + 1) & ~1;
+    if ((int64_t)(t.nAp[0] + t.nAp[1] + nr) * P >= (int64_t(1) << 31))
+        return set_error(LA_ERR_INVALID_ARG, "grid too large for 32-bit edge indices");
+    t.goff[0] = 0;
+    t.goff[1] = (int32_t)(t.nAp[0] * P);
+    t.goff[2] = (int32_t)((t.nAp[0] + t.nAp[1]) * P);
     return LA_OK;
 }
 
@@ -412,6 +415,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     b->nodes = M;
     b->sinks = S;
     b->E = (int64_t)X * Y * L;
+    b->Eg = tab.goff[2] + (int64_t)(L - tab.nA[0] - tab.nA[1]) * X * Y;
     b->levels = max_h + 1;
     b->max_net_nodes = max_net;
     b->gcell_edges = gcell;
@@ -440,7 +444,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     std::vector<int32_t> budget(nets->net_budget_fs, nets->net_budget_fs + N);
     std::vector<int32_t> rdrv(nets->net_rdrv_mohm, nets->net_rdrv_mohm + N);
     // capacities in the plane layout
-    std::vector<uint8_t> caps(b->E);
+    std::vector<uint8_t> caps(b->Eg, 0);
     for (int32_t y = 0; y < Y; ++y)
         for (int32_t x = 0; x < X; ++x)
             for (int l = 0; l < L; ++l)
@@ -487,9 +491,9 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(alloc(&b->cl_start, (size_t)b->cl_start_cap));
     chk(alloc(&b->cl_off, 256 + 2));
     chk(upload(&b->caps, caps));
-    chk(alloc(&b->D, b->E));
-    chk(alloc(&b->D_alt, b->E));
-    chk(alloc(&b->Hi, b->E));
+    chk(alloc(&b->D, b->Eg));
+    chk(alloc(&b->D_alt, b->Eg));
+    chk(alloc(&b->Hi, b->Eg));
     chk(alloc(&b->cur_layer, M));
     chk(alloc(&b->vlo, M));
     chk(alloc(&b->vhi, M));
@@ -528,7 +532,8 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     LA_HIP(hipMemsetAsync(b->S, 0, M * b->NAmax * sizeof(int32_t), b->stream));
     LA_HIP(hipMemsetAsync(b->bt, 0, M * b->NAmax, b->stream));
     LA_HIP(hipMemsetAsync(b->sel, 0, M * b->NAmax + kMaxA, b->stream));
-    LA_HIP(hipMemsetAsync(b->D, 0, b->E * sizeof(int32_t), b->stream));
+    LA_HIP(hipMemsetAsync(b->D, 0, b->Eg * sizeof(int32_t), b->stream));
+    LA_HIP(hipMemsetAsync(b->Hi, 0, b->Eg * sizeof(int32_t), b->stream));   // record padding stays 0
     LA_HIP(hipMemsetAsync(b->cur_layer, 0, M, b->stream));
     LA_HIP(hipMemsetAsync(b->vlo, 0, M, b->stream));
     LA_HIP(hipMemsetAsync(b->vhi, 0, M, b->stream));

@@ -120,7 +120,7 @@ __device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb
 {
     const int32_t len = a.T.len[n];
     const int d = a.T.dir[n];
-    const int32_t step = tb.nA[d];
+    const int32_t step = tb.nAp[d];
     int32_t g = route_index(tb, d, tb.jidx[l], a.T.g0[n]);
     const int32_t self = (a.w.self_excl && a.prev[n] == l) ? 1 : 0;
     const int32_t *lut = a.w.lut + l * 2 * kNDelta;

@@ -35,12 +35,14 @@ struct LayerTab {
     int32_t r[kMaxL], c[kMaxL];     // mOhm / aF per GCell
     int32_t pv[kMaxL + 1];          // prefix sums of via R: Rvia(a,b) = |pv[a]-pv[b]|
     int32_t r_avg[2], c_avg[2];     // integer averages over routable layers per direction
+    int32_t nAp[2];                 // record length per direction: nA rounded up to even (8-byte records)
     int32_t goff[3];                // grid-array regions: routable layers of direction 0, of 1, the rest
     int8_t nrk[kMaxL];              // rank of a layer among the non-routable ones
 };
 
 // Grid arrays inside the library are stored by direction: for each direction one record per
-// GCell holding its routable layers of that direction (ascending), records ordered along the
+// GCell holding its routable layers of that direction (ascending; padded to an even count so
+// that records are 8-byte aligned), records ordered along the
 // direction -- horizontal row by row (x fastest), vertical column by column (y fastest) -- so
 // a segment's GCell edges on all its candidate layers are consecutive words.  Non-routable
 // layers follow, one plane each.  The API's arrays use (y * X + x) * L + l; la_assign and
@@ -53,7 +55,7 @@ __host__ __device__ inline int32_t plane_pos(const LayerTab &t, int d, int32_t x
 // index of the edge at position q of routable layer index jj of direction d
 __host__ __device__ inline int32_t route_index(const LayerTab &t, int d, int jj, int32_t q)
 {
-    return t.goff[d] + q * t.nA[d] + jj;
+    return t.goff[d] + q * t.nAp[d] + jj;
 }
 // index of the edge at position q (along layer l's direction) of any layer l
 __host__ __device__ inline int32_t grid_index(const LayerTab &t, int l, int32_t q)
@@ -99,6 +101,7 @@ struct la_batch {
     hipStream_t stream = nullptr;
     gapla::LayerTab tab{};
     int64_t nets = 0, nodes = 0, sinks = 0, E = 0;
+    int64_t Eg = 0;   // length of the library's grid arrays (E plus record padding)
     int32_t levels = 0, max_net_nodes = 0;
     int64_t gcell_edges = 0;
     int32_t NAmax = 0;              // stride of per-(node, layer index) DP arrays
@@ -221,7 +224,7 @@ la_status launch_rc_pre(la_batch *b);
 la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay);
 la_status elmore_backward(la_batch *b, const float *gbar_neg_dslack, bool from_dslack, float *dR, float *dC);
 la_status commit_changed(la_batch *b, int32_t *D);
-// conversions between the API's grid order and the plane layout (E int32 each)
+// conversions between the API's grid order (E int32) and the library's layout (Eg int32)
 la_status grid_to_planes(la_batch *b, const int32_t *api, int32_t *planes);
 la_status planes_to_grid(la_batch *b, const int32_t *planes, int32_t *api);
 la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t hist_inc);
