@@ -264,7 +264,7 @@ __global__ void k_edge_w(TreeDev T, Levels lv, int32_t cnt, const uint16_t *pin_
 }
 
 constexpr int kTailBlock = 1024;
-constexpr int32_t kTailNodes = 4096;   // levels this sparse run in the single-workgroup launch
+constexpr int32_t kTailNodes = 1024;   // levels this sparse run in the single-workgroup launch
 
 __global__ void k_neg(const float *x, float *y, int64_t n)
 {
