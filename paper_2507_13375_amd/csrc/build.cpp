@@ -351,6 +351,43 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
         for (int64_t v = 0; v < M; ++v) level_nodes[fill[height[v]]++] = (int32_t)v;
     }
 
+    // ---- Elmore tiles: runs of whole nets in canonical order, at most kETile nodes and
+    // heights below kEMaxH; the other nets' nodes grouped by height ------------------------
+    std::vector<int32_t> etile, ebig_ptr(max_h + 2, 0), ebig_nodes;
+    {
+        std::vector<char> ebig(std::max<int32_t>(N, 1), 0);
+        int32_t t0 = -1, tn = 0;
+        for (int32_t i = 0; i < N; ++i) {
+            const int32_t b0 = net_ptr[i], n = net_ptr[i + 1] - b0;
+            int32_t hm = 0;
+            for (int32_t v = b0; v < b0 + n; ++v) hm = std::max(hm, height[v]);
+            const bool big = n > kETile || hm >= kEMaxH;
+            if (t0 >= 0 && (big || tn + n > kETile)) {
+                etile.push_back(t0);
+                etile.push_back(t0 + tn);
+                t0 = -1;
+                tn = 0;
+            }
+            if (big) {
+                ebig[i] = 1;
+                for (int32_t v = b0; v < b0 + n; ++v) ebig_ptr[height[v] + 1]++;
+                continue;
+            }
+            if (t0 < 0) t0 = b0;
+            tn += n;
+        }
+        if (t0 >= 0) {
+            etile.push_back(t0);
+            etile.push_back(t0 + tn);
+        }
+        for (int h = 0; h <= max_h; ++h) ebig_ptr[h + 1] += ebig_ptr[h];
+        ebig_nodes.resize(std::max<int32_t>(ebig_ptr[max_h + 1], 1));
+        std::vector<int32_t> fill(ebig_ptr.begin(), ebig_ptr.end() - 1);
+        for (int32_t i = 0; i < N; ++i)
+            if (ebig[i])
+                for (int32_t v = net_ptr[i]; v < net_ptr[i + 1]; ++v) ebig_nodes[fill[height[v]]++] = v;
+    }
+
     // ---- batched form: nets with more nodes than one LDS tile, nodes grouped by height ---
     std::vector<int32_t> net_big(std::max<int32_t>(N, 1), -1), bn_order, bn_lvl, bn_lvl_off, bn_nlev;
     for (int32_t i = 0; i < N; ++i) {
@@ -425,6 +462,8 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     b->bnd_via = bvia;
     b->bnd_d = bd;
     b->h_level_ptr = level_ptr;
+    b->h_ebig_ptr = ebig_ptr;
+    b->e_ntiles = (int32_t)(etile.size() / 2);
     b->h_net_ptr = net_ptr;
     b->h_bbox.resize((size_t)4 * N);
     for (int32_t i = 0; i < N; ++i) {
@@ -471,6 +510,9 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->flags, flags));
     chk(upload(&b->level_nodes, level_nodes));
     chk(upload(&b->level_ptr, level_ptr));
+    chk(upload(&b->e_tile, etile));
+    chk(upload(&b->e_big_nodes, ebig_nodes));
+    chk(upload(&b->e_big_ptr, ebig_ptr));
     chk(upload(&b->height, height));
     chk(alloc(&b->bucket_nodes, M));
     b->n_big = (int32_t)bn_nlev.size();

@@ -8,6 +8,7 @@
 // These kernels are HBM-streaming sweeps over nodes grouped by tree height.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "la_internal.h"
@@ -263,6 +264,159 @@ __global__ void k_edge_w(TreeDev T, Levels lv, int32_t cnt, const uint16_t *pin_
     each_node(lv, cnt, [&](int32_t v) { edge_w(T, v, pin_w, seg_w); });
 }
 
+// ---------------------------------------------------------------------------
+// Tiles: a workgroup takes a run of whole nets (at most kETile nodes, heights below kEMaxH),
+// orders its nodes by height in LDS and runs both sweeps there, level by level with
+// barriers.  Each node does the same operations in the same order as the per-level kernels,
+// so the results are the same bits.
+// ---------------------------------------------------------------------------
+constexpr int kEThreads = 256;
+
+struct TileLevels {
+    int16_t ord[kETile];        // tile-local nodes by height
+    int32_t start[kEMaxH + 1];  // level h: ord[start[h], start[h + 1])
+    int32_t cur[kEMaxH];
+    int32_t maxh;
+};
+
+// orders the tile's nodes [n0, n0 + nn) by height; returns the highest level
+__device__ __forceinline__ int32_t tile_levels(TileLevels &L, const int32_t *height, int32_t n0, int32_t nn)
+{
+    for (int i = threadIdx.x; i <= kEMaxH; i += blockDim.x) L.start[i] = 0;
+    if (threadIdx.x == 0) L.maxh = 0;
+    __syncthreads();
+    for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
+        const int32_t h = height[n0 + u];
+        atomicAdd(&L.start[h + 1], 1);
+        atomicMax(&L.maxh, h);
+    }
+    __syncthreads();
+    const int32_t mh = L.maxh;
+    if (threadIdx.x == 0)
+        for (int32_t h = 1; h <= mh + 1; ++h) L.start[h] += L.start[h - 1];
+    __syncthreads();
+    for (int32_t h = threadIdx.x; h <= mh; h += blockDim.x) L.cur[h] = L.start[h];
+    __syncthreads();
+    for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) L.ord[atomicAdd(&L.cur[height[n0 + u]], 1)] = (int16_t)u;
+    __syncthreads();
+    return mh;
+}
+
+__global__ void __launch_bounds__(kEThreads) k_elmore_tiles(TreeDev T, const int32_t *tiles, int32_t ntiles,
+                                                            const int32_t *height, const float *R, const float *C,
+                                                            float *S, float *Slo, float *delay)
+{
+    __shared__ TileLevels L;
+    __shared__ float sh[kETile], sl[kETile], th[kETile], tl[kETile];
+    for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+        const int32_t n0 = tiles[2 * ti], nn = tiles[2 * ti + 1] - n0;
+        const int32_t mh = tile_levels(L, height, n0, nn);
+        // S(v) = sum over RC children of (C + S), bottom-up
+        for (int32_t h = 0; h <= mh; ++h) {
+            for (int32_t i = L.start[h] + threadIdx.x; i < L.start[h + 1]; i += blockDim.x) {
+                const int32_t u = L.ord[i], v = n0 + u;
+                ff x{0.f, 0.f};
+                const int32_t k = T.sink_id[v];
+                if (k >= 0) {
+                    x = ff_add(x, C[T.nodes + k]);
+                    x = ff_add(x, (float)((double)T.cpin[v] * 1e-3));
+                }
+                for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) {
+                    const int32_t c = T.ch[q], cu = c - n0;
+                    x = ff_add(x, C[c]);
+                    x = ff_add(x, ff{sh[cu], sl[cu]});
+                }
+                x = ff_norm(x);
+                sh[u] = x.hi;
+                sl[u] = x.lo;
+            }
+            __syncthreads();
+        }
+        for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
+            S[n0 + u] = sh[u];
+            Slo[n0 + u] = sl[u];
+        }
+        // t(v) = t(parent) + R_v (C_v/2 + S_v), top-down; delay at sink pins
+        for (int32_t h = mh; h >= 0; --h) {
+            for (int32_t i = L.start[h] + threadIdx.x; i < L.start[h + 1]; i += blockDim.x) {
+                const int32_t u = L.ord[i], v = n0 + u;
+                const int32_t p = T.parent[v];
+                const ff up = p < 0 ? ff{0.f, 0.f} : ff{th[p - n0], tl[p - n0]};
+                const ff load = ff_add(ff{sh[u], sl[u]}, 0.5f * C[v]);
+                const ff tv = ff_norm(ff_add(up, ff_mul(R[v], load)));
+                th[u] = tv.hi;
+                tl[u] = tv.lo;
+                const int32_t k = T.sink_id[v];
+                if (k >= 0) {
+                    const int64_t e = T.nodes + k;
+                    const ff pl = ff_add(ff{0.5f * C[e], 0.f}, (float)((double)T.cpin[v] * 1e-3));
+                    delay[k] = ff_val(ff_add(tv, ff_mul(R[e], pl)));
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kEThreads) k_adj_tiles(TreeDev T, const int32_t *tiles, int32_t ntiles,
+                                                         const int32_t *height, const float *R, const float *C,
+                                                         const float *S, const float *Slo, const float *gbar, float *G,
+                                                         float *Glo, float *Sig, float *Siglo, float *dR, float *dC)
+{
+    __shared__ TileLevels L;
+    __shared__ float gh[kETile], gl[kETile], qh[kETile], ql[kETile];
+    for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+        const int32_t n0 = tiles[2 * ti], nn = tiles[2 * ti + 1] - n0;
+        const int32_t mh = tile_levels(L, height, n0, nn);
+        // G(v) = sum of g below v, bottom-up
+        for (int32_t h = 0; h <= mh; ++h) {
+            for (int32_t i = L.start[h] + threadIdx.x; i < L.start[h + 1]; i += blockDim.x) {
+                const int32_t u = L.ord[i], v = n0 + u;
+                ff g{0.f, 0.f};
+                const int32_t k = T.sink_id[v];
+                if (k >= 0) g = ff_add(g, gbar[k]);
+                for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) {
+                    const int32_t cu = T.ch[q] - n0;
+                    g = ff_add(g, ff{gh[cu], gl[cu]});
+                }
+                g = ff_norm(g);
+                gh[u] = g.hi;
+                gl[u] = g.lo;
+            }
+            __syncthreads();
+        }
+        // Sig(v) = Sig(parent) + R_v G(v), top-down, and the R / C gradients
+        for (int32_t h = mh; h >= 0; --h) {
+            for (int32_t i = L.start[h] + threadIdx.x; i < L.start[h + 1]; i += blockDim.x) {
+                const int32_t u = L.ord[i], v = n0 + u;
+                const int32_t p = T.parent[v];
+                const ff up = p < 0 ? ff{0.f, 0.f} : ff{qh[p - n0], ql[p - n0]};
+                const ff g{gh[u], gl[u]};
+                const ff sv = ff_norm(ff_add(up, ff_mul(R[v], g)));
+                qh[u] = sv.hi;
+                ql[u] = sv.lo;
+                if (dR) dR[v] = ff_val(ff_mul(ff_val(g), ff_add(ff{S[v], Slo[v]}, 0.5f * C[v])));
+                if (dC) dC[v] = ff_val(ff_add(up, 0.5f * R[v] * ff_val(g)));
+                const int32_t k = T.sink_id[v];
+                if (k >= 0) {
+                    const int64_t e = T.nodes + k;
+                    const float gk = gbar[k];
+                    if (dR) dR[e] = gk * (0.5f * C[e] + (float)((double)T.cpin[v] * 1e-3));
+                    if (dC) dC[e] = ff_val(ff_add(sv, 0.5f * R[e] * gk));
+                }
+            }
+            __syncthreads();
+        }
+        for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
+            G[n0 + u] = gh[u];
+            Glo[n0 + u] = gl[u];
+            Sig[n0 + u] = qh[u];
+            Siglo[n0 + u] = ql[u];
+        }
+        __syncthreads();
+    }
+}
+
 constexpr int kTailBlock = 1024;
 constexpr int32_t kTailNodes = 1024;   // levels this sparse run in the single-workgroup launch
 
@@ -482,31 +636,38 @@ la_status launch_rc_from_layers(la_batch *b)
     return LA_OK;
 }
 
+// Nodes grouped by height: host copy of the level starts, device nodes and starts.
+struct LevelList {
+    const std::vector<int32_t> *lp;   // [levels + 1]
+    const int32_t *nodes, *dptr;
+};
+
 // Start of the run of top levels that each hold at most kTailNodes nodes; those levels go to one
 // single-workgroup launch when there are at least two of them.
-static int32_t tail_start(const la_batch *b)
+static int32_t tail_start(const std::vector<int32_t> &lp)
 {
-    const auto &lp = b->h_level_ptr;
-    int32_t h0 = b->levels;
+    const int32_t levels = (int32_t)lp.size() - 1;
+    int32_t h0 = levels;
     while (h0 > 0 && lp[h0] - lp[h0 - 1] <= kTailNodes) --h0;
-    return b->levels - h0 >= 2 ? h0 : b->levels;
+    return levels - h0 >= 2 ? h0 : levels;
 }
 
 // Visits the levels bottom-up (down = false) or top-down.  `launch(lv, grid, block, cnt)` issues
 // one kernel over the nodes that `lv` names.
 template <class Launch>
-static void sweep_levels(la_batch *b, bool down, Launch launch)
+static void sweep_levels(const LevelList &ll, bool down, Launch launch)
 {
-    const auto &lp = b->h_level_ptr;
-    const int32_t h0 = tail_start(b);
+    const auto &lp = *ll.lp;
+    const int32_t levels = (int32_t)lp.size() - 1;
+    if (levels <= 0 || lp[levels] == 0) return;
+    const int32_t h0 = tail_start(lp);
     auto dense = [&](int32_t h) {
         const int32_t cnt = lp[h + 1] - lp[h];
-        if (cnt) launch(Levels{b->level_nodes + lp[h], nullptr, 0, -1, false}, dim3((cnt + kBlock - 1) / kBlock),
+        if (cnt) launch(Levels{ll.nodes + lp[h], nullptr, 0, -1, false}, dim3((cnt + kBlock - 1) / kBlock),
                         dim3(kBlock), cnt);
     };
     auto tail = [&]() {
-        if (h0 < b->levels)
-            launch(Levels{b->level_nodes, b->level_ptr, h0, b->levels, down}, dim3(1), dim3(kTailBlock), 0);
+        if (h0 < levels) launch(Levels{ll.nodes, ll.dptr, h0, levels, down}, dim3(1), dim3(kTailBlock), 0);
     };
     if (!down) {
         for (int32_t h = 0; h < h0; ++h) dense(h);
@@ -517,14 +678,26 @@ static void sweep_levels(la_batch *b, bool down, Launch launch)
     }
 }
 
+static LevelList all_levels(const la_batch *b) { return LevelList{&b->h_level_ptr, b->level_nodes, b->level_ptr}; }
+static LevelList untiled_levels(const la_batch *b) { return LevelList{&b->h_ebig_ptr, b->e_big_nodes, b->e_big_ptr}; }
+
+// workgroups of the tile kernels: 8 per CU of a 256-CU part (the loop over tiles strides by it)
+static int tile_grid(const la_batch *b) { return std::max(1, std::min<int>(b->e_ntiles, 2048)); }
+
 la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay)
 {
     const TreeDev T = tree_view(b);
-    sweep_levels(b, false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
+    // nets in tiles: one launch; the others level by level
+    if (b->e_ntiles > 0)
+        LA_TIMED(b, "k_elmore_tiles", b->stream,
+                 hipLaunchKernelGGL(k_elmore_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T, b->e_tile,
+                                    b->e_ntiles, b->height, R, C, b->el_S, b->el_Slo, delay));
+    const LevelList ll = untiled_levels(b);
+    sweep_levels(ll, false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
         LA_TIMED(b, "k_elmore_up", b->stream,
                  hipLaunchKernelGGL(k_elmore_up, g, t, 0, b->stream, T, lv, cnt, R, C, b->el_S, b->el_Slo));
     });
-    sweep_levels(b, true, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
+    sweep_levels(ll, true, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
         LA_TIMED(b, "k_elmore_down", b->stream,
                  hipLaunchKernelGGL(k_elmore_down, g, t, 0, b->stream, T, lv, cnt, R, C, b->el_S, b->el_Slo, b->el_t,
                                     b->el_tlo, delay));
@@ -549,11 +722,17 @@ la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *
         gbar = b->scratch_f;
     }
     float *Glo = b->el_Glo, *Siglo = b->el_Siglo;
-    sweep_levels(b, false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
+    if (b->e_ntiles > 0)
+        LA_TIMED(b, "k_adj_tiles", b->stream,
+                 hipLaunchKernelGGL(k_adj_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T, b->e_tile,
+                                    b->e_ntiles, b->height, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, gbar, b->el_G,
+                                    Glo, b->el_Sig, Siglo, dR, dC));
+    const LevelList ll = untiled_levels(b);
+    sweep_levels(ll, false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
         LA_TIMED(b, "k_adj_up", b->stream,
                  hipLaunchKernelGGL(k_adj_up, g, t, 0, b->stream, T, lv, cnt, gbar, b->el_G, Glo));
     });
-    sweep_levels(b, true, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
+    sweep_levels(ll, true, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
         LA_TIMED(b, "k_adj_down", b->stream,
                  hipLaunchKernelGGL(k_adj_down, g, t, 0, b->stream, T, lv, cnt, b->fwd_R, b->fwd_C, b->el_S,
                                     b->el_Slo, b->el_G, Glo, gbar, b->el_Sig, Siglo, dR, dC));
@@ -578,7 +757,7 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
              hipLaunchKernelGGL(k_tiers, dim3(grid_for(b->nets)), dim3(kBlock), 0, b->stream, T, b->slack,
                                 b->wns_bits, tier));
     if (mode == LA_WEIGHTS_PLAIN) {
-        sweep_levels(b, false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
+        sweep_levels(all_levels(b), false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
             LA_TIMED(b, "k_edge_w", b->stream,
                      hipLaunchKernelGGL(k_edge_w, g, t, 0, b->stream, T, lv, cnt, pin_w, seg_w));
         });

@@ -12,6 +12,8 @@
 namespace gapla {
 
 constexpr int kMaxL = 16;          // layers supported (4-bit layer ids)
+constexpr int kETile = 1024;        // nodes of one Elmore tile (whole nets, swept in one workgroup)
+constexpr int kEMaxH = 128;         // tree heights an Elmore tile handles
 constexpr int kCap = 192;          // nodes of one batched-form workgroup's LDS tile
 constexpr int kClaimUnits = 220;   // work-queue claim size: sum over its nets of (nodes + kNetUnits)
 constexpr int kNetUnits = 3;
@@ -111,6 +113,11 @@ struct la_batch {
 
     // host copies
     std::vector<int32_t> h_level_ptr;   // [levels+1]
+    // Elmore: tiles of whole nets ([start, end) node pairs) and, grouped by height, the nodes of
+    // the nets no tile takes
+    int32_t *e_tile = nullptr, *e_big_nodes = nullptr, *e_big_ptr = nullptr;
+    int32_t e_ntiles = 0;
+    std::vector<int32_t> h_ebig_ptr;    // [levels+1]
     std::vector<int32_t> h_net_ptr;
     std::vector<int16_t> h_bbox;        // [nets][4] x min, x max, y min, y max of the net's nodes
 
