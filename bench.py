@@ -215,11 +215,11 @@ def roofline(b, form, kernels):
 
 def elmore_rate(b, kernels):
     """Algorithmic HBM rate of the Elmore forward sweeps (28 B per RC edge per sweep)."""
-    up, down = kernels.get("k_elmore_up"), kernels.get("k_elmore_down")
-    if not up or not down:
+    names = ("k_elmore_tiles", "k_elmore_up", "k_elmore_down")   # tiles, and untiled nets by level
+    if not any(k in kernels for k in names):
         return None
     sweeps = I_ITERS + 1
-    ms = up[1] + down[1]
+    ms = sum(kernels[k][1] for k in names if k in kernels)
     gbs = b.elmore_fwd_bytes * sweeps / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
             "ms_per_sweep": ms / sweeps}
