@@ -81,7 +81,9 @@ struct Tile {
     static constexpr size_t ENT = SEL + (size_t)kCap * NAMAX;       // uint8 [kCap] entering-layer index
     static constexpr size_t FLD = ENT + (size_t)kCap;               // uint8 [kCap] flags | dir << 4
     static constexpr size_t PRV = FLD + (size_t)kCap;               // uint8 [kCap] previous layer (255: none)
-    static constexpr size_t LUT = (PRV + (size_t)kCap + 15) & ~(size_t)15;
+    static constexpr size_t NEWL = PRV + (size_t)kCap;              // uint8 [kCap] new layer of a moved segment, else 255
+    static constexpr size_t SMAP = NEWL + (size_t)kCap;             // uint8 [kCap * NAMAX] GCell step -> segment
+    static constexpr size_t LUT = (SMAP + (size_t)kCap * NAMAX + 15) & ~(size_t)15;
     static size_t bytes(int L) { return LUT + (size_t)L * 2 * kNDelta * 4; }
 };
 
@@ -153,6 +155,8 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
     uint16_t *pinw = (uint16_t *)(smem + TL::PINW);
     uint8_t *bt = smem + TL::BT;
     uint8_t *sel = smem + TL::SEL;
+    uint8_t *newl = smem + TL::NEWL;
+    uint8_t *smap = smem + TL::SMAP;
     uint8_t *ent = smem + TL::ENT;
     uint8_t *fld = smem + TL::FLD;
     uint8_t *prv = smem + TL::PRV;
@@ -275,11 +279,21 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             block_scan(kst, 4 * maxlev + 5, scan_tmp);   // bucket starts
             block_scan(lenp, nn + 1, scan_tmp);          // lenp[u]: first GCell step of u
             // (height, class) order; kst[q] ends as the end of bucket q = start of q+1.  The
-            // step -> segment map of the gather borrows sel, which the DP fills only later.
+            // step -> segment map serves the gather and the demand moves.
             const int32_t steps = lenp[nn];
             static_assert(kCap <= 256, "the step map holds tile-local node ids in one byte");
-            uint8_t *smap = sel;
             const bool mapped = steps <= kCap * NAMAX;
+            // the segment of GCell step pidx: the last u with lenp[u] <= pidx
+            auto seg_of = [&](int32_t pidx) -> int32_t {
+                if (mapped) return smap[pidx];
+                int32_t lo_ = 0, hi_ = nn;
+                while (hi_ - lo_ > 1) {
+                    const int32_t mid = (lo_ + hi_) >> 1;
+                    if (lenp[mid] <= pidx) lo_ = mid;
+                    else hi_ = mid;
+                }
+                return lo_;
+            };
             for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
                 order[atomicAdd(&kst[key[u]], 1)] = (int16_t)u;
                 if (mapped)
@@ -289,18 +303,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             // congestion costs: one thread per GCell edge of the tile's segments, every
             // routable layer of the segment's direction at once
             for (int32_t pidx = threadIdx.x; pidx < steps; pidx += blockDim.x) {
-                int32_t u;
-                if (mapped) {
-                    u = smap[pidx];
-                } else {
-                    int32_t lo_ = 0, hi_ = nn;      // last u with lenp[u] <= pidx
-                    while (hi_ - lo_ > 1) {
-                        const int32_t mid = (lo_ + hi_) >> 1;
-                        if (lenp[mid] <= pidx) lo_ = mid;
-                        else hi_ = mid;
-                    }
-                    u = lo_;
-                }
+                const int32_t u = seg_of(pidx);
                 const int d = fld[u] >> 4;
                 const int32_t q = g0a[u] + (pidx - lenp[u]);   // in-plane position of this edge
                 const int self = prv[u];
@@ -436,17 +439,23 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                                 &old_l, ba.has_prev ? prv[u] : 0);
                 }
                 if (ba.Dw) {
-                    // commit the move along the segment's GCell edges (the DP of this batch
-                    // reads the other demand buffer)
-                    if (changed) {
-                        const int32_t q = g0a[u], len = lenp[u + 1] - lenp[u];
-                        for (int32_t k = 0; k < len; ++k) {
-                            if (old_l != 255) atomicAdd(&ba.Dw[grid_index(tb, old_l, q + k)], -1);
-                            atomicAdd(&ba.Dw[grid_index(tb, ln, q + k)], 1);
-                        }
-                    }
+                    if (u < nn) newl[u] = changed ? (uint8_t)ln : (uint8_t)255;
                 } else {
                     append_change(ba.cl, changed, n, old_l, (uint8_t)ln);
+                }
+            }
+            if (ba.Dw) {
+                // demand moves, one lane per GCell edge of the moved segments (the DP of this
+                // batch reads the other demand buffer); the previous layer is prv, if any
+                __syncthreads();
+                for (int32_t pidx = threadIdx.x; pidx < steps; pidx += blockDim.x) {
+                    const int32_t u = seg_of(pidx);
+                    const int nl = newl[u];
+                    if (nl == 255) continue;
+                    const int32_t q = g0a[u] + (pidx - lenp[u]);
+                    const int ol = ba.has_prev ? prv[u] : 255;
+                    if (ol != 255) atomicAdd(&ba.Dw[grid_index(tb, ol, q)], -1);
+                    atomicAdd(&ba.Dw[grid_index(tb, nl, q)], 1);
                 }
             }
             __syncthreads();   // the next tile restages the LDS this pass reads
