@@ -417,6 +417,30 @@ __global__ void __launch_bounds__(kEThreads) k_adj_tiles(TreeDev T, const int32_
     }
 }
 
+// Eq. 5 on the tiles: the largest pin weight below each segment, bottom-up in LDS
+__global__ void __launch_bounds__(kEThreads) k_edge_w_tiles(TreeDev T, const int32_t *tiles, int32_t ntiles,
+                                                            const int32_t *height, const uint16_t *pin_w,
+                                                            uint16_t *seg_w)
+{
+    __shared__ TileLevels L;
+    __shared__ uint16_t wl[kETile];
+    for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+        const int32_t n0 = tiles[2 * ti], nn = tiles[2 * ti + 1] - n0;
+        const int32_t mh = tile_levels(L, height, n0, nn);
+        for (int32_t h = 0; h <= mh; ++h) {
+            for (int32_t i = L.start[h] + threadIdx.x; i < L.start[h + 1]; i += blockDim.x) {
+                const int32_t u = L.ord[i], v = n0 + u;
+                uint16_t w = T.sink_id[v] >= 0 ? pin_w[T.sink_id[v]] : 0;
+                for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) w = max(w, wl[T.ch[q] - n0]);
+                wl[u] = w;
+            }
+            __syncthreads();
+        }
+        for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) seg_w[n0 + u] = wl[u];
+        __syncthreads();
+    }
+}
+
 constexpr int kTailBlock = 1024;
 constexpr int32_t kTailNodes = 1024;   // levels this sparse run in the single-workgroup launch
 
@@ -678,7 +702,6 @@ static void sweep_levels(const LevelList &ll, bool down, Launch launch)
     }
 }
 
-static LevelList all_levels(const la_batch *b) { return LevelList{&b->h_level_ptr, b->level_nodes, b->level_ptr}; }
 static LevelList untiled_levels(const la_batch *b) { return LevelList{&b->h_ebig_ptr, b->e_big_nodes, b->e_big_ptr}; }
 
 // workgroups of the tile kernels: 8 per CU of a 256-CU part (the loop over tiles strides by it)
@@ -757,7 +780,11 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
              hipLaunchKernelGGL(k_tiers, dim3(grid_for(b->nets)), dim3(kBlock), 0, b->stream, T, b->slack,
                                 b->wns_bits, tier));
     if (mode == LA_WEIGHTS_PLAIN) {
-        sweep_levels(all_levels(b), false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
+        if (b->e_ntiles > 0)
+            LA_TIMED(b, "k_edge_w_tiles", b->stream,
+                     hipLaunchKernelGGL(k_edge_w_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T,
+                                        b->e_tile, b->e_ntiles, b->height, pin_w, seg_w));
+        sweep_levels(untiled_levels(b), false, [&](const Levels &lv, dim3 g, dim3 t, int32_t cnt) {
             LA_TIMED(b, "k_edge_w", b->stream,
                      hipLaunchKernelGGL(k_edge_w, g, t, 0, b->stream, T, lv, cnt, pin_w, seg_w));
         });
