@@ -595,16 +595,18 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
         }
         // child 1's layer, bounds and validity of every index, for the pairs of this lane
         const uint32_t pack1 = (uint32_t)l1 | (uint32_t)(lb1 + 1) << 4 | (uint32_t)(ub1 + 1) << 9 | (v1 ? 1u << 14 : 0u);
-        ChildVZ z0{0, 0};
+        // each lane's own contributions; child 1's reach the pairs by broadcast
+        ChildVZ z0{0, 0}, z1o{0, 0};
         if (v0) z0 = child_vz_j(tb, st, wd, c0, l, l0, sub);
+        if (v1) z1o = child_vz_j(tb, st, wd, c1, l, l1, sub);
 #pragma unroll
         for (int i = 0; i < kGroup; ++i) {
             const uint32_t p = __shfl(pack1, i, kGroup);
+            const ChildVZ z1{__shfl(z1o.V, i, kGroup), (uint32_t)__shfl((int32_t)z1o.Z, i, kGroup)};
             if (!v0 || !((p >> 14) & 1u)) continue;
             const int L2 = (int)(p & 15u), lb2 = (int)((p >> 4) & 31u) - 1, ub2 = (int)((p >> 9) & 31u) - 1;
             const int b = min(lo, min(l0, L2)), t = max(hi, max(l0, L2));
             if (lb0 < b && t < ub0 && lb2 < b && t < ub2) {
-                const ChildVZ z1 = child_vz_j(tb, st, wd, c1, l, L2, i);
                 uint32_t Xc;
                 const int64_t f = value(b, t, z0.V + z1.V, (int64_t)z0.Z + z1.Z, Xc);
                 const uint32_t btc = (uint32_t)(b << 4 | t);
