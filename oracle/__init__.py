@@ -86,6 +86,9 @@ def _load():
         lib.oracle_slack.argtypes = [V, V, V, ctypes.POINTER(ctypes.c_double), V, V]
         lib.oracle_edge_weights.argtypes = [V, ctypes.POINTER(_OParams), V, V, V]
         lib.oracle_adjoint_weights.argtypes = [V] * 7
+        lib.oracle_quality.argtypes = [V, I32, I32, I32] + [V] * 7 + [ctypes.POINTER(ctypes.c_double)] + \
+            [ctypes.POINTER(I64)] * 4
+        lib.oracle_quality.restype = None
         _lib = lib
     return _lib
 
@@ -235,6 +238,24 @@ def kappa(tree: Tree, P: Params, node: int, layer: int, D, H=None, self_layer: i
     H = np.zeros_like(D) if H is None else H
     return lib.oracle_kappa(tree.handle, ctypes.byref(P.s), node, layer, _p(np.ascontiguousarray(D, np.int32)),
                             _p(caps), _p(np.ascontiguousarray(H, np.int32)), self_layer)
+
+
+def quality(tree: Tree, layers, vlo, vhi, D, ofw=None) -> dict:
+    """Quality terms of an assignment (Sec. II): Eq. 3 total overflow (FP64), Eq. 2 total
+    overflow and overflowed edges, via count, wire capacitance in aF."""
+    lib = _load()
+    inst = tree.inst
+    caps = np.ascontiguousarray(inst.caps, np.uint8).reshape(-1)
+    c_af = np.ascontiguousarray(inst.c_af, np.int32)
+    tof = ctypes.c_double()
+    o2, n2, nv, wc = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    lib.oracle_quality(tree.handle, inst.X, inst.Y, inst.L, _p(c_af), _p(np.ascontiguousarray(layers, np.uint8)),
+                       _p(np.ascontiguousarray(vlo, np.uint8)), _p(np.ascontiguousarray(vhi, np.uint8)),
+                       _p(np.ascontiguousarray(D, np.int32).reshape(-1)), _p(caps),
+                       _p(None if ofw is None else np.ascontiguousarray(ofw, np.float64)), ctypes.byref(tof),
+                       ctypes.byref(o2), ctypes.byref(n2), ctypes.byref(nv), ctypes.byref(wc))
+    return {"tof": tof.value, "overflow_sum": o2.value, "overflow_edges": n2.value, "vias": nv.value,
+            "wire_cap_af": wc.value}
 
 
 def num_threads() -> int:

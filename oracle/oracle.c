@@ -24,7 +24,11 @@
  *     against one demand snapshot and then committed, and negotiation rounds
  *     with a history cost (prior art the paper cites in Sec. I);
  *   - the objective J(a) of a complete assignment and a brute-force minimum
- *     over every layer combination of a small net.
+ *     over every layer combination of a small net;
+ *   - the quality terms of a routing solution: total overflow with the
+ *     exponential per-edge overflow of Eq. 3 and with the clipped difference of
+ *     Eq. 2, the via count and the wire capacitance that stands for power in
+ *     the weighted score of Eq. 1 (Sec. II).
  *
  * Fixed-point conventions: R in mOhm, C in aF, via R in mOhm, all int32;
  * costs in int64.  T(w, R, X) = (w * ((R * X) >> 11)) >> 10 with w in Q10 and
@@ -855,3 +859,38 @@ void oracle_adjoint_weights(const otree *T, const double *G, const double *Sig, 
 
 /* Threads the OpenMP loops above use (for reporting timings). */
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* Quality terms (Sec. II).  Over every GCell edge g on every layer l, with demand d and
+ * capacity c: Eq. 3 overflow ofw(l) e^{s (d - c)}, s = 0.5 when c > 0 and 1.5 when c = 0,
+ * summed in FP64 in grid order ((y X + x) L + l); Eq. 2 overflow max(0, d - c) summed, and the
+ * number of edges with d > c.  Vias: the via span t - b of every node (Alg. 4's stack).  Wire
+ * capacitance: c(layer) * len over every tree segment (aF). */
+void oracle_quality(const otree *T, int32_t X, int32_t Y, int32_t L, const int32_t *c_af, const uint8_t *lay,
+                    const uint8_t *vlo, const uint8_t *vhi, const int32_t *D, const uint8_t *cap,
+                    const double *ofw, double *tof, int64_t *ov_sum, int64_t *ov_edges, int64_t *vias,
+                    int64_t *wire_cap)
+{
+    double t = 0.0;
+    int64_t s2 = 0, n2 = 0;
+    for (int64_t g = 0; g < (int64_t)X * Y; ++g)
+        for (int l = 0; l < L; ++l) {
+            const int64_t e = g * L + l;
+            const int64_t over = (int64_t)D[e] - (int64_t)cap[e];
+            const double s = cap[e] > 0 ? 0.5 : 1.5;
+            t += (ofw ? ofw[l] : 1.0) * exp(s * (double)over);
+            if (over > 0) {
+                s2 += over;
+                n2 += 1;
+            }
+        }
+    int64_t nv = 0, wc = 0;
+    for (int64_t v = 0; v < T->nodes; ++v) {
+        nv += (int64_t)vhi[v] - (int64_t)vlo[v];
+        if (T->parent[v] >= 0) wc += (int64_t)c_af[lay[v]] * T->len[v];
+    }
+    *tof = t;
+    *ov_sum = s2;
+    *ov_edges = n2;
+    *vias = nv;
+    *wire_cap = wc;
+}
