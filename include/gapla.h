@@ -205,6 +205,37 @@ la_status la_elmore_backward(la_batch *b, const float *dSlack, float *out_dR, fl
  * the stream and writes the HOST doubles. */
 la_status la_timing_summary(la_batch *b, const float *delay, double *tns, double *wns);
 
+/*
+ * la_quality_report -- quality terms of the current assignment (Sec. II, Eq. 1-3).
+ * Over every GCell edge of every layer l, with demand d and capacity c: tof, the sum of the
+ * Eq. 3 overflow ofw(l) e^{s (d - c)} (s = 0.5 if c > 0, 1.5 if c = 0; FP64, summed per
+ * workgroup and then in workgroup order, so within rounding of any other order);
+ * overflow_sum, the sum of the Eq. 2 overflow max(0, d - c), and overflow_edges, the number
+ * of edges with d > c.  vias: the sum over tree nodes of the via span (via_hi - via_lo) of
+ * the last la_assign.  wire_cap_af: the sum over tree segments of c(layer) * length, the
+ * capacitance that stands for power.  The integer sums are exact.  With delays (DEVICE
+ * [sinks], ps; NULL skips timing) it also reports WNS and TNS as la_timing_summary does and
+ * the Eq. 1 score w1 (WNS - r1) + w2 (TNS - r2) / N_end + w3 (pow - r3) + w4 tof, with
+ * N_end = sinks and pow = wire_cap_af / 1000 (fF); without delays or weights score = 0.
+ * ofw: HOST [L] overflow weight per layer (NULL = all 1).  Synchronises the batch's stream
+ * and writes the HOST struct `out`.  LA_ERR_INVALID_ARG for NULL b or out.
+ */
+typedef struct {
+    double w1, w2, w3, w4;   /* weights of WNS, TNS / N_end, power and total overflow */
+    double r1, r2, r3;       /* reference WNS, TNS, power */
+} la_score_weights;
+typedef struct {
+    double tof;              /* Eq. 3 total overflow */
+    int64_t overflow_sum;    /* Eq. 2 total overflow */
+    int64_t overflow_edges;
+    int64_t vias;
+    int64_t wire_cap_af;
+    double wns_ps, tns_ps;   /* 0 without delays */
+    double score;
+} la_quality;
+la_status la_quality_report(la_batch *b, const double *ofw, const float *delay, const la_score_weights *sw,
+                            la_quality *out);
+
 #define LA_WEIGHTS_PLAIN 0    /* Eq. 4 pin weights, Eq. 5 edge weights, lambda = (w*r_est)>>10 */
 #define LA_WEIGHTS_ADJOINT 1  /* weights and lambda from the reverse sweep of weighted TNS     */
 

@@ -23,7 +23,8 @@ LA_WEIGHTS_PLAIN, LA_WEIGHTS_ADJOINT = 0, 1
 W_CONG, W_CAP, W_D, W_VIA, HIST_INC = 1000, 100, 1, 100000, 64
 
 EXPORTS = ["la_build_batch", "la_batch_info", "la_assign", "la_vias", "la_demand", "la_reset", "la_batch_rc",
-           "la_elmore", "la_elmore_rc", "la_elmore_backward", "la_timing_summary", "la_timing_weights",
+           "la_elmore", "la_elmore_rc", "la_elmore_backward", "la_timing_summary", "la_quality_report",
+           "la_timing_weights",
            "la_default_cong_lut", "la_save_state", "la_load_state", "la_sync", "la_profile_begin", "la_profile_end",
            "la_free_batch", "la_status_str", "la_last_error"]
 
@@ -54,6 +55,16 @@ class la_info(ctypes.Structure):
 
 class la_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", I32), ("total_ms", ctypes.c_double)]
+
+
+class la_score_weights(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("w1", "w2", "w3", "w4", "r1", "r2", "r3")]
+
+
+class la_quality(ctypes.Structure):
+    _fields_ = [("tof", ctypes.c_double), ("overflow_sum", I64), ("overflow_edges", I64), ("vias", I64),
+                ("wire_cap_af", I64), ("wns_ps", ctypes.c_double), ("tns_ps", ctypes.c_double),
+                ("score", ctypes.c_double)]
 
 
 class la_weights(ctypes.Structure):
@@ -96,6 +107,7 @@ def _load():
         lib.la_elmore_rc.argtypes = [V, V, V, V]
         lib.la_elmore_backward.argtypes = [V, V, V, V]
         lib.la_timing_summary.argtypes = [V, V, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        lib.la_quality_report.argtypes = [V, V, V, ctypes.POINTER(la_score_weights), ctypes.POINTER(la_quality)]
         lib.la_timing_weights.argtypes = [V, V, I32, V, V, V, V]
         lib.la_default_cong_lut.argtypes = [I32, V, V]
         lib.la_save_state.argtypes = [V, V, ctypes.POINTER(ctypes.c_size_t)]
@@ -239,6 +251,22 @@ def la_timing_summary(b: Batch, delay):
     tns, wns = ctypes.c_double(), ctypes.c_double()
     _chk(_load().la_timing_summary(b.h, _dev(delay), ctypes.byref(tns), ctypes.byref(wns)), "la_timing_summary")
     return tns.value, wns.value
+
+
+def la_quality_report(b: Batch, ofw=None, delay=None, weights=None) -> dict:
+    """Quality terms of the current assignment: Eq. 3 and Eq. 2 total overflow, overflowed
+    edges, vias, wire capacitance (aF); WNS, TNS and the Eq. 1 score when delays are given.
+    weights: dict of w1..w4, r1..r3 (missing keys 0)."""
+    w = None
+    if ofw is not None:
+        w = np.ascontiguousarray(ofw, np.float64)
+    sw = None
+    if weights is not None:
+        sw = la_score_weights(*[float(weights.get(k, 0.0)) for k in ("w1", "w2", "w3", "w4", "r1", "r2", "r3")])
+    q = la_quality()
+    _chk(_load().la_quality_report(b.h, None if w is None else w.ctypes.data, _dev(delay),
+                                   None if sw is None else ctypes.byref(sw), ctypes.byref(q)), "la_quality_report")
+    return {k: getattr(q, k) for k, _ in la_quality._fields_}
 
 
 def la_timing_weights(b: Batch, delay, mode, seg_w_q10, pin_w_q10, lambda_mohm, net_tier):

@@ -28,6 +28,8 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
 la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t *seg_w, uint16_t *pin_w,
                          int32_t *lam, uint8_t *tier);
 la_status timing_summary(la_batch *b, const float *delay, double *tns, double *wns);
+la_status quality_report(la_batch *b, const double *ofw, const float *delay, const la_score_weights *sw,
+                         la_quality *out);
 la_status zero_i32(la_batch *b, int32_t *p, int64_t n);
 la_status interleave_vias(la_batch *b, uint8_t *out);
 
@@ -210,6 +212,15 @@ la_status la_elmore_backward(la_batch *b, const float *dSlack, float *out_dR, fl
     return elmore_backward(b, dSlack, true, out_dR, out_dC);
 }
 
+la_status la_quality_report(la_batch *b, const double *ofw, const float *delay, const la_score_weights *sw,
+                            la_quality *out)
+{
+    if (!b || !out) return set_error(LA_ERR_INVALID_ARG, "la_quality_report: NULL batch or out");
+    la_status s = set_device(b);
+    if (s != LA_OK) return s;
+    return quality_report(b, ofw, delay, sw, out);
+}
+
 la_status la_timing_summary(la_batch *b, const float *delay, double *tns, double *wns)
 {
     if (!b || !tns || !wns || (!delay && b->sinks)) return set_error(LA_ERR_INVALID_ARG, "la_timing_summary: NULL");
@@ -322,7 +333,7 @@ void la_free_batch(la_batch *b)
                     b->scratch_f, b->wns_bits, b->red, b->net_big, b->bn_order, b->bn_lvl, b->bn_lvl_off,
                     b->bn_nlev, b->tier_nets, b->tier_off, b->tier_cur, b->tier_cnt, b->claim,
                     b->cl_pre, b->cl_blk, b->cl_start, b->cl_off, b->D_alt, b->Hi,
-                    b->e_tile, b->e_big_nodes, b->e_big_ptr};
+                    b->e_tile, b->e_big_nodes, b->e_big_ptr, b->qofw, b->qpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);

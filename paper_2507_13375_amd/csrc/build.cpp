@@ -563,6 +563,8 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(alloc(&b->wns_bits, 4));
     b->red_blocks = 1024;
     chk(alloc(&b->red, (size_t)b->red_blocks * 4));
+    chk(alloc(&b->qofw, (size_t)kMaxL + 2 * (2 * kQSpan + 1)));
+    chk(alloc(&b->qpart, (size_t)kQPartials));
     if (s != LA_OK) {
         la_free_batch(b);
         return s;

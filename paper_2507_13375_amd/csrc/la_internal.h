@@ -12,6 +12,8 @@
 namespace gapla {
 
 constexpr int kMaxL = 16;          // layers supported (4-bit layer ids)
+constexpr int kQPartials = 2048 * 5;   // quality report: workgroups x partial sums
+constexpr int kQSpan = 64;             // quality report: e^{s x} tabulated for integer x in [-kQSpan, kQSpan]
 constexpr int kETile = 1024;        // nodes of one Elmore tile (whole nets, swept in one workgroup)
 constexpr int kEMaxH = 128;         // tree heights an Elmore tile handles
 constexpr int kCap = 192;          // nodes of one batched-form workgroup's LDS tile
@@ -179,6 +181,8 @@ struct la_batch {
     float *scratch_f = nullptr;         // [sinks] temporaries
     uint32_t *wns_bits = nullptr;       // ordered-int encoding of the WNS float
     double *red = nullptr;              // reduction partials
+    double *qofw = nullptr;             // overflow weights and exponential table of the quality report
+    double *qpart = nullptr;            // [kQPartials] its workgroup partial sums
     int32_t red_blocks = 0;
 
     // algorithmic work per DP round and per Elmore sweep (computed at build)

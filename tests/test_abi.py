@@ -95,3 +95,9 @@ def test_python_binding_has_no_cpu_fallback(tmp_path, monkeypatch):
     monkeypatch.setattr(la, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         la.la_status_str(0)
+
+
+def test_quality_report_rejects_null_arguments_on_host():
+    lib = la._load()
+    q = la.la_quality()
+    assert lib.la_quality_report(None, None, None, None, ctypes.byref(q)) == la.LA_ERR_INVALID_ARG
