@@ -37,6 +37,9 @@ def main():
     ap.add_argument("--forms", default="batched,plain,batched_plainw",
                     help="batched (adjoint weights), plain (Eq. 4/5 weights), batched_plainw (batched, Eq. 4/5 weights)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ablations", action="store_true",
+                    help="also run the batched+adjoint schedule without look-ahead and with other w_d / w_cap, "
+                         "and report the quality terms of each (one step each)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one device-to-device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
@@ -78,13 +81,16 @@ def main():
     lam = torch.zeros(b.nodes, dtype=torch.int32, device=dev)
     tier = torch.zeros(b.nets, dtype=torch.uint8, device=dev)
 
-    def step(form, mode):
+    def step(form, mode, lookahead=True, **weights):
         la.la_reset(b)
         H.zero_()
         for _ in range(I_ITERS):
             la.la_elmore(b, delay)
             la.la_timing_weights(b, delay, mode, sw, pw, lam, tier)
-            la.la_assign(b, sw, pw, lam, H, layers, net_tier=tier, num_tiers=11, rounds=R_ROUNDS, form=form)
+            if not lookahead:
+                lam.zero_()
+            la.la_assign(b, sw, pw, lam, H, layers, net_tier=tier, num_tiers=11, rounds=R_ROUNDS, form=form,
+                         **weights)
         la.la_elmore(b, delay)
 
     results = {}
@@ -127,6 +133,23 @@ def main():
             results[name]["quality"] = quality_rate(b, inst, q, la.la_profile_end(b))
             log("  quality: %s" % results[name]["quality"])
 
+    ablations = None
+    if args.ablations:
+        # Sec. IV ablations on synthetic data: look-ahead off, and the delay and capacitance weights
+        # scaled (from the defaults W_D = 1, W_CAP = 100)
+        ablations = {}
+        variants = [("default", {}), ("no_lookahead", {"lookahead": False}),
+                    ("w_d_x0", {"w_d": 0}), ("w_d_x4", {"w_d": 4 * la.W_D}),
+                    ("w_cap_x0", {"w_cap": 0}), ("w_cap_x10", {"w_cap": 10 * la.W_CAP})]
+        for vname, kw in variants:
+            t0 = time.time()
+            step(la.LA_FORM_BATCHED, la.LA_WEIGHTS_ADJOINT, **kw)
+            q = la.la_quality_report(b, delay=delay, weights=SCORE_WEIGHTS)
+            torch.cuda.synchronize()
+            ablations[vname] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in q.items()}
+            ablations[vname]["wall_s"] = round(time.time() - t0, 3)
+            log("ablation %-12s %s" % (vname, ablations[vname]))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(inst)
@@ -161,6 +184,8 @@ def main():
     }
     if "quality" in results.get("batched", {}):
         out["quality"] = results["batched"]["quality"]
+    if ablations is not None:
+        out["ablations"] = ablations
     if "batched" in results and "plain" in results:
         out["batched_over_plain"] = results["batched"]["nets_per_s"] / results["plain"]["nets_per_s"]
     if "batched_plainw" in results and "plain" in results:
