@@ -587,7 +587,7 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
 #pragma unroll
         for (int i = 0; i < kGroup; ++i) {
             const int64_t ki0 = __shfl(k0, i, kGroup), ki1 = __shfl(k1, i, kGroup);
-            const int li0 = __shfl(l0, i, kGroup), li1 = __shfl(l1, i, kGroup);
+            const int li0 = tb.lay[c0.dir][i < kMaxA ? i : 0], li1 = tb.lay[c1.dir][i < kMaxA ? i : 0];
             if (i < n0 && i < sub && ki0 <= k0) lb0 = li0;
             if (i < n1 && i < sub && ki1 <= k1) lb1 = li1;
             if (i < n0 && i > sub && ki0 < k0 && ub0 == 16) ub0 = li0;
@@ -640,7 +640,7 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
 #pragma unroll
             for (int i = 0; i < NAMAX; ++i) {
                 ky[i] = __shfl(kq, i, kGroup);
-                ly[i] = __shfl(lq, i, kGroup);
+                ly[i] = tb.lay[cq[q].dir][i];
                 lyp[q] |= (uint32_t)ly[i] << (4 * i);
             }
             bnd[q] = block_bounds<NAMAX>(ky, ly, nq[q]);
