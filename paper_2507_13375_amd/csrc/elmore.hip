@@ -481,7 +481,10 @@ __global__ void k_slack(TreeDev T, const float *delay, float *slack, uint32_t *w
         slack[k] = s;
         m = min(m, f2ord(s));
     }
-    atomicMin(&smin, m);
+    // one LDS atomic per wavefront, one device atomic per workgroup
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) m = min(m, (uint32_t)__shfl_down((int)m, d));
+    if ((threadIdx.x & 63) == 0) atomicMin(&smin, m);
     __syncthreads();
     if (threadIdx.x == 0) atomicMin(wns_ord, smin);
 }
@@ -771,8 +774,8 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
     const TreeDev T = tree_view(b);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, b->stream, b->wns_bits, 0xffffffffu, 1);
     LA_TIMED(b, "k_slack", b->stream,
-             hipLaunchKernelGGL(k_slack, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, delay, b->slack,
-                                b->wns_bits));
+             hipLaunchKernelGGL(k_slack, dim3(std::min(grid_for(b->sinks), 2048)), dim3(kBlock), 0, b->stream, T, delay,
+                                b->slack, b->wns_bits));
     LA_TIMED(b, "k_pin_weights", b->stream,
              hipLaunchKernelGGL(k_pin_weights, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, b->slack,
                                 b->wns_bits, pin_w));
