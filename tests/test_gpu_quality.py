@@ -64,3 +64,25 @@ def test_quality_empty_demand():
     qo = oracle.quality(T, z, z, z, np.zeros(inst.X * inst.Y * inst.L, np.int32))
     assert q["tof"] == pytest.approx(qo["tof"], rel=REL_TOF)
     assert q["overflow_sum"] == 0 and q["vias"] == 0 and q["wire_cap_af"] == qo["wire_cap_af"]
+
+
+def test_quality_min_layer():
+    # layers below min_layer are not routable: their edges sit in planes of their own
+    from helpers import make_instance
+    from test_gpu_assign import _star
+    inst = make_instance([_star(5), _star(3)], X=24, Y=24, L=8,
+                         caps=np.random.default_rng(2).integers(0, 3, (24, 24, 8)).astype(np.uint8))
+    T = oracle.Tree(inst)
+    rng = np.random.default_rng(5)
+    sw = rng.integers(0, 1025, T.nodes)
+    pw = rng.integers(0, 1025, max(T.sinks, 1))
+    lam = rng.integers(0, 500000, T.nodes)
+    o = oracle_assign(inst, sw, pw, lam, None, rounds=2, min_layer=2)
+    g = GpuRun(inst, min_layer=2)
+    g.assign(sw, pw, lam, None, rounds=2, form=la.LA_FORM_BATCHED)
+    ofw = np.linspace(1.0, 2.0, inst.L)
+    q = la.la_quality_report(g.b, ofw=ofw)
+    qo = oracle.quality(T, o["layers"], o["vlo"], o["vhi"], o["D"], ofw)
+    for k in ("overflow_sum", "overflow_edges", "vias", "wire_cap_af"):
+        assert q[k] == qo[k], k
+    assert q["tof"] == pytest.approx(qo["tof"], rel=REL_TOF)
