@@ -446,7 +446,13 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     b->el_fwd_bytes = 28.0 * (double)(M + S);
     b->el_bwd_bytes = 40.0 * (double)(M + S);
     b->stream = (hipStream_t)stream;
-    LA_HIP(hipGetDevice(&b->device));
+    {
+        const hipError_t e = hipGetDevice(&b->device);
+        if (e != hipSuccess) {
+            delete b;
+            return hip_fail(e, "hipGetDevice");
+        }
+    }
     b->tab = tab;
     b->nets = N;
     b->nodes = M;
@@ -569,19 +575,23 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
         la_free_batch(b);
         return s;
     }
-    std::vector<int32_t> lut((size_t)L * 2 * kNDelta);
-    la_default_cong_lut(L, nullptr, lut.data());
-    LA_HIP(hipMemcpy(b->lut, lut.data(), lut.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    LA_HIP(hipMemsetAsync(b->F, 0, M * b->NAmax * sizeof(int64_t), b->stream));
-    LA_HIP(hipMemsetAsync(b->S, 0, M * b->NAmax * sizeof(int32_t), b->stream));
-    LA_HIP(hipMemsetAsync(b->bt, 0, M * b->NAmax, b->stream));
-    LA_HIP(hipMemsetAsync(b->sel, 0, M * b->NAmax + kMaxA, b->stream));
-    LA_HIP(hipMemsetAsync(b->D, 0, b->Eg * sizeof(int32_t), b->stream));
-    LA_HIP(hipMemsetAsync(b->Hi, 0, b->Eg * sizeof(int32_t), b->stream));   // record padding stays 0
-    LA_HIP(hipMemsetAsync(b->cur_layer, 0, M, b->stream));
-    LA_HIP(hipMemsetAsync(b->vlo, 0, M, b->stream));
-    LA_HIP(hipMemsetAsync(b->vhi, 0, M, b->stream));
-    la_status r = launch_rc_pre(b);
+    // initial contents; any failure from here on frees the whole batch
+    auto init = [&]() -> la_status {
+        std::vector<int32_t> lut((size_t)L * 2 * kNDelta);
+        la_default_cong_lut(L, nullptr, lut.data());
+        LA_HIP(hipMemcpy(b->lut, lut.data(), lut.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        LA_HIP(hipMemsetAsync(b->F, 0, M * b->NAmax * sizeof(int64_t), b->stream));
+        LA_HIP(hipMemsetAsync(b->S, 0, M * b->NAmax * sizeof(int32_t), b->stream));
+        LA_HIP(hipMemsetAsync(b->bt, 0, M * b->NAmax, b->stream));
+        LA_HIP(hipMemsetAsync(b->sel, 0, M * b->NAmax + kMaxA, b->stream));
+        LA_HIP(hipMemsetAsync(b->D, 0, b->Eg * sizeof(int32_t), b->stream));
+        LA_HIP(hipMemsetAsync(b->Hi, 0, b->Eg * sizeof(int32_t), b->stream));   // record padding stays 0
+        LA_HIP(hipMemsetAsync(b->cur_layer, 0, M, b->stream));
+        LA_HIP(hipMemsetAsync(b->vlo, 0, M, b->stream));
+        LA_HIP(hipMemsetAsync(b->vhi, 0, M, b->stream));
+        return launch_rc_pre(b);
+    };
+    const la_status r = init();
     if (r != LA_OK) {
         la_free_batch(b);
         return r;
