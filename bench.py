@@ -156,7 +156,8 @@ def main():
 
     main_form = "batched" if "batched" in results else "plain"
     r = results[main_form]
-    roof = {k: roofline(b, k, v["kernels"]) for k, v in results.items()}
+    digest = inst.digest()
+    roof = {k: roofline(b, k, v["kernels"], digest) for k, v in results.items()}
     out = {
         "metric": "nets layer-assigned/sec (DP+Elmore) at 2M nets; batched vs plain, same GPU",
         "value": r["nets_per_s"],
@@ -209,9 +210,10 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(workload_digest):
     """HBM bytes per k_batched_dp launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
-    when it is missing or was taken on other kernel sources."""
+    when it is missing, was taken on other kernel sources, or on another workload (the figure is
+    per launch of one instance: its digest must match)."""
     try:
         vals = {}
         with open(TRAFFIC_FILE) as fh:
@@ -220,6 +222,8 @@ def measured_traffic():
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
         if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+            return None
+        if vals.get("workload_digest") != workload_digest:
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -230,7 +234,7 @@ def measured_traffic():
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
-def roofline(b, form, kernels):
+def roofline(b, form, kernels, workload_digest):
     """The DP enumeration kernel against the vector-ALU peak.  Algorithmic work = stacks x
     (6 ops per child + 10) over every node and entering layer (la_info.dp_ops_per_round),
     times the rounds the step runs; divided by that kernel's summed launch time."""
@@ -243,7 +247,7 @@ def roofline(b, form, kernels):
     ops = ops_round * R_ROUNDS * I_ITERS
     achieved = ops / (ms * 1e-3) / 1e12
     return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic() if form == "batched" else None,
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic(workload_digest) if form == "batched" else None,
             "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": b.dp_bytes_per_round * R_ROUNDS * I_ITERS / n,
             "launches": n, "avg_launch_us": 1e3 * ms / n, "ops_per_launch": ops / n}
 
