@@ -479,9 +479,15 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
         const int32_t lo = ba.bn_lvl_off[q], nl = ba.bn_nlev[q];
         for (int32_t h = 0; h < nl; ++h) {
             const int32_t b0 = ba.bn_lvl[lo + h], c = ba.bn_lvl[lo + h + 1] - b0;
-            for (int32_t it = threadIdx.x; it < c * NAMAX; it += blockDim.x) {
-                const int32_t n = ba.bn_order[b0 + it / NAMAX];
-                const int j = it % NAMAX;
+            // most levels of a tall tree hold a few nodes: then each item takes a group of
+            // kGroup lanes (one to three children lane-parallel, others on the first lane)
+            const bool grp = a.w.w_via > 0 && c * NAMAX <= kThreads / kGroup;
+            const int32_t span = grp ? c * NAMAX * kGroup : c * NAMAX;
+            for (int32_t it = threadIdx.x; it < span; it += blockDim.x) {
+                const int32_t gi = grp ? it / kGroup : it;
+                const int sub = grp ? it % kGroup : 0;
+                const int32_t n = ba.bn_order[b0 + gi / NAMAX];
+                const int j = gi % NAMAX;
                 const bool root = a.T.parent[n] < 0;
                 int l;
                 if (root) {
@@ -492,7 +498,16 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
                     if (j >= tb.nA[d]) continue;
                     l = tb.lay[d][j];
                 }
-                dp_node<GlobalState, NAMAX>(a, tb, gst, n, l, j, root, root ? 0 : kappa_seg(a, tb, n, l));
+                const int64_t kp = root ? 0 : kappa_seg(a, tb, n, l);
+                if (!grp) {
+                    dp_node<GlobalState, NAMAX>(a, tb, gst, n, l, j, root, kp);
+                } else {
+                    const int k = gst.nch(n);
+                    if (k >= 1 && k <= 3)
+                        dp_group<GlobalState, NAMAX>(a, tb, gst, n, l, j, root, kp, sub);
+                    else if (sub == 0)
+                        dp_node<GlobalState, NAMAX, false>(a, tb, gst, n, l, j, root, kp);
+                }
             }
             __syncthreads();
         }

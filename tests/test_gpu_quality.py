@@ -86,3 +86,19 @@ def test_quality_min_layer():
     for k in ("overflow_sum", "overflow_edges", "vias", "wire_cap_af"):
         assert q[k] == qo[k], k
     assert q["tof"] == pytest.approx(qo["tof"], rel=REL_TOF)
+
+
+@pytest.mark.parametrize("form", [la.LA_FORM_PLAIN, la.LA_FORM_BATCHED])
+def test_quality_large_excess(form):
+    # excesses far outside the tabulated [-64, 64]: 200 two-pin nets stacked on one row whose only
+    # horizontal layer has capacity 5 (over = 195, factor 0.5), 150 on a row of capacity 0
+    # (over = 150, factor 1.5); both sides evaluate e^{s x} directly there
+    from helpers import make_instance
+    X, Y, L = 24, 12, 2
+    caps = np.full((Y, X, L), 40, np.uint8)
+    caps[5, :, 0] = 5
+    caps[7, :, 0] = 0
+    nets = [([(2, 5, -1, "driver"), (20, 5, 0, "sink")], None)] * 200 + \
+           [([(3, 7, -1, "driver"), (18, 7, 0, "sink")], None)] * 150
+    inst = make_instance(nets, X=X, Y=Y, L=L, caps=caps)
+    _check(inst, 2, form, None, False)

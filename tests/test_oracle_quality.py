@@ -79,3 +79,22 @@ def test_vias_and_capacitance_of_an_assignment(small):
     # demand after the rounds: every GCell edge a segment covers holds one unit per segment
     lens = np.asarray(T.len)[nonroot]
     assert int(st.D.sum()) == int(lens.sum())
+
+
+def test_eq3_far_outside_the_tabulated_range():
+    # one edge 195 over a capacity of 5 (slope 0.5) and one 150 over a capacity of 0 (slope 1.5),
+    # every other edge empty at capacity 40: closed form of the Eq. 3 total
+    from helpers import make_instance
+    X, Y, L = 6, 5, 2
+    caps = np.full((Y, X, L), 40, np.uint8)
+    caps[1, 2, 0] = 5
+    caps[3, 4, 1] = 0
+    inst = make_instance([([(0, 0, -1, "driver"), (3, 0, 0, "sink")], None)], X=X, Y=Y, L=L, caps=caps)
+    T = oracle.Tree(inst)
+    D = np.zeros((Y, X, L), np.int32)
+    D[1, 2, 0] = 200
+    D[3, 4, 1] = 150
+    q = oracle.quality(T, *_layers(T), D.reshape(-1))
+    want = (X * Y * L - 2) * math.exp(-20.0) + math.exp(0.5 * 195) + math.exp(1.5 * 150)
+    assert q["tof"] == pytest.approx(want, rel=1e-12)
+    assert q["overflow_sum"] == 195 + 150 and q["overflow_edges"] == 2
