@@ -498,7 +498,15 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
                     if (j >= tb.nA[d]) continue;
                     l = tb.lay[d][j];
                 }
-                const int64_t kp = root ? 0 : kappa_seg(a, tb, n, l);
+                int64_t kp = 0;
+                if (!root && grp) {
+                    // the group's lanes take every kGroup-th GCell step of the segment
+                    kp = kappa_seg(a, tb, n, l, sub, kGroup);
+#pragma unroll
+                    for (int m = 1; m < kGroup; m <<= 1) kp += __shfl_xor(kp, m, kGroup);
+                } else if (!root) {
+                    kp = kappa_seg(a, tb, n, l);
+                }
                 if (!grp) {
                     dp_node<GlobalState, NAMAX>(a, tb, gst, n, l, j, root, kp);
                 } else {

@@ -115,17 +115,20 @@ __device__ __forceinline__ uint32_t rvia_d(const LayerTab &t, int a, int b)
     return (uint32_t)(d < 0 ? -d : d);
 }
 
-// congestion cost kappa_n(l): marginal Eq. 3 cost plus history along the GCell edges of segment n
-__device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb, int32_t n, int l)
+// congestion cost kappa_n(l): marginal Eq. 3 cost plus history along the GCell edges of segment n;
+// with first/stride, the part over GCell steps first, first + stride, ... (integer, so parts
+// summed in any order give the same total)
+__device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb, int32_t n, int l, int first = 0,
+                                             int stride = 1)
 {
     const int32_t len = a.T.len[n];
     const int d = a.T.dir[n];
     const int32_t step = tb.nAp[d];
-    int32_t g = route_index(tb, d, tb.jidx[l], a.T.g0[n]);
+    int32_t g = route_index(tb, d, tb.jidx[l], a.T.g0[n]) + first * step;
     const int32_t self = (a.w.self_excl && a.prev[n] == l) ? 1 : 0;
     const int32_t *lut = a.w.lut + l * 2 * kNDelta;
     int64_t s = 0;
-    for (int32_t k = 0; k < len; ++k, g += step) {
+    for (int32_t k = first; k < len; k += stride, g += stride * step) {
         const int32_t cap = a.caps[g];
         int32_t d = a.D[g] - self - cap;
         d = d < kDeltaMin ? kDeltaMin : (d > kDeltaMin + kNDelta - 1 ? kDeltaMin + kNDelta - 1 : d);
