@@ -28,7 +28,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-class GpuRun:
+class DeviceRun:
     """One batch on the GPU plus helpers to run assignment and timing through the C ABI."""
 
     def __init__(self, inst, min_layer=0):

@@ -6,7 +6,7 @@ import pytest
 import gen
 import oracle
 import paper_2507_13375_amd as la
-from gpu_util import GpuRun, assert_assign_equal, oracle_assign, say
+from gpu_util import DeviceRun, assert_assign_equal, oracle_assign, say
 from helpers import make_instance
 
 pytestmark = pytest.mark.gpu
@@ -27,7 +27,7 @@ def test_config1(form, rounds, tiered):
     tiers = w["tier"] if tiered else None
     say("c1 form=%d rounds=%d tiered=%s" % (form, rounds, tiered))
     o = oracle_assign(inst, w["seg_w"], w["pin_w"], w["lam"], tiers, rounds=rounds)
-    g = GpuRun(inst).assign(w["seg_w"], w["pin_w"], w["lam"], tiers, num_tiers=11, rounds=rounds, form=form)
+    g = DeviceRun(inst).assign(w["seg_w"], w["pin_w"], w["lam"], tiers, num_tiers=11, rounds=rounds, form=form)
     assert_assign_equal(g, o, "c1")
 
 
@@ -40,7 +40,7 @@ def test_synthetic_weights_many_tiers(form):
     say("synthetic form=%d nodes=%d" % (form, T.nodes))
     o = oracle_assign(inst, sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], rounds=3,
                       w_d=3, w_via=7000)
-    g = GpuRun(inst).assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], num_tiers=7,
+    g = DeviceRun(inst).assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], num_tiers=7,
                             rounds=3, form=form, w_d=3, w_via=7000)
     assert_assign_equal(g, o, "synthetic")
 
@@ -96,13 +96,13 @@ def test_edge_cases(case, form):
     pw = rng.integers(0, 1025, max(T.sinks, 1))
     lam = rng.integers(0, 500000, T.nodes)
     o = oracle_assign(inst, sw, pw, lam, None, rounds=2, min_layer=min_layer, **kw)
-    g = GpuRun(inst, min_layer=min_layer).assign(sw, pw, lam, None, rounds=2, form=form, **kw)
+    g = DeviceRun(inst, min_layer=min_layer).assign(sw, pw, lam, None, rounds=2, form=form, **kw)
     assert_assign_equal(g, o, case)
 
 
 def test_empty_batch():
     inst = make_instance([], X=4, Y=4)
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     assert g.b.nets == 0 and g.b.nodes == 0
     g.assign(np.zeros(1), np.zeros(1), np.zeros(1))
 
@@ -113,7 +113,7 @@ def test_config2_full(form):
     w = _weights_from_oracle(inst)
     say("c2 full form=%d" % form)
     o = oracle_assign(inst, w["seg_w"], w["pin_w"], w["lam"], w["tier"], rounds=1)
-    g = GpuRun(inst).assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=1, form=form)
+    g = DeviceRun(inst).assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=1, form=form)
     assert_assign_equal(g, o, "c2")
 
 
@@ -143,7 +143,7 @@ def test_config3_full_size_sampled(form):
     # result is fixed by the net alone and the oracle checks it one by one
     inst = gen.config(3)
     say("c3 full sampled form=%d" % form)
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     n = g.b.nodes
     sw = gen.synthetic_weights(n, g.b.sinks, g.b.nets, seed=11)
     res = g.assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], None, rounds=1, form=form)
@@ -179,7 +179,7 @@ def test_nets_larger_than_a_tile(form):
     sw = gen.synthetic_weights(T.nodes, T.sinks, T.nets, seed=8, n_tiers=3)
     say("big nets form=%d max nodes %d" % (form, sizes.max()))
     o = oracle_assign(inst, sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], rounds=2)
-    g = GpuRun(inst).assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], num_tiers=3,
+    g = DeviceRun(inst).assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], num_tiers=3,
                             rounds=2, form=form)
     assert_assign_equal(g, o, "big")
 
@@ -189,8 +189,8 @@ def test_graph_replays_match_eager_plain_form():
     # synchronisation in between, must give the plain (eager) form's result
     inst = gen.config(2, num_nets=30000)
     w = _weights_from_oracle(inst)
-    ref = GpuRun(inst).assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=3)
-    g = GpuRun(inst)
+    ref = DeviceRun(inst).assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=3)
+    g = DeviceRun(inst)
     for rep in range(4):
         la.la_reset(g.b)
         g.H.zero_()
@@ -203,12 +203,12 @@ def test_graph_replays_match_eager_plain_form():
 def test_checkpoint_resume_on_gpu():
     inst = gen.config(1)
     w = _weights_from_oracle(inst)
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     g.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=2, form=la.LA_FORM_BATCHED)
     state = la.la_save_state(g.b)
     H_saved = g.H.clone()
     nxt = g.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=1, form=la.LA_FORM_BATCHED)
-    g2 = GpuRun(inst)
+    g2 = DeviceRun(inst)
     la.la_load_state(g2.b, state)
     g2.H.copy_(H_saved)
     again = g2.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=1, form=la.LA_FORM_PLAIN)
@@ -218,7 +218,7 @@ def test_checkpoint_resume_on_gpu():
 
 def test_out_of_range_batch_index_is_rejected():
     inst = gen.config(1)
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     n = g.b.nodes
     for form in FORMS:
         with pytest.raises(la.LAError) as e:
@@ -236,7 +236,7 @@ def test_merged_single_net_batches():
     tiers[:40] = np.arange(40)
     say("merged batches: %d nets" % T.nets)
     o = oracle_assign(inst, sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], tiers, rounds=2)
-    run = GpuRun(inst)
+    run = DeviceRun(inst)
     la.la_profile_begin(run.b)
     g = run.assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], tiers, num_tiers=41, rounds=2,
                    form=la.LA_FORM_BATCHED)

@@ -9,7 +9,7 @@ import pytest
 import gen
 import oracle
 import paper_2507_13375_amd as la
-from gpu_util import GpuRun, host, oracle_assign, say
+from gpu_util import DeviceRun, host, oracle_assign, say
 from test_gpu_assign import _subset
 
 pytestmark = pytest.mark.gpu
@@ -24,7 +24,7 @@ def test_config5_full_size_sampled():
     say("c5: %d nets, %d input nodes, %d nets of more than 1000 pins" % (inst.num_nets, inst.num_nodes, huge.size))
     assert huge.size == 120
     T = oracle.Tree(inst)
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     assert g.b.nodes == T.nodes and g.b.sinks == T.sinks
     say("c5 batch: %d LA nodes, %d sinks, %d levels" % (g.b.nodes, g.b.sinks, g.b.levels))
 

@@ -7,7 +7,7 @@ import pytest
 import gen
 import oracle
 import paper_2507_13375_amd as la
-from gpu_util import GpuRun, say
+from gpu_util import DeviceRun, say
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def test_timed_run_matches_untimed(form):
     used_tiers = len(np.unique(w["tier"]))
     runs = []
     for timed in (False, True):
-        g = GpuRun(inst)
+        g = DeviceRun(inst)
         if timed:
             la.la_profile_begin(g.b)
         r = g.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=ntier, rounds=rounds, form=form)

@@ -7,7 +7,7 @@ import pytest
 import gen
 import oracle
 import paper_2507_13375_amd as la
-from gpu_util import GpuRun, oracle_assign, say
+from gpu_util import DeviceRun, oracle_assign, say
 
 pytestmark = pytest.mark.gpu
 
@@ -18,7 +18,7 @@ REL_TOF = 1e-12  # FP64 sums in different orders
 def _check(inst, rounds, form, ofw, timing):
     T = oracle.Tree(inst)
     w = oracle.plain_weights(T, oracle.Params(T))
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     g.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=rounds, form=form)
     o = oracle_assign(inst, w["seg_w"], w["pin_w"], w["lam"], w["tier"], rounds=rounds)
     sw = {"w1": -3.0, "w2": -5.0, "w3": 0.25, "w4": 2.0, "r1": -1.0, "r2": -100.0, "r3": 10.0}
@@ -57,7 +57,7 @@ def test_quality_c2_no_timing():
 def test_quality_empty_demand():
     # before any assignment: zero demand, so every edge gives ofw e^{-s c}
     inst = gen.config(1, num_nets=40)
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     q = la.la_quality_report(g.b)
     T = oracle.Tree(inst)
     z = np.zeros(T.nodes, np.uint8)
@@ -78,7 +78,7 @@ def test_quality_min_layer():
     pw = rng.integers(0, 1025, max(T.sinks, 1))
     lam = rng.integers(0, 500000, T.nodes)
     o = oracle_assign(inst, sw, pw, lam, None, rounds=2, min_layer=2)
-    g = GpuRun(inst, min_layer=2)
+    g = DeviceRun(inst, min_layer=2)
     g.assign(sw, pw, lam, None, rounds=2, form=la.LA_FORM_BATCHED)
     ofw = np.linspace(1.0, 2.0, inst.L)
     q = la.la_quality_report(g.b, ofw=ofw)

@@ -6,7 +6,7 @@ import pytest
 import gen
 import oracle
 import paper_2507_13375_amd as la
-from gpu_util import GpuRun, dev, host, say, torch
+from gpu_util import DeviceRun, dev, host, say, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,7 @@ def _rel_close(gpu, ref, rel=REL, what=""):
 def test_elmore_before_assignment(cfg, n):
     inst = gen.config(cfg, num_nets=n)
     say("elmore pre-LA c%d nets=%d" % (cfg, inst.num_nets))
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     T = oracle.Tree(inst)
     P = oracle.Params(T)
     R, C = oracle.rc(T, P, None)
@@ -52,7 +52,7 @@ def test_elmore_after_assignment_and_summary(c1):
     o = oracle.Params(T, seg_w=w["seg_w"], pin_w=w["pin_w"], lam=w["lam"])
     st = oracle.State(T)
     lay, _, _, _ = oracle.assign(T, o, st, w["tier"], rounds=2)
-    g = GpuRun(c1)
+    g = DeviceRun(c1)
     g.assign(w["seg_w"], w["pin_w"], w["lam"], w["tier"], num_tiers=11, rounds=2)
     R, C = oracle.rc(T, o, lay)
     Rg, Cg = g.rc()
@@ -95,7 +95,7 @@ def test_elmore_backward_matches_oracle_adjoint(c1, signs):
     G, Sig, dR, dC = oracle.elmore_adjoint(T, R, C, S, gbar)
     # the same sweep on |g| bounds every partial sum, hence the rounding of mixed-sign sums
     _, _, dRa, dCa = oracle.elmore_adjoint(T, R, C, S, np.abs(gbar))
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     g.elmore()
     t_ = torch()
     dRg = t_.empty(T.nodes + T.sinks, dtype=t_.float32, device="cuda")
@@ -114,7 +114,7 @@ def test_elmore_backward_matches_oracle_adjoint(c1, signs):
 
 
 def test_backward_before_forward_is_state_error(c1):
-    g = GpuRun(c1)
+    g = DeviceRun(c1)
     t_ = torch()
     z = t_.zeros(g.b.sinks, dtype=t_.float32, device="cuda")
     with pytest.raises(la.LAError) as e:
@@ -124,7 +124,7 @@ def test_backward_before_forward_is_state_error(c1):
 
 def test_autograd_function(c1):
     t_ = torch()
-    g = GpuRun(c1)
+    g = DeviceRun(c1)
     R0, C0 = g.rc()
     R = R0.clone().requires_grad_(True)
     C = C0.clone().requires_grad_(True)
@@ -160,7 +160,7 @@ def test_plain_weights(cfg, n):
     inst = gen.config(cfg, num_nets=n)
     say("plain weights c%d" % cfg)
     T, w = _oracle_weights(inst)
-    g = GpuRun(inst)
+    g = DeviceRun(inst)
     t_ = torch()
     d = g.elmore()
     sw = t_.empty(T.nodes, dtype=t_.uint16, device="cuda")
@@ -184,7 +184,7 @@ def test_plain_weights(cfg, n):
 def test_adjoint_weights(c1):
     T = oracle.Tree(c1)
     w = oracle.adjoint_form_weights(T, oracle.Params(T), None)
-    g = GpuRun(c1)
+    g = DeviceRun(c1)
     t_ = torch()
     d = g.elmore()
     sw = t_.empty(T.nodes, dtype=t_.uint16, device="cuda")
