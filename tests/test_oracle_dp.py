@@ -352,3 +352,136 @@ def test_history_saturates():
     oracle.assign(T, P, st, None, rounds=2, hist_inc=1 << 23)
     D = st.D.astype(np.int64)
     assert st.H.max() == 1 << 24 and (st.H[D >= 2] == 1 << 24).all()
+
+
+# ---- the history term of the congestion cost (Eq. 3 marginal plus history H) --------------
+
+def _seg_edges(T, v, I, l):
+    """API grid indices of the GCell edges segment parent->v covers on layer l (recounted
+    from the coordinates)."""
+    p = int(T.parent[v])
+    if T.dir[v] == 0:
+        x0, x1 = sorted((int(T.x[p]), int(T.x[v])))
+        return [((int(T.y[v]) * I.X) + x) * I.L + l for x in range(x0, x1)]
+    y0, y1 = sorted((int(T.y[p]), int(T.y[v])))
+    return [((y * I.X) + int(T.x[v])) * I.L + l for y in range(y0, y1)]
+
+
+def test_kappa_rises_by_the_history_along_the_segment():
+    # kappa_s(l) = sum over the segment's GCell edges of [LUT(D - Cap) + H]: with the demand held,
+    # adding a history map raises it by exactly the history summed over those edges on layer l
+    I, rng = _small(15, nets=50)
+    T = oracle.Tree(I)
+    P = oracle.Params(T)
+    D = rng.integers(0, 9, T.num_edges).astype(np.int32)
+    H = np.zeros(T.num_edges, np.int32)
+    H[rng.random(T.num_edges) < 0.4] = rng.integers(1, 1 << 20, 1)[0]
+    H += rng.integers(0, 3000, T.num_edges).astype(np.int32)
+    checked = 0
+    for v in np.nonzero(T.parent >= 0)[0][:200]:
+        for l in np.nonzero(I.layer_dir == T.dir[v])[0]:
+            rise = oracle.kappa(T, P, int(v), int(l), D, H) - oracle.kappa(T, P, int(v), int(l), D)
+            assert rise == int(H[_seg_edges(T, int(v), I, int(l))].astype(np.int64).sum())
+            checked += 1
+    assert checked > 300
+
+
+def test_objective_history_term_is_history_under_the_recounted_demand():
+    # W_cong * sum_s kappa_s(a_s): the history part is H summed over every GCell edge the
+    # assignment occupies, i.e. the dot product of H with the recounted demand
+    I = gen.generate(80, 24, 24, 8, 16, pin_max=6)
+    T = oracle.Tree(I)
+    rng = np.random.default_rng(16)
+    lay = np.zeros(T.nodes, np.uint8)
+    for v in range(T.nodes):
+        if T.parent[v] >= 0:
+            opts = np.nonzero(I.layer_dir == T.dir[v])[0]
+            lay[v] = opts[rng.integers(0, len(opts))]
+    D = rng.integers(0, 10, T.num_edges).astype(np.int32)
+    H = rng.integers(0, 50000, T.num_edges).astype(np.int32)
+    P = oracle.Params(T, w_cong=7, w_cap=0, w_d=0, w_via=0)
+    dj = int(oracle.objective(T, P, lay, D, H).sum() - oracle.objective(T, P, lay, D).sum())
+    occ = recount_demand(T, lay, I.X, I.Y, I.L)
+    assert dj == 7 * int(occ @ H.astype(np.int64))
+
+
+def test_history_alone_moves_a_single_segment():
+    # a straight 2-pin net with a closed-form cost per layer: history on the layer that wins
+    # without it moves the net, and F_root is the closed form with the history included
+    I = make_instance([([(1, 2, -1, "driver"), (7, 2, 0, "sink")], [[], []])], X=10, Y=4, L=8)
+    T = oracle.Tree(I)
+    rng = np.random.default_rng(17)
+    D = rng.integers(0, 12, T.num_edges).astype(np.int32)
+    P = oracle.Params(T, w_d=1, lam=np.zeros(T.nodes, np.int32))
+    r, c, vr, L = I.r_mohm, I.c_af, I.via_r_mohm, I.L
+    lut = oracle.cong_lut(L)
+    caps = I.caps.reshape(-1)
+
+    def cost(a, H):
+        k = 0
+        for x in range(1, 7):
+            g = ((2 * I.X) + x) * L + a
+            k += int(lut[a, 0 if caps[g] else 1, min(max(int(D[g]) - int(caps[g]), -32), 31) + 32]) + int(H[g])
+        C = int(c[a]) * 6
+        X = C + 2 * 1000
+        rv = int(sum(vr[:a]))
+        T_ = lambda R, XX: (1024 * ((R * XX) >> 11)) >> 10
+        return 1000 * k + 100 * C + 2 * 100000 * a + T_(int(r[a]) * 6, X) + T_(rv, X) + T_(rv, 2000)
+
+    H0 = np.zeros(T.num_edges, np.int32)
+    c0 = {a: cost(a, H0) for a in range(0, L, 2)}
+    a0 = min(c0, key=lambda a: (c0[a], a))
+    H = H0.copy()
+    for x in range(1, 7):
+        H[((2 * I.X) + x) * L + a0] = 5000 + 13 * x
+    c1 = {a: cost(a, H) for a in range(0, L, 2)}
+    a1 = min(c1, key=lambda a: (c1[a], a))
+    assert a1 != a0
+    lay, vlo, vhi, froot = _run_dp(T, P, D, H)
+    assert lay[1] == a1 and froot[0] == c1[a1]
+    jmin, best, nmin = oracle.bruteforce(T, P, 0, D, H)
+    assert jmin == c1[a1] and nmin == 1 and best[1] == a1
+
+
+# ---- tie between a child's layers: the lowest layer, and its capacitance upstream ---------
+
+def test_child_tie_takes_the_lowest_layer_and_its_capacitance():
+    # driver -H-> sink A -H-> sink B.  History on B's edges makes B's cost equal on layers 0, 2
+    # and 4 (the via stack [0, l] costs W_via l, the history the rest), and B carries no delay
+    # weight, so B's keys tie whatever A's layer.  A's history sends A to layer 4, whose stack
+    # [0, 4] holds all three tied layers: B must take the lowest, 0, and the capacitance of B on
+    # layer 0 (not 2 or 4) must reach A's downstream load, which A's delay term prices.
+    V = 1000
+    I = make_instance([([(0, 0, -1, "driver"), (5, 0, 0, "sink"), (9, 0, 1, "sink")], [[], [], []])],
+                      X=12, Y=3, L=8)
+    T = oracle.Tree(I)
+    L = I.L
+    H = np.zeros(T.num_edges, np.int32)
+    for x in range(5, 9):                      # B's edges: 4 of them
+        H[x * L + 0] = V                       # 0 * V + 4 V = 4 V
+        H[x * L + 2] = V // 2                  # 2 V + 2 V
+        H[x * L + 4] = 0                       # 4 V
+        H[x * L + 6] = 0                       # 6 V: dearer
+    for x in range(0, 5):                      # A's edges: only layer 4 is cheap
+        for l in (0, 2, 6):
+            H[x * L + l] = 1 << 20
+    sw = np.zeros(T.nodes, np.uint16)
+    sw[1] = 1024                               # A's segment prices its downstream capacitance
+    P = oracle.Params(T, seg_w=sw, pin_w=np.zeros(T.sinks, np.uint16), lam=np.zeros(T.nodes, np.int32),
+                      w_cong=1, w_cap=0, w_d=1, w_via=V)
+    D = np.zeros(T.num_edges, np.int32)
+    lay, vlo, vhi, froot = _run_dp(T, P, D, H)
+    assert lay[1] == 4 and lay[2] == 0
+    assert (vlo[1], vhi[1]) == (0, 4)
+    # F_root is J of the traced assignment, whose downstream load at A has B on layer 0
+    assert froot[0] == oracle.objective(T, P, lay, D, H)[0]
+    c, vr = I.c_af, I.via_r_mohm
+    S_A = 1000 + int(c[0]) * 4 + 1000
+    X_A = int(c[4]) * 5 + 2 * S_A
+    T_ = lambda w, R, XX: (w * ((R * XX) >> 11)) >> 10
+    lut = oracle.cong_lut(L)
+    base = int(lut[0, 0, 0 - 8 + 32])          # D = 0, cap = 8 on every edge and layer
+    F_B = 4 * base + 4 * V
+    F_A = 4 * V + F_B + 5 * base + T_(1024, int(I.r_mohm[4]) * 5, X_A)
+    root = 4 * V + F_A + T_(1024, int(sum(vr[:4])), X_A)
+    assert froot[0] == root

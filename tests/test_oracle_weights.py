@@ -106,3 +106,59 @@ def test_adjoint_weights_bound_eq5():
             stack.extend(ch[u])
         assert w["seg_w"][v] >= mx - 1
     assert (w["lam"] >= 0).all()
+
+
+def _chain_net(budget_fs):
+    # driver -H(4)-> A -V(5)-> B -H(5)-> sink: one sink, so every edge above it carries its weight
+    nodes = [(0, 0, -1, "driver"), (4, 0, 0, "steiner"), (4, 5, 1, "steiner"), (9, 5, 2, "sink")]
+    return make_instance([(nodes, [[]] * 4)], X=12, Y=8, L=8, budget_fs=[budget_fs])
+
+
+@pytest.mark.parametrize("assigned", [False, True])
+def test_adjoint_weights_closed_form_on_a_chain(assigned):
+    # One violating sink of weight w (its Eq. 4 weight, slack = WNS so rho = 1).  With
+    # J = w min(0, slack): dJ/d delay = -w, G = -w on every edge above the sink, and
+    # Sig(v) = -w * (resistance from the driver down to v, R_drv included).  The adjoint form
+    # quantises seg_w = pin_w = rne(1024 w) (= the Q10 weight itself) and
+    # lambda_s = rne(1e6 w R_up(parent(s))) with R_up in kOhm, i.e. weighted mOhm.
+    I = _chain_net(-400000)
+    T = oracle.Tree(I)
+    P = oracle.Params(T)
+    L = I.L
+    lay = np.array([0, 2, 3, 4], np.uint8) if assigned else None
+    out = oracle.adjoint_form_weights(T, P, lay)
+    assert out["slack"][0] < 0
+    q = int(golden("eq4_logistic.json")["values"][0]["q10"])   # rho = 1
+    w = q / 1024.0
+    assert out["pin_w"].tolist() == [q]
+    assert out["seg_w"].tolist() == [q, q, q, q]
+    # resistance of each RC edge, recomputed from the layer table (mOhm)
+    r, vr = [int(v) for v in I.r_mohm], [int(v) for v in I.via_r_mohm]
+    lens = [0, 4, 5, 5]
+    if assigned:
+        lays = [0, 2, 3, 4]
+        ent = [0, 0, 2, 3]                     # entering layer of each segment's upper node
+        Rm = [1000000] + [sum(vr[min(ent[v], lays[v]):max(ent[v], lays[v])]) + r[lays[v]] * lens[v]
+                          for v in range(1, 4)]
+    else:
+        ravg = [sum(r[0::2]) // (L // 2), sum(r[1::2]) // (L // 2)]
+        Rm = [1000000, ravg[0] * 4, ravg[1] * 5, ravg[0] * 5]
+    up = np.cumsum(Rm)                          # R from the driver through edge v (mOhm)
+    want = [0] + [int(np.rint(1e6 * w * up[v - 1] * 1e-6)) for v in range(1, 4)]
+    assert out["lam"].tolist() == want
+    # and G, Sig themselves
+    assert np.allclose(out["G"], -w, rtol=0, atol=1e-15)
+    assert np.allclose(out["Sig"], -w * up * 1e-6, rtol=1e-13)
+
+
+def test_adjoint_weights_quantisation_rounds_half_even_and_clamps():
+    # seg_w and pin_w clamp at 1024 and round half to even; lambda clamps at 0 and 2^31 - 1
+    I = _chain_net(-400000)
+    T = oracle.Tree(I)
+    G = np.array([-1.5, -(700.5 / 1024), -(701.5 / 1024), 0.25])
+    Sig = np.array([-3000.0, -(12.5e-6), -(13.5e-6), 5.0])
+    gbar = np.array([-(11.5 / 1024)])
+    sw, pw, lam = oracle.adjoint_weights(T, G, Sig, gbar)
+    assert sw.tolist() == [1024, 700, 702, 0]
+    assert pw.tolist() == [12]
+    assert lam.tolist() == [0, 2147483647, 12, 14]
