@@ -197,7 +197,8 @@ la_status la_elmore_rc(la_batch *b, const float *R, const float *C, float *out_d
  * Sig(v) = Sig(parent) + R_v*G(v); dR_v = G(v)*(C_v/2 + S_v),
  * dC_v = R_v*G(v)/2 + Sig(parent).
  *  dSlack: device [sinks] dJ/dslack; out_dR, out_dC: device [nodes+sinks] (either may be NULL).
- * LA_ERR_STATE if no forward ran on this batch.
+ * LA_ERR_STATE if no forward ran on this batch, or if the last forward read the batch-owned
+ * R/C views (la_elmore) and a later la_assign, la_reset or la_load_state rewrote them.
  */
 la_status la_elmore_backward(la_batch *b, const float *dSlack, float *out_dR, float *out_dC);
 
@@ -249,6 +250,8 @@ la_status la_quality_report(la_batch *b, const double *ofw, const float *delay, 
  *         average-R estimate from the driver to the segment's upper end (Sec. III-D).
  *  ADJOINT: J = sum over violating sinks of (w/1024)*slack; its reverse sweep gives
  *         seg_w = min(1024, rne(-1024 G)), pin_w = rne(-1024 g), lambda = rne(-Sig(parent)*1e6).
+ *         Needs the forward sweep that produced `delay` to be the batch's last one and still
+ *         current (LA_ERR_STATE otherwise, as for la_elmore_backward).
  * Outputs are device arrays sized [nodes], [sinks], [nodes], [nets].
  */
 la_status la_timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t *seg_w_q10,

@@ -147,11 +147,26 @@ def _stream():
     return V(torch.cuda.current_stream().cuda_stream)
 
 
+def _on(b):
+    """The batch's handle, after checking that torch's current stream is the batch's stream.
+
+    The library enqueues every call on the stream the batch was built with, while torch
+    allocates and frees the tensors it is handed on its current stream; with two different
+    streams torch could reuse a buffer the library still reads, or read an output early."""
+    import torch
+    cur = torch.cuda.current_stream().cuda_stream or 0
+    if cur != b.stream:
+        raise ValueError("batch built on stream %#x but torch's current stream is %#x; call it under "
+                         "torch.cuda.stream() of the batch's stream" % (b.stream, cur))
+    return b.h
+
+
 class Batch:
     """Owns one la_batch handle and its sizes."""
 
-    def __init__(self, handle, inst):
+    def __init__(self, handle, inst, stream=0):
         self.h = handle
+        self.stream = int(stream or 0)
         info = la_info()
         _chk(_load().la_batch_info(self.h, ctypes.byref(info)), "la_batch_info")
         self.nets, self.nodes, self.sinks = info.nets, info.nodes, info.sinks
@@ -199,9 +214,11 @@ def la_build_batch(inst, min_layer: int = 0, stream=None) -> Batch:
     grid = la_grid(inst.X, inst.Y, inst.L, min_layer, _np(k["layer_dir"]))
     rc = la_layer_rc(_np(k["r"]), _np(k["c"]), _np(k["vr"]))
     h = V()
-    _chk(lib.la_build_batch(ctypes.byref(nets), ctypes.byref(grid), ctypes.byref(rc), _np(k["caps"]),
-                            stream if stream is not None else _stream(), ctypes.byref(h)), "la_build_batch")
-    return Batch(h, inst)
+    s = stream if stream is not None else _stream()
+    s = s.value if isinstance(s, V) else s
+    _chk(lib.la_build_batch(ctypes.byref(nets), ctypes.byref(grid), ctypes.byref(rc), _np(k["caps"]), V(s),
+                            ctypes.byref(h)), "la_build_batch")
+    return Batch(h, inst, s)
 
 
 def la_free_batch(b: Batch):
@@ -213,19 +230,19 @@ def la_assign(b: Batch, seg_w_q10, pin_w_q10, lambda_mohm, history, out_layers, 
               cong_lut=None):
     w = la_weights(w_cong, w_cap, w_d, w_via, _dev(seg_w_q10), _dev(pin_w_q10), _dev(lambda_mohm), _dev(net_tier),
                    _dev(cong_lut), rounds, hist_inc, form, num_tiers)
-    _chk(_load().la_assign(b.h, ctypes.byref(w), _dev(history), _dev(out_layers)), "la_assign")
+    _chk(_load().la_assign(_on(b), ctypes.byref(w), _dev(history), _dev(out_layers)), "la_assign")
 
 
 def la_vias(b: Batch, out_lo_hi):
-    _chk(_load().la_vias(b.h, _dev(out_lo_hi)), "la_vias")
+    _chk(_load().la_vias(_on(b), _dev(out_lo_hi)), "la_vias")
 
 
 def la_demand(b: Batch, out):
-    _chk(_load().la_demand(b.h, _dev(out)), "la_demand")
+    _chk(_load().la_demand(_on(b), _dev(out)), "la_demand")
 
 
 def la_reset(b: Batch):
-    _chk(_load().la_reset(b.h), "la_reset")
+    _chk(_load().la_reset(_on(b)), "la_reset")
 
 
 def la_batch_rc(b: Batch):
@@ -236,20 +253,20 @@ def la_batch_rc(b: Batch):
 
 
 def la_elmore(b: Batch, out_delay):
-    _chk(_load().la_elmore(b.h, _dev(out_delay)), "la_elmore")
+    _chk(_load().la_elmore(_on(b), _dev(out_delay)), "la_elmore")
 
 
 def la_elmore_rc(b: Batch, R, C, out_delay):
-    _chk(_load().la_elmore_rc(b.h, _dev(R), _dev(C), _dev(out_delay)), "la_elmore_rc")
+    _chk(_load().la_elmore_rc(_on(b), _dev(R), _dev(C), _dev(out_delay)), "la_elmore_rc")
 
 
 def la_elmore_backward(b: Batch, dSlack, out_dR, out_dC):
-    _chk(_load().la_elmore_backward(b.h, _dev(dSlack), _dev(out_dR), _dev(out_dC)), "la_elmore_backward")
+    _chk(_load().la_elmore_backward(_on(b), _dev(dSlack), _dev(out_dR), _dev(out_dC)), "la_elmore_backward")
 
 
 def la_timing_summary(b: Batch, delay):
     tns, wns = ctypes.c_double(), ctypes.c_double()
-    _chk(_load().la_timing_summary(b.h, _dev(delay), ctypes.byref(tns), ctypes.byref(wns)), "la_timing_summary")
+    _chk(_load().la_timing_summary(_on(b), _dev(delay), ctypes.byref(tns), ctypes.byref(wns)), "la_timing_summary")
     return tns.value, wns.value
 
 
@@ -264,13 +281,13 @@ def la_quality_report(b: Batch, ofw=None, delay=None, weights=None) -> dict:
     if weights is not None:
         sw = la_score_weights(*[float(weights.get(k, 0.0)) for k in ("w1", "w2", "w3", "w4", "r1", "r2", "r3")])
     q = la_quality()
-    _chk(_load().la_quality_report(b.h, None if w is None else w.ctypes.data, _dev(delay),
+    _chk(_load().la_quality_report(_on(b), None if w is None else w.ctypes.data, _dev(delay),
                                    None if sw is None else ctypes.byref(sw), ctypes.byref(q)), "la_quality_report")
     return {k: getattr(q, k) for k, _ in la_quality._fields_}
 
 
 def la_timing_weights(b: Batch, delay, mode, seg_w_q10, pin_w_q10, lambda_mohm, net_tier):
-    _chk(_load().la_timing_weights(b.h, _dev(delay), mode, _dev(seg_w_q10), _dev(pin_w_q10), _dev(lambda_mohm),
+    _chk(_load().la_timing_weights(_on(b), _dev(delay), mode, _dev(seg_w_q10), _dev(pin_w_q10), _dev(lambda_mohm),
                                    _dev(net_tier)), "la_timing_weights")
 
 
@@ -283,19 +300,19 @@ def la_default_cong_lut(L: int, ofw=None) -> np.ndarray:
 
 def la_save_state(b: Batch) -> bytes:
     n = ctypes.c_size_t()
-    _chk(_load().la_save_state(b.h, None, ctypes.byref(n)), "la_save_state")
+    _chk(_load().la_save_state(_on(b), None, ctypes.byref(n)), "la_save_state")
     buf = ctypes.create_string_buffer(n.value)
-    _chk(_load().la_save_state(b.h, buf, ctypes.byref(n)), "la_save_state")
+    _chk(_load().la_save_state(_on(b), buf, ctypes.byref(n)), "la_save_state")
     return buf.raw
 
 
 def la_load_state(b: Batch, state: bytes):
     buf = ctypes.create_string_buffer(state, len(state))
-    _chk(_load().la_load_state(b.h, buf, len(state)), "la_load_state")
+    _chk(_load().la_load_state(_on(b), buf, len(state)), "la_load_state")
 
 
 def la_sync(b: Batch):
-    _chk(_load().la_sync(b.h), "la_sync")
+    _chk(_load().la_sync(_on(b)), "la_sync")
 
 
 def la_profile_begin(b: Batch):

@@ -643,6 +643,13 @@ TreeDev tree_view(const la_batch *b)
     return t;
 }
 
+// A forward sweep over the batch-owned R/C describes those arrays as they were; once they are
+// rewritten the reverse sweep and the adjoint weights must not reuse that forward's state.
+static void forget_forward_on_batch_rc(la_batch *b)
+{
+    if (b->fwd_R == b->R || b->fwd_C == b->C) b->fwd_done = b->bwd_done = false;
+}
+
 la_status launch_rc_pre(la_batch *b)
 {
     LA_TIMED(b, "k_rc", b->stream,
@@ -650,6 +657,7 @@ la_status launch_rc_pre(la_batch *b)
                                 b->tab, (const uint8_t *)nullptr, b->R, b->C));
     LA_HIP(hipGetLastError());
     b->rc_assigned = false;
+    forget_forward_on_batch_rc(b);
     return LA_OK;
 }
 
@@ -660,6 +668,7 @@ la_status launch_rc_from_layers(la_batch *b)
                                 b->tab, (const uint8_t *)b->cur_layer, b->R, b->C));
     LA_HIP(hipGetLastError());
     b->rc_assigned = true;
+    forget_forward_on_batch_rc(b);
     return LA_OK;
 }
 

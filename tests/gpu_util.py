@@ -98,3 +98,20 @@ def assert_assign_equal(g, o, what=""):
         what, bad.size, bad[:5], g["layers"][bad[:5]], o["layers"][bad[:5]])
     assert np.array_equal(g["D"], o["D"]), what + " demand differs"
     assert np.array_equal(g["H"], o["H"]), what + " history differs"
+
+
+# lower bound of each critical batch's slack/WNS bin (Alg. 1 slack bins): batch 0 is rho = 1,
+# batch k in 1..6 is [LOW[k], LOW[k-1]); batches 7..10 hold the non-critical nets (rho < 0.7)
+BIN_LOW = [1.0, 0.99, 0.96, 0.91, 0.84, 0.75, 0.7]
+
+
+def tier_flips_at_bin_edges(gt, ot, rho):
+    """Number of nets whose batch differs; every difference must be between two neighbouring
+    bins with the FP64 rho within 1e-5 of the edge between them (FP32 slack on the GPU)."""
+    diff = np.nonzero(gt != ot)[0]
+    for i in diff:
+        a, b = sorted((int(gt[i]), int(ot[i])))
+        assert a <= 6 and (b == a + 1 or (a == 6 and b >= 7)), (i, gt[i], ot[i], rho[i])
+        e = BIN_LOW[a]
+        assert abs(rho[i] - e) < 1e-5, (i, gt[i], ot[i], rho[i])
+    return diff.size

@@ -6,7 +6,7 @@ import pytest
 import gen
 import oracle
 import paper_2507_13375_amd as la
-from gpu_util import DeviceRun, dev, host, say, torch
+from gpu_util import DeviceRun, dev, host, say, tier_flips_at_bin_edges, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -141,20 +141,6 @@ def test_autograd_function(c1):
     assert _adjoint_tol(host(C.grad), dC, net_of).all()
 
 
-def _tier_boundary_ok(gt, ot, rho):
-    """Batches may differ only where the FP64 rho lies within 1e-5 of the bin edge between them."""
-    edges = np.array([1.0, 0.99, 0.96, 0.91, 0.84, 0.75, 0.7])
-    diff = np.nonzero(gt != ot)[0]
-    for i in diff:
-        a, b = sorted((int(gt[i]), int(ot[i])))
-        if b > 7 or a > 6:
-            e = 0.7
-        else:
-            e = edges[b] if b < len(edges) else 0.7
-        assert abs(rho[i] - e) < 1e-5 * max(1.0, abs(e)), (i, gt[i], ot[i], rho[i])
-    return diff.size
-
-
 @pytest.mark.parametrize("cfg,n", [(1, None), (2, 40000)])
 def test_plain_weights(cfg, n):
     inst = gen.config(cfg, num_nets=n)
@@ -177,7 +163,7 @@ def test_plain_weights(cfg, n):
     ns = np.full(T.nets, np.inf)
     sink_net = np.searchsorted(T.net_ptr, T.sink_node, side="right") - 1
     np.minimum.at(ns, sink_net, sl)
-    flips = _tier_boundary_ok(tg, w["tier"], ns / w["wns"])
+    flips = tier_flips_at_bin_edges(tg, w["tier"], ns / w["wns"])
     say("pin weight LSB diffs %d, tier flips %d" % (int((pwg != w["pin_w"]).sum()), flips))
 
 
@@ -196,3 +182,212 @@ def test_adjoint_weights(c1):
     assert np.abs(pwg - w["pin_w"]).max() <= 1
     assert np.abs(swg - w["seg_w"]).max() <= 1
     assert (np.abs(lg - w["lam"]) <= 1 + 1e-5 * np.abs(w["lam"])).all()
+
+
+def _net_of(T):
+    node_net = np.searchsorted(T.net_ptr, np.arange(T.nodes), side="right") - 1
+    return np.concatenate([node_net, node_net[T.sink_node]])
+
+
+def _heights(T):
+    h = np.zeros(T.nodes, np.int64)
+    changed = True
+    par = T.parent
+    while changed:                               # relax: h(parent) >= h(child) + 1
+        nonroot = par >= 0
+        cand = np.zeros(T.nodes, np.int64)
+        np.maximum.at(cand, par[nonroot], h[nonroot] + 1)
+        changed = bool((cand > h).any())
+        h = np.maximum(h, cand)
+    return h
+
+
+def test_untiled_nets_elmore_adjoint_and_eq5():
+    # nets of more than 1024 layer-assignment nodes, or of height 128 or more, do not fit an
+    # Elmore tile: their sweeps run in the per-level kernels (one launch per dense level, one
+    # workgroup over the sparse top levels).  Forward, reverse sweep and Eq. 5 weights of those
+    # nets against the FP64 oracle.
+    inst = gen.generate(240, 256, 256, 10, 23, pin_law=1, pin_max=16, placement=2, fanout_every=40,
+                        fanout_min=1000, fanout_max=1600, cap_min=4, cap_max=10, budget_min_fs=-400000,
+                        budget_max_fs=-100000)
+    T = oracle.Tree(inst)
+    sizes = np.diff(T.net_ptr)
+    h = _heights(T)
+    net_h = np.zeros(T.nets, np.int64)
+    np.maximum.at(net_h, np.searchsorted(T.net_ptr, np.arange(T.nodes), side="right") - 1, h)
+    untiled = (sizes > 1024) | (net_h >= 128)
+    say("untiled nets: %d of %d (largest %d nodes, tallest %d levels)" % (untiled.sum(), T.nets, sizes.max(),
+                                                                          net_h.max() + 1))
+    assert untiled.sum() >= 3
+    P = oracle.Params(T)
+    R, C = oracle.rc(T, P, None)
+    S, t, d = oracle.elmore(T, R, C)
+    g = DeviceRun(inst)
+    dg = g.elmore()
+    _rel_close(host(dg)[:T.sinks], d, REL, "delay")
+    # reverse sweep for a weighted TNS
+    rng = np.random.default_rng(29)
+    dslack = rng.uniform(0, 1, T.sinks).astype(np.float32)
+    G, Sig, dR, dC = oracle.elmore_adjoint(T, R, C, S, -dslack.astype(np.float64))
+    t_ = torch()
+    dRg = t_.empty(T.nodes + T.sinks, dtype=t_.float32, device="cuda")
+    dCg = t_.empty_like(dRg)
+    la.la_elmore_backward(g.b, dev(dslack), dRg, dCg)
+    net_of = _net_of(T)
+    for name, gpu, ref in (("dR", host(dRg), dR), ("dC", host(dCg), dC)):
+        ok = _adjoint_tol(gpu, ref, net_of)
+        assert ok.all(), "%s: %d bad (%d in untiled nets)" % (name, (~ok).sum(), (~ok & untiled[net_of]).sum())
+    # plain weights: Eq. 5 over the untiled nets' levels
+    w = oracle.plain_weights(T, P)
+    d2 = g.elmore()
+    sw = t_.empty(T.nodes, dtype=t_.uint16, device="cuda")
+    pw = t_.empty(max(T.sinks, 1), dtype=t_.uint16, device="cuda")
+    lam = t_.empty(T.nodes, dtype=t_.int32, device="cuda")
+    tier = t_.empty(T.nets, dtype=t_.uint8, device="cuda")
+    la.la_timing_weights(g.b, d2, la.LA_WEIGHTS_PLAIN, sw, pw, lam, tier)
+    swg, pwg, lg = host(sw).astype(np.int64), host(pw)[:T.sinks].astype(np.int64), host(lam)
+    assert np.abs(pwg - w["pin_w"]).max() <= 1
+    assert np.abs(swg - w["seg_w"]).max() <= 1
+    same = swg == w["seg_w"]
+    assert (lg[same] == w["lam"][same]).all()
+    # where the pin weights agree over a whole net, Eq. 5 (an integer max) must agree exactly
+    sink_net = net_of[T.nodes:]
+    bad_net = np.zeros(T.nets, bool)
+    bad_net[sink_net[pwg != w["pin_w"]]] = True
+    exact = ~bad_net[net_of[:T.nodes]]
+    assert (swg[exact] == w["seg_w"][exact]).all() and (lg[exact] == w["lam"][exact]).all()
+    say("untiled Eq. 5: %d of %d nodes in nets with identical pin weights" % (exact.sum(), T.nodes))
+
+
+def test_backward_after_reassignment_is_state_error(c1):
+    # la_elmore reads the batch-owned R/C; la_assign then rewrites them from the new layers, so
+    # that forward no longer describes them and the reverse sweep must refuse to reuse it
+    T = oracle.Tree(c1)
+    g = DeviceRun(c1)
+    g.elmore()
+    g.assign(np.full(T.nodes, 512), np.full(T.sinks, 512), np.zeros(T.nodes), None, rounds=1)
+    t_ = torch()
+    z = t_.zeros(g.b.sinks, dtype=t_.float32, device="cuda")
+    with pytest.raises(la.LAError) as e:
+        la.la_elmore_backward(g.b, z, None, None)
+    assert e.value.code == la.LA_ERR_STATE
+    sw = t_.empty(T.nodes, dtype=t_.uint16, device="cuda")
+    pw = t_.empty(T.sinks, dtype=t_.uint16, device="cuda")
+    lam = t_.empty(T.nodes, dtype=t_.int32, device="cuda")
+    tier = t_.empty(T.nets, dtype=t_.uint8, device="cuda")
+    with pytest.raises(la.LAError) as e:
+        la.la_timing_weights(g.b, z, la.LA_WEIGHTS_ADJOINT, sw, pw, lam, tier)
+    assert e.value.code == la.LA_ERR_STATE
+    # a fresh forward makes both legal again
+    d = g.elmore()
+    la.la_elmore_backward(g.b, z, None, None)
+    la.la_timing_weights(g.b, d, la.LA_WEIGHTS_ADJOINT, sw, pw, lam, tier)
+    torch().cuda.synchronize()
+
+
+def test_call_on_another_stream_is_refused(c1):
+    t_ = torch()
+    g = DeviceRun(c1)
+    d = t_.empty(g.b.sinks, dtype=t_.float32, device="cuda")
+    s = t_.cuda.Stream()
+    with t_.cuda.stream(s):
+        with pytest.raises(ValueError):
+            la.la_elmore(g.b, d)
+    la.la_elmore(g.b, d)
+
+
+def test_central_differences_on_sampled_2m_nets():
+    # The differentiation form's gradient at its full size: the 2,000,000-net batch on an assigned
+    # RC (vias included; a seeded assignment), J = sum over violating sinks of w * slack with w the
+    # Eq. 4 weight.  On 1,000 seeded nets: central differences of each net's own J_net (h = 1e-3
+    # relative, FP64) against the FP64 reverse sweep (1e-8), and the GPU's FP32 reverse sweep
+    # against both (1e-5 of max(|g|, 1e-3 x the net's largest |g|)).  J is linear in each single R
+    # and C away from slack = 0, so the differences are exact up to rounding; edges whose
+    # perturbation flips a sink of the net across slack = 0 are skipped.
+    from test_gpu_assign import _subset
+    inst = gen.config(4)
+    T = oracle.Tree(inst)
+    P = oracle.Params(T)
+    rng = np.random.default_rng(4)
+    lay = np.zeros(T.nodes, np.uint8)
+    nonroot = T.parent >= 0
+    for d in (0, 1):
+        opts = np.nonzero(inst.layer_dir == d)[0]
+        m = nonroot & (T.dir == d)
+        lay[m] = opts[rng.integers(0, len(opts), int(m.sum()))]
+    R, C = oracle.rc(T, P, lay)
+    R32, C32 = R.astype(np.float32), C.astype(np.float32)
+    R64, C64 = R32.astype(np.float64), C32.astype(np.float64)
+    S, t, d = oracle.elmore(T, R64, C64)
+    sl, wns, pw, tier = oracle.slack(T, d)
+    omega = np.where(sl < 0, pw / 1024.0, 0.0)
+    say("c4 gradient: %d nets, %d violating sinks" % (T.nets, int((sl < 0).sum())))
+    # GPU: forward on the same float R/C, then the reverse sweep of J
+    run = DeviceRun(inst)
+    t_ = torch()
+    Rg, Cg = dev(R32), dev(C32)
+    delay = t_.empty(T.sinks, dtype=t_.float32, device="cuda")
+    la.la_elmore_rc(run.b, Rg, Cg, delay)
+    dRg = t_.empty(T.nodes + T.sinks, dtype=t_.float32, device="cuda")
+    dCg = t_.empty_like(dRg)
+    la.la_elmore_backward(run.b, dev(omega.astype(np.float32)), dRg, dCg)
+    dRg, dCg = host(dRg).astype(np.float64), host(dCg).astype(np.float64)
+    # the sample: 1,000 seeded nets among those with a violating sink (the others have J_net = 0)
+    sink_net_full = np.searchsorted(T.net_ptr, T.sink_node, side="right") - 1
+    nets = np.sort(rng.choice(np.unique(sink_net_full[sl < 0]), 1000, replace=False))
+    sub = _subset(inst, nets)
+    Ts = oracle.Tree(sub)
+    nidx = np.concatenate([np.arange(T.net_ptr[i], T.net_ptr[i + 1]) for i in nets])
+    sidx = np.nonzero(np.isin(T.sink_node, nidx))[0]
+    ridx = np.concatenate([nidx, T.nodes + sidx])       # the sample's RC edges in the full index space
+    Rs, Cs = R64[ridx].copy(), C64[ridx].copy()
+    om_s = omega[sidx]
+    bud = sub.net_budget_fs[np.searchsorted(Ts.net_ptr, Ts.sink_node, side="right") - 1] * 1e-3
+    s_net = np.searchsorted(Ts.net_ptr, Ts.sink_node, side="right") - 1
+    n_of = _net_of(Ts)
+    Ss, _, ds = oracle.elmore(Ts, Rs, Cs)
+    G, Sig, dR_o, dC_o = oracle.elmore_adjoint(Ts, Rs, Cs, Ss, -om_s)
+    viol0 = bud - ds < 0
+
+    def jnet(delays):
+        j = np.zeros(Ts.nets)
+        np.add.at(j, s_net, om_s * np.minimum(0.0, bud - delays))
+        return j, (bud - delays) < 0
+
+    # the RC edges of every sampled net, position by position
+    members = [[] for _ in range(Ts.nets)]
+    for e in range(Ts.nodes + Ts.sinks):
+        members[n_of[e]].append(e)
+    depth = max(len(m) for m in members)
+    fd = {"R": np.full(len(n_of), np.nan), "C": np.full(len(n_of), np.nan)}
+    floor = {"R": np.zeros(len(n_of)), "C": np.zeros(len(n_of))}
+    h = 1e-3
+    for q in range(depth):
+        es = np.array([m[q] for m in members if len(m) > q])
+        for name, arr in (("R", Rs), ("C", Cs)):
+            x0 = arr[es].copy()
+            step = h * np.where(x0 != 0, np.abs(x0), 1.0)
+            arr[es] = x0 + step
+            jp, vp = jnet(oracle.elmore(Ts, Rs, Cs)[2])
+            arr[es] = x0 - step
+            jm, vm = jnet(oracle.elmore(Ts, Rs, Cs)[2])
+            arr[es] = x0
+            ok_sign = np.ones(Ts.nets, bool)
+            flip = (vp != viol0) | (vm != viol0)
+            ok_sign[s_net[flip]] = False
+            nn = n_of[es]
+            keep = ok_sign[nn]
+            fd[name][es[keep]] = (jp[nn] - jm[nn])[keep] / (2 * step[keep])
+            floor[name][es] = 16 * np.finfo(np.float64).eps * (np.abs(jp[nn]) + np.abs(jm[nn])) / (2 * step)
+    checked = 0
+    for name, ref, gpu in (("R", dR_o, dRg[ridx]), ("C", dC_o, dCg[ridx])):
+        m = ~np.isnan(fd[name])
+        checked += int(m.sum())
+        err_fd = np.abs(fd[name][m] - ref[m])
+        assert (err_fd <= 1e-8 * np.abs(ref[m]) + floor[name][m]).all(), "FD vs FP64 adjoint (%s)" % name
+        ok = _adjoint_tol(gpu, ref, n_of)
+        assert ok.all(), "GPU d%s vs FP64 adjoint: %d bad" % (name, (~ok).sum())
+        ok_fd = _adjoint_tol(gpu[m], fd[name][m], n_of[m])
+        assert ok_fd.all(), "GPU d%s vs central differences: %d bad" % (name, (~ok_fd).sum())
+    say("central differences: %d RC-edge partials on %d nets" % (checked, Ts.nets))
+    assert checked > 10000
