@@ -69,7 +69,20 @@ def test_config4_full_adjoint_schedule():
         gw = _adjoint_weights_gpu(run, T)
         assert np.abs(gw["seg_w"] - w["seg_w"]).max() <= 1
         assert np.abs(gw["pin_w"] - w["pin_w"]).max() <= 1
-        assert (np.abs(gw["lam"] - w["lam"]) <= 1 + 1e-5 * np.abs(w["lam"])).all()
+        # lambda = -Sig(parent) * 1e6 sums omega * (upstream R) over the sinks below; a sink
+        # whose quantised omega differs by one LSB on the two sides (FP32 against FP64 slack)
+        # moves it by at most |d omega| * (the net's summed R) * 1e6, so that is added to the
+        # rounding and FP32 allowance, net by net
+        R, _ = oracle.rc(T, P0, lay)
+        node_net = np.searchsorted(T.net_ptr, np.arange(T.nodes), side="right") - 1
+        rsum = np.bincount(np.concatenate([node_net, sink_net]), weights=R, minlength=T.nets)
+        dom = np.bincount(sink_net, weights=np.abs(gw["pin_w"] - w["pin_w"]) / 1024.0, minlength=T.nets)
+        slackq = 1e6 * dom * rsum * (1 + 1e-6)
+        dl = np.abs(gw["lam"] - w["lam"])
+        tight = dom[node_net] == 0
+        say("iteration %d: lambda max diff %d on nets with equal omegas (%d nodes), %d on the others (%d nodes)" % (
+            it, int(dl[tight].max(initial=0)), int(tight.sum()), int(dl[~tight].max(initial=0)), int((~tight).sum())))
+        assert (dl <= 1 + 1e-5 * np.abs(w["lam"]) + slackq[node_net]).all()
         ns = np.full(T.nets, np.inf)
         np.minimum.at(ns, sink_net, w["slack"])
         flips = tier_flips_at_bin_edges(gw["tier"], w["tier"], ns / w["wns"])
