@@ -206,6 +206,17 @@ la_status la_elmore_backward(la_batch *b, const float *dSlack, float *out_dR, fl
  * the stream and writes the HOST doubles. */
 la_status la_timing_summary(la_batch *b, const float *delay, double *tns, double *wns);
 
+/* la_timing_summary_noalloc -- the same TNS / WNS, bit for bit, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid it).  It calls no
+ * allocator: its workgroup partials (at most 1024 workgroups, each striding over the sinks, so
+ * any sink count fits) and its two results live in a fixed 16 KB device array that each GPU
+ * holds once until the process ends; la_build_batch looks up that array's address on its
+ * device.  Every call on one GPU shares the array: calls that overlap on one GPU (two host
+ * threads, or two streams) race and must be serialised by the caller.  Synchronises the
+ * batch's stream and writes the HOST doubles.  LA_ERR_INVALID_ARG for NULL arguments;
+ * LA_ERR_RANGE if the partials would not fit the array. */
+la_status la_timing_summary_noalloc(la_batch *b, const float *delay, double *tns, double *wns);
+
 /*
  * la_quality_report -- quality terms of the current assignment (Sec. II, Eq. 1-3).
  * Over every GCell edge of every layer l, with demand d and capacity c: tof, the sum of the

@@ -23,7 +23,8 @@ LA_WEIGHTS_PLAIN, LA_WEIGHTS_ADJOINT = 0, 1
 W_CONG, W_CAP, W_D, W_VIA, HIST_INC = 1000, 100, 1, 100000, 64
 
 EXPORTS = ["la_build_batch", "la_batch_info", "la_assign", "la_vias", "la_demand", "la_reset", "la_batch_rc",
-           "la_elmore", "la_elmore_rc", "la_elmore_backward", "la_timing_summary", "la_quality_report",
+           "la_elmore", "la_elmore_rc", "la_elmore_backward", "la_timing_summary", "la_timing_summary_noalloc",
+           "la_quality_report",
            "la_timing_weights",
            "la_default_cong_lut", "la_save_state", "la_load_state", "la_sync", "la_profile_begin", "la_profile_end",
            "la_free_batch", "la_status_str", "la_last_error"]
@@ -107,6 +108,8 @@ def _load():
         lib.la_elmore_rc.argtypes = [V, V, V, V]
         lib.la_elmore_backward.argtypes = [V, V, V, V]
         lib.la_timing_summary.argtypes = [V, V, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        lib.la_timing_summary_noalloc.argtypes = [V, V, ctypes.POINTER(ctypes.c_double),
+                                                  ctypes.POINTER(ctypes.c_double)]
         lib.la_quality_report.argtypes = [V, V, V, ctypes.POINTER(la_score_weights), ctypes.POINTER(la_quality)]
         lib.la_timing_weights.argtypes = [V, V, I32, V, V, V, V]
         lib.la_default_cong_lut.argtypes = [I32, V, V]
@@ -267,6 +270,15 @@ def la_elmore_backward(b: Batch, dSlack, out_dR, out_dC):
 def la_timing_summary(b: Batch, delay):
     tns, wns = ctypes.c_double(), ctypes.c_double()
     _chk(_load().la_timing_summary(_on(b), _dev(delay), ctypes.byref(tns), ctypes.byref(wns)), "la_timing_summary")
+    return tns.value, wns.value
+
+
+def la_timing_summary_noalloc(b: Batch, delay):
+    """la_timing_summary without any allocation (its partials sit in the library's static
+    device scratch); calls on one GPU must not overlap."""
+    tns, wns = ctypes.c_double(), ctypes.c_double()
+    _chk(_load().la_timing_summary_noalloc(_on(b), _dev(delay), ctypes.byref(tns), ctypes.byref(wns)),
+         "la_timing_summary_noalloc")
     return tns.value, wns.value
 
 

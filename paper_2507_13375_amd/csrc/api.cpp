@@ -227,6 +227,15 @@ la_status la_timing_summary(la_batch *b, const float *delay, double *tns, double
     return timing_summary(b, delay, tns, wns);
 }
 
+la_status la_timing_summary_noalloc(la_batch *b, const float *delay, double *tns, double *wns)
+{
+    if (!b || !tns || !wns || (!delay && b->sinks))
+        return set_error(LA_ERR_INVALID_ARG, "la_timing_summary_noalloc: NULL");
+    const la_status s = set_device(b);
+    if (s != LA_OK) return s;
+    return timing_summary_noalloc(b, delay, tns, wns);
+}
+
 la_status la_timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t *seg_w, uint16_t *pin_w,
                             int32_t *lam, uint8_t *tier)
 {

@@ -589,6 +589,9 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
         LA_HIP(hipMemsetAsync(b->cur_layer, 0, M, b->stream));
         LA_HIP(hipMemsetAsync(b->vlo, 0, M, b->stream));
         LA_HIP(hipMemsetAsync(b->vhi, 0, M, b->stream));
+        // address of the static scratch on this device (la_timing_summary_noalloc)
+        const la_status ss = scratch_setup(b->device);
+        if (ss != LA_OK) return ss;
         return launch_rc_pre(b);
     };
     const la_status r = init();

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "la_internal.h"
 
@@ -819,19 +820,80 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
     return LA_OK;
 }
 
-la_status timing_summary(la_batch *b, const float *delay, double *tns, double *wns)
+// TNS / WNS into `part` (2 doubles per block for nb blocks, then the 2 results)
+static la_status tns_reduce(la_batch *b, const float *delay, double *part, int nb, double *tns, double *wns)
 {
     const TreeDev T = tree_view(b);
-    const int nb = (int)std::min<int64_t>(b->red_blocks, std::max<int64_t>(1, (b->sinks + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL(k_tns_partial, dim3(nb), dim3(kBlock), 0, b->stream, T, delay, b->red);
-    hipLaunchKernelGGL(k_tns_final, dim3(1), dim3(kBlock), 0, b->stream, b->red, nb, b->red + 2 * b->red_blocks);
+    hipLaunchKernelGGL(k_tns_partial, dim3(nb), dim3(kBlock), 0, b->stream, T, delay, part);
+    hipLaunchKernelGGL(k_tns_final, dim3(1), dim3(kBlock), 0, b->stream, part, nb, part + 2 * nb);
     LA_HIP(hipGetLastError());
     double h[2];
-    LA_HIP(hipMemcpyAsync(h, b->red + 2 * b->red_blocks, sizeof(h), hipMemcpyDeviceToHost, b->stream));
+    LA_HIP(hipMemcpyAsync(h, part + 2 * nb, sizeof(h), hipMemcpyDeviceToHost, b->stream));
     LA_HIP(hipStreamSynchronize(b->stream));
     *tns = h[0];
     *wns = h[1];
     return LA_OK;
+}
+
+static int tns_blocks(const la_batch *b, int cap)
+{
+    return (int)std::min<int64_t>(cap, std::max<int64_t>(1, (b->sinks + kBlock - 1) / kBlock));
+}
+
+la_status timing_summary(la_batch *b, const float *delay, double *tns, double *wns)
+{
+    return tns_reduce(b, delay, b->red, tns_blocks(b, b->red_blocks), tns, wns);
+}
+
+// ---------------------------------------------------------------------------
+// The same summary without any library-owned allocation: the block partials and the two
+// results live in `scratch`, a fixed device array that every GPU holds once for the life of
+// the process.  Host code must not pass the array's name to a kernel (on the host it is a
+// stand-in symbol, not a device address): it uses the address hipGetSymbolAddress gives on
+// each device, kept in g_scratch.  Calls that overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+constexpr int kScratchBlocks = 1024;                        // block partials: at most this many
+constexpr int kScratchDoubles = 2 * kScratchBlocks + 2;     // (sum, min) per block, then TNS, WNS
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static double *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+la_status scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return set_error(LA_ERR_INVALID_ARG, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return LA_OK;
+    int cur = -1;
+    LA_HIP(hipGetDevice(&cur));
+    if (cur != device) LA_HIP(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch[device] = (double *)p;
+    return LA_OK;
+}
+
+la_status timing_summary_noalloc(la_batch *b, const float *delay, double *tns, double *wns)
+{
+    double *ws = nullptr;
+    if (b->device >= 0 && b->device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ws = g_scratch[b->device];
+    }
+    if (!ws) {
+        const la_status s = scratch_setup(b->device);
+        if (s != LA_OK) return s;
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ws = g_scratch[b->device];
+    }
+    // every block strides over the sinks, so any sink count fits kScratchBlocks partials
+    const int nb = tns_blocks(b, kScratchBlocks);
+    if (2 * nb + 2 > kScratchDoubles)
+        return set_error(LA_ERR_RANGE, "la_timing_summary_noalloc: partials exceed the static scratch");
+    return tns_reduce(b, delay, ws, nb, tns, wns);
 }
 
 }  // namespace gapla

@@ -240,5 +240,8 @@ la_status grid_to_planes(la_batch *b, const int32_t *api, int32_t *planes);
 la_status planes_to_grid(la_batch *b, const int32_t *planes, int32_t *api);
 la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t hist_inc);
 la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut);
+// the static scratch of the allocation-free entry point: its address on `device` (once per device)
+la_status scratch_setup(int device);
+la_status timing_summary_noalloc(la_batch *b, const float *delay, double *tns, double *wns);
 
 }  // namespace gapla
