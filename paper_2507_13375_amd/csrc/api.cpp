@@ -339,7 +339,7 @@ void la_free_batch(la_batch *b)
                     b->F, b->S, b->bt, b->sel, b->bucket_nodes, b->bucket_cnt, b->bucket_cur,
                     b->chg_node, b->chg_count, b->chg_old, b->chg_new, b->lut, b->R, b->C, b->el_S,
                     b->el_Slo, b->el_t, b->el_tlo, b->el_G, b->el_Glo, b->el_Sig, b->el_Siglo, b->slack,
-                    b->scratch_f, b->wns_bits, b->red, b->net_big, b->bn_order, b->bn_lvl, b->bn_lvl_off,
+                    b->scratch_f, b->wns_bits, b->red, b->net_big, b->net_zw, b->nrec, b->dynrec, b->cnet, b->bn_order, b->bn_lvl, b->bn_lvl_off,
                     b->bn_nlev, b->tier_nets, b->tier_off, b->tier_cur, b->tier_cnt, b->claim,
                     b->cl_pre, b->cl_blk, b->cl_start, b->cl_off, b->D_alt, b->Hi,
                     b->e_tile, b->e_big_nodes, b->e_big_ptr, b->qofw, b->qpart};

@@ -26,15 +26,19 @@ la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t inc)
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBook = 9 * kClaimNets + 8;   // ints of per-claim bookkeeping
-constexpr int kHB = 32;      // height classes of small nets per batch
-constexpr int kNB = 1 + kHB; // partition buckets per batch
+constexpr int kBook = 10 * kClaimNets + 8;  // ints of per-claim bookkeeping
+constexpr int kHB = kHeightClasses;   // height classes of small nets per batch
+constexpr int kNB = kPartBuckets;     // partition buckets per batch
 constexpr int32_t kFuseNets = 16384;   // batches with this many small nets commit from their DP kernel
 constexpr int32_t kMergeNets = 64;     // batches of at most this many small nets may share a launch
 
-// DP state and per-node inputs of one LDS tile, indexed by tile-local node id.
+// DP state and per-node inputs of one LDS tile, indexed by tile-local node id.  ZW: every net
+// of the tile has zero segment weights, look-ahead coefficients and pin weights, so the delay
+// and look-ahead terms of the cost are zero; reading the weights as the constant 0 lets the
+// compiler drop those terms (and the capacitances that only they use) -- the same costs, bit
+// for bit, for such a tile.
 
-template <int NAMAX>
+template <int NAMAX, bool ZW = false>
 struct LdsState {
     int64_t *F_;
     int32_t *S_;
@@ -51,9 +55,10 @@ struct LdsState {
     __device__ NodeIn in(int32_t s) const
     {
         const uint4 r = rec[s];
-        return NodeIn{(int32_t)r.x, r.y, r.z & 0xffffu, (int)((r.z >> 16) & 1u), (uint8_t)(r.z >> 24), (int32_t)r.w};
+        return NodeIn{(int32_t)r.x, ZW ? 0u : r.y, ZW ? 0u : (r.z & 0xffffu), (int)((r.z >> 16) & 1u),
+                      (uint8_t)(r.z >> 24), (int32_t)r.w};
     }
-    __device__ uint32_t pinw(int32_t s) const { return pinw_[s]; }
+    __device__ uint32_t pinw(int32_t s) const { return ZW ? 0u : (uint32_t)pinw_[s]; }
 };
 
 // LDS layout of one tile (byte offsets), shared by the host launch and the kernel.  The
@@ -96,6 +101,11 @@ struct BArgs {
     const int32_t *cl_off;
     const int32_t *height;
     const int32_t *net_big, *bn_order, *bn_lvl, *bn_lvl_off, *bn_nlev;
+    const uint8_t *net_zw;      // per net: all timing weights zero
+    const uint4 *nrec;          // static node records (see la_batch::nrec)
+    const uint2 *dynrec;        // this call's node weights: look-ahead, segment | pin << 16
+    const int4 *cnet;           // per sorted net position: first node, nodes, first child entry, zero flag
+    const int32_t *ch;          // child entries (global node ids)
     uint8_t *cur, *vlo, *vhi, *out_layers;
     int has_prev;
     ChangeList cl;
@@ -163,20 +173,22 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
     int32_t *lut = (int32_t *)(smem + TL::LUT);
 
     // bookkeeping: [0] claim index, [1] #tiles, [2] max height of the tile; per tile: first
-    // and end claim index, node count; per claimed net: node count, first global node,
-    // first global child entry, tile-local node base and child base
+    // and end claim index, node count, all-zero-weight flag; per claimed net: node count, first
+    // global node, first global child entry, tile-local node base and child base, zero-weight flag
     constexpr int Q = kClaimNets;
     int32_t *s_base = book, *s_nsub = book + 1, *s_maxlev = book + 2;
     int32_t *s_sub0 = book + 8, *s_sub1 = book + 8 + Q, *s_tn = book + 8 + 2 * Q;
     int32_t *s_nn = book + 8 + 3 * Q, *s_g0 = book + 8 + 4 * Q, *s_c0 = book + 8 + 5 * Q;
     int32_t *s_lb = book + 8 + 6 * Q, *s_cb = book + 8 + 7 * Q;
-    static_assert(kBook >= 8 + 8 * kClaimNets && kClaimNets <= kThreads, "bookkeeping layout");
+    int32_t *s_zn = book + 8 + 8 * Q, *s_tz = book + 8 + 9 * Q;
+    static_assert(kBook >= 8 + 10 * kClaimNets && kClaimNets <= kThreads, "bookkeeping layout");
     static_assert(kClaimUnits / (1 + kNetUnits) + 1 <= kClaimNets, "nets per claim");
 
     const int L = tb.L;
     for (int i = threadIdx.x; i < L * 2 * kNDelta; i += blockDim.x) lut[i] = a.w.lut[i];
 
     LdsState<NAMAX> st{F, S, bt, sel, chp, chl, rec, pinw};
+    LdsState<NAMAX, true> stz{F, S, bt, sel, chp, chl, rec, pinw};
     // the claims of the small nets of batches tier..tier_hi (big nets run in k_batched_big);
     // batch t lists n_t claims and an end slot from cl_off[t]
     auto nclaims = [&](int32_t t) { return max(0, ba.cl_off[t + 1] - ba.cl_off[t] - 1); };
@@ -194,11 +206,11 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
         // at most kClaimNets by construction (each net counts >= 1 + kNetUnits units)
         const int32_t p0 = ba.cl_start[coff + c], nclaim = min(ba.cl_start[coff + c + 1] - p0, kClaimNets);
         if (threadIdx.x < nclaim) {
-            const int32_t net = ba.tier_nets[p0 + threadIdx.x];
-            const int32_t g0 = a.T.net_ptr[net];
-            s_nn[threadIdx.x] = a.T.net_ptr[net + 1] - g0;
-            s_g0[threadIdx.x] = g0;
-            s_c0[threadIdx.x] = a.T.ch_ptr[g0];
+            const int4 cr = ba.cnet[p0 + threadIdx.x];
+            s_g0[threadIdx.x] = cr.x;
+            s_nn[threadIdx.x] = cr.y;
+            s_c0[threadIdx.x] = cr.z;
+            s_zn[threadIdx.x] = (a.w.w_d == 0 || cr.w) ? 1 : 0;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -212,10 +224,12 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                         s_sub1[ns - 1] = i;
                         s_tn[ns - 1] = nodes;
                     }
+                    s_tz[ns] = 1;
                     s_sub0[ns++] = i;
                     nodes = 0;
                     kids = 0;
                 }
+                s_tz[ns - 1] &= s_zn[i];
                 s_lb[i] = nodes;
                 s_cb[i] = kids;
                 nodes += n;
@@ -231,6 +245,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
         const int32_t nsub = *s_nsub;
         for (int32_t sb = 0; sb < nsub; ++sb) {
             const int32_t i0 = s_sub0[sb], i1 = s_sub1[sb], nn = s_tn[sb];
+            const bool zt = s_tz[sb] != 0;   // every net of the tile has zero timing weights
             // ---- stage the tile: topology, inputs, (height, class) counts ----------------
             for (int32_t i = threadIdx.x; i < TL::nkey; i += blockDim.x) kst[i] = 0;
             if (threadIdx.x == 0) {
@@ -239,7 +254,21 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                 chp[nn] = (int16_t)(s_cb[i1 - 1] + s_nn[i1 - 1] - 1);
             }
             __syncthreads();
-            for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
+            // one pass over the tile's nodes and its child entries (both contiguous in HBM): a
+            // node reads its static record, this call's weights and its previous layer; an
+            // entry its child's global id
+            const int32_t nent = nn - (i1 - i0);
+            for (int32_t u = threadIdx.x; u < max(nn, nent); u += blockDim.x) {
+                if (u < nent) {
+                    int32_t lo_ = i0, hi_ = i1;   // the net of entry u: last k with s_cb[k] <= u
+                    while (hi_ - lo_ > 1) {
+                        const int32_t mid = (lo_ + hi_) >> 1;
+                        if (s_cb[mid] <= u) lo_ = mid;
+                        else hi_ = mid;
+                    }
+                    chl[u] = (int16_t)(ba.ch[s_c0[lo_] + (u - s_cb[lo_])] - s_g0[lo_] + s_lb[lo_]);
+                }
+                if (u >= nn) continue;
                 int32_t lo_ = i0, hi_ = i1;      // the net of u: last k with s_lb[k] <= u
                 while (hi_ - lo_ > 1) {
                     const int32_t mid = (lo_ + hi_) >> 1;
@@ -249,28 +278,31 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                 const int32_t g0 = s_g0[lo_], lb = s_lb[lo_];
                 const int32_t g = g0 + (u - lb);
                 gid[u] = g;
-                const int32_t pg = a.T.parent[g];
-                par[u] = (int16_t)(pg < 0 ? -1 : pg - g0 + lb);
-                const int32_t e0 = a.T.ch_ptr[g], e1 = a.T.ch_ptr[g + 1];
-                const int32_t cb = s_cb[lo_] + (e0 - s_c0[lo_]);
-                chp[u] = (int16_t)cb;
-                for (int32_t e = e0; e < e1; ++e) chl[cb + (e - e0)] = (int16_t)(a.T.ch[e] - g0 + lb);
-                const int32_t h = ba.height[g];
-                const int32_t kk = e1 - e0;
-                const int32_t bk = 4 * h + (kk < 3 ? kk : 3);
+                const uint4 nr = ba.nrec[g];
+                // a zero-weight tile reads its weights as 0 (LdsState<.., true>) and skips the loads
+                const uint2 dw = zt ? make_uint2(0u, 0u) : ba.dynrec[g];
+                const int pv = a.w.self_excl ? a.prev[g] : 255;
+                const uint32_t po = nr.y >> 16;
+                const bool isroot = po == 0xffffu;
+                par[u] = (int16_t)(isroot ? -1 : (int32_t)po + lb);
+                const int32_t kk = (int32_t)(nr.w & 0xffu);
+                chp[u] = (int16_t)(s_cb[lo_] + (int32_t)(nr.w >> 24));
+                const int32_t h = (int32_t)((nr.w >> 16) & 0xffu);
+                // classes inside a level: 0 leaves, 1 one child, 2 a root with one child (one
+                // state), 3 two or more children
+                const int32_t bk = 4 * h + (kk >= 2 ? 3 : (kk == 1 && isroot ? 2 : kk));
                 key[u] = (int16_t)bk;
                 atomicAdd(&kst[bk + 1], 1);
                 atomicMax(s_maxlev, h);
-                const int32_t len = a.T.len[g];
-                const uint32_t fl = a.T.flags[g], dr = a.T.dir[g];
+                const int32_t len = (int32_t)(nr.y & 0xffffu);
+                const uint32_t fd = (nr.w >> 8) & 0xffu;
+                const uint32_t fl = fd & 15u, dr = fd >> 4;
                 lenp[u + 1] = len;
-                g0a[u] = a.T.g0[g];
-                fld[u] = (uint8_t)(fl | (dr << 4));
-                rec[u] = make_uint4((uint32_t)len, (uint32_t)a.w.lam[g],
-                                    (uint32_t)a.w.seg_w[g] | (dr << 16) | (fl << 24), (uint32_t)a.T.cpin[g]);
-                const int32_t sid = a.T.sink_id[g];
-                pinw[u] = sid >= 0 ? a.w.pin_w[sid] : (uint16_t)0;
-                prv[u] = a.w.self_excl ? a.prev[g] : (uint8_t)255;
+                g0a[u] = (int32_t)nr.x;
+                fld[u] = (uint8_t)fd;
+                rec[u] = make_uint4((uint32_t)len, dw.x, (dw.y & 0xffffu) | (dr << 16) | (fl << 24), nr.z);
+                pinw[u] = (uint16_t)(dw.y >> 16);
+                prv[u] = (uint8_t)pv;
 #pragma unroll
                 for (int jj = 0; jj < NAMAX; ++jj) kap[u * NAMAX + jj] = 0;
             }
@@ -346,53 +378,44 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             for (int32_t h = 0; h <= maxlev; ++h) {
                 const int32_t lb = h == 0 ? 0 : kst[4 * h - 1], le = kst[4 * h + 3];
                 const int32_t items = (le - lb) * NAMAX;
+                // one-lane items first: NAMAX per node of classes 0-1, one per root of class 2 (its
+                // single state), and NAMAX per node of class 3 when the via weight is zero; padded
+                // to a wavefront boundary; then, with a positive via weight, group items of kGroup
+                // lanes for class 3 (every item of a short level goes to a group)
+                int32_t c2b = lb, nA1 = 0, nR = 0, nA = 0, pA = 0, total = items * kGroup;
+                const int32_t c1e = kst[4 * h + 1], c2e = kst[4 * h + 2];
                 if (items > kThreads / kGroup) {
-                    const bool g2 = a.w.w_via > 0;
-                    const int32_t c2b = g2 ? kst[4 * h + 1] : le;   // first node with >= 2 children
-                    const int32_t nA = (c2b - lb) * NAMAX, nB = (le - c2b) * NAMAX * kGroup;
-                    const int32_t pA = (nA + 63) & ~63;
-                    const int32_t total = pA + nB;
-                    for (int32_t it = threadIdx.x; it < total; it += blockDim.x) {
-                        int32_t pos;
-                        int j, sub = -1;
-                        if (it < pA) {
-                            if (it >= nA) continue;
+                    nA1 = (c1e - lb) * NAMAX;
+                    nR = c2e - c1e;
+                    c2b = a.w.w_via > 0 ? c2e : le;
+                    nA = nA1 + nR + (c2b - c2e) * NAMAX;
+                    pA = (nA + 63) & ~63;
+                    total = pA + (le - c2b) * NAMAX * kGroup;
+                }
+                for (int32_t it = threadIdx.x; it < total; it += blockDim.x) {
+                    int32_t pos;
+                    int j, sub = -1;
+                    if (it < pA) {
+                        if (it >= nA) continue;
+                        if (it < nA1) {
                             pos = lb + it / NAMAX;
                             j = it % NAMAX;
+                        } else if (it < nA1 + nR) {
+                            pos = c1e + (it - nA1);
+                            j = 0;
                         } else {
-                            const int32_t r = it - pA;
-                            const int32_t gi = r / kGroup;
-                            sub = r % kGroup;
-                            pos = c2b + gi / NAMAX;
-                            j = gi % NAMAX;
+                            const int32_t r = it - nA1 - nR;
+                            pos = c2e + r / NAMAX;
+                            j = r % NAMAX;
                         }
-                        const int32_t u = order[pos];
-                        const bool root = par[u] < 0;
-                        int l;
-                        if (root) {
-                            if (j != 0) continue;
-                            l = 0;
-                        } else {
-                            const int d = fld[u] >> 4;
-                            if (j >= tb.nA[d]) continue;
-                            l = tb.lay[d][j];
-                        }
-                        const int64_t kp = root ? 0 : kap[u * NAMAX + j];
-                        if (sub < 0)
-                            dp_node<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp);
-                        else if (st.nch(u) <= 3)
-                            dp_group<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp, sub);
-                        else if (sub == 0)
-                            dp_node<LdsState<NAMAX>, NAMAX, false>(a, tb, st, u, l, j, root, kp);
+                    } else {
+                        const int32_t r = it - pA;
+                        const int32_t gi = r / kGroup;
+                        sub = r % kGroup;
+                        pos = c2b + gi / NAMAX;
+                        j = gi % NAMAX;
                     }
-                    __syncthreads();
-                    continue;
-                }
-                for (int32_t it = threadIdx.x; it < items * kGroup; it += blockDim.x) {
-                    const int32_t gi = it / kGroup;
-                    const int sub = it % kGroup;
-                    const int32_t u = order[lb + gi / NAMAX];
-                    const int j = gi % NAMAX;
+                    const int32_t u = order[pos];
                     const bool root = par[u] < 0;
                     int l;
                     if (root) {
@@ -405,10 +428,19 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
                     }
                     const int64_t kp = root ? 0 : kap[u * NAMAX + j];
                     const int k = st.nch(u);
-                    if (a.w.w_via > 0 && k >= 1 && k <= 3)
-                        dp_group<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp, sub);
-                    else if (sub == 0)
-                        dp_node<LdsState<NAMAX>, NAMAX, false>(a, tb, st, u, l, j, root, kp);
+                    // group items with one to three children are lane-parallel; the others run
+                    // on one lane (the group's first)
+                    if (sub >= 0 && a.w.w_via > 0 && k >= 1 && k <= 3) {
+                        if (zt)
+                            dp_group<LdsState<NAMAX, true>, NAMAX>(a, tb, stz, u, l, j, root, kp, sub);
+                        else
+                            dp_group<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp, sub);
+                    } else if (sub <= 0) {   // no child count 2..3 here while the via weight is positive
+                        if (zt)
+                            dp_node<LdsState<NAMAX, true>, NAMAX, true, false>(a, tb, stz, u, l, j, root, kp);
+                        else
+                            dp_node<LdsState<NAMAX>, NAMAX, true, false>(a, tb, st, u, l, j, root, kp);
+                    }
                 }
                 __syncthreads();
             }
@@ -546,15 +578,39 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
 // tree to the shortest (height classes 0..kHB-1, taller trees share the last class), so
 // a workgroup's tile holds trees of similar height and walks few levels, and the work
 // queue hands out the long trees first.
-__device__ __forceinline__ int32_t net_bucket(int t, bool big, int32_t h)
+__device__ __forceinline__ int32_t net_bucket(int t, bool big, bool zw, int32_t h)
 {
-    return t * kNB + (big ? 0 : 1 + (kHB - 1 - (h < kHB - 1 ? h : kHB - 1)));
+    return t * kNB + (big ? 0 : 1 + (zw ? kHB : 0) + (kHB - 1 - (h < kHB - 1 ? h : kHB - 1)));
+}
+
+// zw[net] = 1 when the net's segment weights and look-ahead coefficients (below its root) and its
+// sinks' pin weights are all zero: the DP of such a net has no delay or look-ahead term
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_net_zero_weights(TreeDev T, const uint16_t *seg_w, const uint16_t *pin_w, const int32_t *lam,
+                                   uint8_t *zw, uint2 *dynrec)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t sid = T.sink_id[v];
+        const uint32_t pw = sid >= 0 ? pin_w[sid] : 0u, sw = seg_w[v];
+        const int32_t lm = lam[v];
+        bool nz = pw != 0;
+        if (T.parent[v] >= 0) nz = nz || sw != 0 || lm != 0;
+        if (nz) zw[T.net[v]] = 0;
+        // the weights a tile stages for this node, in one 8-byte record
+        dynrec[v] = make_uint2((uint32_t)lm, sw | (pw << 16));
+    }
 }
 
 constexpr int kLdsNB = 2048;   // buckets counted in LDS; more go straight to HBM counters
 
 __global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big,
-                             const int32_t *net_ptr, const int32_t *height, int32_t *cnt, int32_t *bad)
+                             const uint8_t *zw, const int32_t *net_ptr, const int32_t *height, int32_t *cnt,
+                             int32_t *bad)
 {
     __shared__ int32_t hist[kLdsNB];
     const int32_t nb = ntier * kNB;
@@ -568,7 +624,7 @@ __global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, c
             atomicAdd(bad, 1);
             continue;
         }
-        const int32_t q = net_bucket(t, net_big[i] >= 0, height[net_ptr[i]]);
+        const int32_t q = net_bucket(t, net_big[i] >= 0, zw[i] != 0, height[net_ptr[i]]);
         atomicAdd(local ? &hist[q] : &cnt[q], 1);
     }
     __syncthreads();
@@ -590,7 +646,8 @@ __global__ void k_tier_offsets(const int32_t *cnt, int32_t nb, int32_t *off, int
 }
 
 __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big,
-                               const int32_t *net_ptr, const int32_t *height, int32_t *cur, int32_t *out)
+                               const uint8_t *zw, const int32_t *net_ptr, const int32_t *height, int32_t *cur,
+                               int32_t *out)
 {
     __shared__ int32_t hist[kLdsNB];
     __shared__ int32_t base[kLdsNB];
@@ -600,7 +657,7 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
              i += (int64_t)gridDim.x * blockDim.x) {
             const int t = tier ? tier[i] : 0;
             if (t >= ntier) continue;
-            out[atomicAdd(&cur[net_bucket(t, net_big[i] >= 0, height[net_ptr[i]])], 1)] = (int32_t)i;
+            out[atomicAdd(&cur[net_bucket(t, net_big[i] >= 0, zw[i] != 0, height[net_ptr[i]])], 1)] = (int32_t)i;
         }
         return;
     }
@@ -613,7 +670,7 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
         if (i < nets) {
             const int t = tier ? tier[i] : 0;
             if (t < ntier) {
-                q = net_bucket(t, net_big[i] >= 0, height[net_ptr[i]]);
+                q = net_bucket(t, net_big[i] >= 0, zw[i] != 0, height[net_ptr[i]]);
                 r = atomicAdd(&hist[q], 1);
             }
         }
@@ -628,11 +685,15 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
 
 // ---- claims: slices of each batch's sorted small nets by units (nodes + kNetUnits) -------
 // pre[0] = 0, pre[i + 1] = units of the net at sorted position i
-__global__ void k_claim_units(const int32_t *tier_nets, int64_t nets, const int32_t *net_ptr, int32_t *pre)
+// (and the record a claim reads per net position: first node, nodes, first child entry, zero flag)
+__global__ void k_claim_units(const int32_t *tier_nets, int64_t nets, const int32_t *net_ptr, const int32_t *ch_ptr,
+                              const uint8_t *zw, int32_t *pre, int4 *cnet)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t net = tier_nets[i];
-        pre[i + 1] = net_ptr[net + 1] - net_ptr[net] + kNetUnits;
+        const int32_t n0 = net_ptr[net], nn = net_ptr[net + 1] - n0;
+        pre[i + 1] = nn + kNetUnits;
+        cnet[i] = make_int4(n0, nn, ch_ptr[n0], zw[net]);
         if (i == 0) pre[0] = 0;
     }
 }
@@ -798,6 +859,11 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             ba.bn_lvl = b->bn_lvl;
             ba.bn_lvl_off = b->bn_lvl_off;
             ba.bn_nlev = b->bn_nlev;
+            ba.net_zw = b->net_zw;
+            ba.nrec = (const uint4 *)b->nrec;
+            ba.dynrec = (const uint2 *)b->dynrec;
+            ba.cnet = (const int4 *)b->cnet;
+            ba.ch = b->ch;
             ba.cur = b->cur_layer;
             ba.vlo = b->vlo;
             ba.vhi = b->vhi;
@@ -841,22 +907,30 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         const int L = b->tab.L;
         b->grid_batched = NA <= 4 ? occupancy_grid<4>(L) : (NA <= 6 ? occupancy_grid<6>(L) : occupancy_grid<8>(L));
     }
-    // partition the nets by batch (big nets first, then by height) and check the batch indices
+    // partition the nets by batch (big nets first, then nets with timing weights, then those
+    // without, each by height) and check the batch indices
+    LA_TIMED(b, "k_net_zero_weights", b->stream, {
+        hipLaunchKernelGGL(k_fill_u8, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, b->net_zw, (uint8_t)1, b->nets);
+        hipLaunchKernelGGL(k_net_zero_weights, dim3(grid1d(b->nodes)), dim3(256), 0, b->stream, tree_view(b),
+                           w->seg_w_q10, w->pin_w_q10, w->lambda_mohm, b->net_zw, (uint2 *)b->dynrec);
+    });
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb + 1);
     LA_TIMED(b, "k_tier_count", b->stream,
              hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
-                                b->nets, b->net_big, b->net_ptr, b->height, b->tier_cnt, b->tier_cnt + nb));
+                                b->nets, b->net_big, b->net_zw, b->net_ptr, b->height, b->tier_cnt,
+                                b->tier_cnt + nb));
     hipLaunchKernelGGL(k_tier_offsets, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb, b->tier_off, b->tier_cur,
                        b->claim, R * ntier);
     LA_TIMED(b, "k_tier_scatter", b->stream,
              hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
-                                b->nets, b->net_big, b->net_ptr, b->height, b->tier_cur, b->tier_nets));
+                                b->nets, b->net_big, b->net_zw, b->net_ptr, b->height, b->tier_cur,
+                                b->tier_nets));
     // work-queue claims of each batch's small nets
     {
         const int64_t n = b->nets + 1;
         const int32_t nchunk = (int32_t)((n + 1023) / 1024);
         hipLaunchKernelGGL(k_claim_units, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, b->tier_nets, b->nets,
-                           b->net_ptr, b->cl_pre);
+                           b->net_ptr, b->ch_ptr, b->net_zw, b->cl_pre, (int4 *)b->cnet);
         hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(256), 0, b->stream, b->cl_pre, n, b->cl_blk);
         hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, b->stream, b->cl_blk, nchunk);
         hipLaunchKernelGGL(k_scan_add, dim3(grid1d(n)), dim3(256), 0, b->stream, b->cl_pre, n, b->cl_blk);

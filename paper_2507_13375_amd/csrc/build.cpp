@@ -520,6 +520,28 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->e_big_nodes, ebig_nodes));
     chk(upload(&b->e_big_ptr, ebig_ptr));
     chk(upload(&b->height, height));
+    {
+        // one 16-byte record per node for the batched form's tiles (fields hold for nets of at
+        // most 256 nodes, the only ones a tile stages): in-plane first GCell edge; length and
+        // parent offset inside the net; pin load; child count, flags | direction << 4, height
+        // and the offset of the node's first child entry inside the net's entries
+        std::vector<uint32_t> rec((size_t)std::max<int64_t>(M, 1) * 4, 0);
+        for (int32_t i = 0; i < N; ++i) {
+            const int32_t n0 = net_ptr[i], c0 = ch_ptr[n0];
+            for (int32_t v = n0; v < net_ptr[i + 1]; ++v) {
+                uint32_t *r = &rec[(size_t)4 * v];
+                const int32_t po = parent[v] < 0 ? 0xffff : ((parent[v] - n0) & 0xffff);
+                r[0] = (uint32_t)g0[v];
+                r[1] = ((uint32_t)len[v] & 0xffffu) | ((uint32_t)po << 16);
+                r[2] = (uint32_t)cpin[v];
+                r[3] = (uint32_t)std::min(ch_ptr[v + 1] - ch_ptr[v], 255) | ((uint32_t)(flags[v] | dir[v] << 4) << 8) |
+                       ((uint32_t)std::min(height[v], 255) << 16) | ((uint32_t)std::min(ch_ptr[v] - c0, 255) << 24);
+            }
+        }
+        chk(upload(&b->nrec, rec));
+    }
+    chk(alloc(&b->dynrec, (size_t)std::max<int64_t>(M, 1) * 2));
+    chk(alloc(&b->cnet, (size_t)std::max<int64_t>(N, 1) * 4));
     chk(alloc(&b->bucket_nodes, M));
     b->n_big = (int32_t)bn_nlev.size();
     chk(upload(&b->net_big, net_big));
@@ -528,10 +550,11 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->bn_lvl_off, bn_lvl_off));
     chk(upload(&b->bn_nlev, bn_nlev));
     chk(alloc(&b->tier_nets, std::max<int64_t>(N, 1)));
-    // batch partition of the batched form: up to 256 batches x 33 buckets (+ error counter)
-    chk(alloc(&b->tier_off, 256 * 33 + 2));
-    chk(alloc(&b->tier_cur, 256 * 33 + 2));
-    chk(alloc(&b->tier_cnt, 256 * 33 + 2));
+    chk(alloc(&b->net_zw, std::max<int64_t>(N, 1)));
+    // batch partition of the batched form: up to 256 batches x kPartBuckets buckets (+ error counter)
+    chk(alloc(&b->tier_off, 256 * kPartBuckets + 2));
+    chk(alloc(&b->tier_cur, 256 * kPartBuckets + 2));
+    chk(alloc(&b->tier_cnt, 256 * kPartBuckets + 2));
     // claims: every claim but the last of a batch covers kClaimUnits units
     chk(alloc(&b->cl_pre, (size_t)N + 1));
     chk(alloc(&b->cl_blk, (size_t)N / 1024 + 2));

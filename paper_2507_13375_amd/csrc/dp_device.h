@@ -275,8 +275,9 @@ struct Best {
 // DP of node state s for its entering layer l (index j in its direction list; j = 0 and
 // l = 0 at the root).  kap is kappa_n(l) (0 at the root).  NAMAX bounds the routable
 // layers per direction.  SMALLK = false leaves out the one- and two-child orders (callers
-// that run those items with dp_group).
-template <class St, int NAMAX, bool SMALLK = true>
+// that run those items with dp_group); HULL23 = false leaves out the two- and three-child
+// hull order (callers that run every such item with dp_group when the via weight is positive).
+template <class St, int NAMAX, bool SMALLK = true, bool HULL23 = true>
 __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, const St &st, int32_t s, int l, int j,
                                         bool root, int64_t kap)
 {
@@ -362,7 +363,7 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
         }
         st.sel(c0.cs, j) = (uint8_t)sel0;
         done = true;
-    } else if (a.w.w_via > 0 && k >= 2 && k <= kHullKids && (SMALLK || k > 2)) {
+    } else if (HULL23 && a.w.w_via > 0 && k >= 2 && k <= kHullKids && (SMALLK || k > 2)) {
         // ---- two or three children: hull candidates ---------------------------------------
         // A winning stack is the hull of lo, hi and the children's choices, each choice being
         // its child's key minimum inside that hull.  Such a choice is also the minimum inside

@@ -21,6 +21,10 @@ constexpr int kClaimUnits = 220;   // work-queue claim size: sum over its nets o
 constexpr int kNetUnits = 3;
 constexpr int kClaimNets = 64;     // bound on the nets of one claim (kClaimUnits / (1 + kNetUnits) + 1)
 constexpr int kMaxA = 8;           // routable layers per direction
+constexpr int kHeightClasses = 32;   // batched work queue: height classes of small nets per batch
+// partition buckets per batch: its big nets, then its small nets with a non-zero timing weight,
+// then those whose weights are all zero, each by height class
+constexpr int kPartBuckets = 1 + 2 * kHeightClasses;
 constexpr int kNDelta = 64;        // congestion table entries per (layer, zero-capacity flag)
 constexpr int kDeltaMin = -32;
 constexpr int32_t kLutSat = 1 << 20;
@@ -155,6 +159,13 @@ struct la_batch {
     // walk their own height levels (bn_order: node ids per net by height; bn_lvl: level
     // starts into bn_order; bn_lvl_off/bn_nlev: each big net's first level and level count)
     int32_t *net_big = nullptr;
+    uint8_t *net_zw = nullptr;      // per net: 1 when every timing weight the DP reads is zero
+    // tile staging: a static 16-byte record per node (built at la_build_batch), the weights of
+    // the current la_assign call per node (look-ahead coefficient, segment | pin weight << 16),
+    // and per position of the batch-sorted net list its first node, node count, first child
+    // entry and zero-weight flag
+    uint32_t *nrec = nullptr, *dynrec = nullptr;
+    int32_t *cnet = nullptr;
     int32_t *bn_order = nullptr, *bn_lvl = nullptr, *bn_lvl_off = nullptr, *bn_nlev = nullptr;
     int32_t n_big = 0;
     int32_t *tier_nets = nullptr, *tier_off = nullptr, *tier_cur = nullptr, *tier_cnt = nullptr;
