@@ -150,11 +150,11 @@ def main():
             ablations[vname]["wall_s"] = round(time.time() - t0, 3)
             log("ablation %-12s %s" % (vname, ablations[vname]))
 
+    main_form = "batched" if "batched" in results else "plain"
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(inst)
+        cpu = cpu_baseline(inst, main_form)
 
-    main_form = "batched" if "batched" in results else "plain"
     r = results[main_form]
     digest = inst.digest()
     roof = {k: roofline(b, k, v["kernels"], digest) for k, v in results.items()}
@@ -280,32 +280,57 @@ def elmore_rate(b, kernels):
             "ms_per_sweep": ms / sweeps}
 
 
-def cpu_baseline(inst, n_max=1000000):
-    """The oracle (as it stands) on a bounded sample: the plain form's whole schedule (I
-    iterations of Elmore -> Eq. 4/5 weights -> R rounds, then Elmore) over the first nets of
-    the same workload, timed on the host threads."""
-    import gen
+def _oracle_schedule(T, adjoint):
+    """The step's schedule on the oracle: I iterations of [FP64 Elmore -> weights -> R rounds],
+    then the Elmore timing of the final assignment (the same work as one timed GPU step)."""
     import oracle
 
-    n = min(inst.num_nets, n_max)
-    sub = gen.config(4, num_nets=n) if inst.name in ("c3", "c4") else inst
-    T = oracle.Tree(sub)
-    t0 = time.time()
     P0 = oracle.Params(T)
     st = oracle.State(T)
     lay = None
     for _ in range(I_ITERS):
-        w = oracle.plain_weights(T, P0, lay)
+        w = (oracle.adjoint_form_weights if adjoint else oracle.plain_weights)(T, P0, lay)
         P = oracle.Params(T, seg_w=w["seg_w"], pin_w=w["pin_w"], lam=w["lam"])
         lay, _, _, _ = oracle.assign(T, P, st, w["tier"], rounds=R_ROUNDS)
     R, C = oracle.rc(T, P0, lay)
     oracle.elmore(T, R, C)
-    dt = time.time() - t0
+    return lay
+
+
+def cpu_baseline(inst, form, single_nets=20000):
+    """The oracle (as it stands) on the host cores: the whole workload with the reported form's
+    schedule (batched+adjoint: adjoint-form weights; plain: Eq. 4/5 weights) on every host
+    thread, then the first `single_nets` nets of the same generator on one thread."""
+    import gen
+    import oracle
+
+    adjoint = form == "batched"
+    T = oracle.Tree(inst)
     cores = oracle.num_threads()
-    log("cpu oracle: %d nets, %d rounds x %d iterations in %.1fs on %d threads" % (n, R_ROUNDS, I_ITERS, dt, cores))
-    return {"value": n * R_ROUNDS * I_ITERS / dt, "unit": "nets/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d nets of the workload, plain form schedule (%d iterations x %d rounds, then Elmore)"
-                      % (n, I_ITERS, R_ROUNDS)}
+    t0 = time.time()
+    _oracle_schedule(T, adjoint)
+    dt = time.time() - t0
+    del T
+    log("cpu oracle: %d nets, %d rounds x %d iterations in %.1fs on %d threads" % (
+        inst.num_nets, R_ROUNDS, I_ITERS, dt, cores))
+    single = None
+    if inst.name in ("c3", "c4") and single_nets:
+        sub = gen.config(4, num_nets=min(single_nets, inst.num_nets))
+        Ts = oracle.Tree(sub)
+        oracle.set_num_threads(1)
+        try:
+            t1 = time.time()
+            _oracle_schedule(Ts, adjoint)
+            ds = time.time() - t1
+        finally:
+            oracle.set_num_threads(cores)
+        single = {"value": sub.num_nets * R_ROUNDS * I_ITERS / ds, "unit": "nets/s", "cores": 1,
+                  "sample": "first %d nets of the workload, same schedule" % sub.num_nets}
+        log("cpu oracle single thread: %d nets in %.1fs" % (sub.num_nets, ds))
+    return {"value": inst.num_nets * R_ROUNDS * I_ITERS / dt, "unit": "nets/s", "cores": cores, "kind": "oracle",
+            "sample": "the whole workload (%d nets), %s schedule: %d iterations x %d rounds, then Elmore" % (
+                inst.num_nets, "adjoint-form" if adjoint else "plain-form", I_ITERS, R_ROUNDS),
+            "single_thread": single}
 
 
 if __name__ == "__main__":

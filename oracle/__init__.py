@@ -86,6 +86,7 @@ def _load():
         lib.oracle_slack.argtypes = [V, V, V, ctypes.POINTER(ctypes.c_double), V, V]
         lib.oracle_edge_weights.argtypes = [V, ctypes.POINTER(_OParams), V, V, V]
         lib.oracle_adjoint_weights.argtypes = [V] * 7
+        lib.oracle_set_num_threads.argtypes = [I32]
         lib.oracle_quality.argtypes = [V, I32, I32, I32] + [V] * 7 + [ctypes.POINTER(ctypes.c_double)] + \
             [ctypes.POINTER(I64)] * 4
         lib.oracle_quality.restype = None
@@ -261,6 +262,11 @@ def quality(tree: Tree, layers, vlo, vhi, D, ofw=None) -> dict:
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops run on."""
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing only; results do not change)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def rc(tree: Tree, P: Params, layers=None):

@@ -857,8 +857,10 @@ void oracle_adjoint_weights(const otree *T, const double *G, const double *Sig, 
     }
 }
 
-/* Threads the OpenMP loops above use (for reporting timings). */
+/* Threads the OpenMP loops above use (for reporting timings), and a way to change it (the
+ * results do not depend on it: per-net work is independent and commits are integer). */
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+void oracle_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 /* Quality terms (Sec. II).  Over every GCell edge g on every layer l, with demand d and
  * capacity c: Eq. 3 overflow ofw(l) e^{s (d - c)}, s = 0.5 when c > 0 and 1.5 when c = 0,
