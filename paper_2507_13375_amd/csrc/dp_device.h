@@ -25,6 +25,8 @@
 // la_assign bounds w_d < 2^20 and the whole cost of a net below 2^62.
 #pragma once
 
+#include <type_traits>
+
 #include "la_internal.h"
 
 namespace gapla {
@@ -506,23 +508,68 @@ __device__ __forceinline__ void dp_node(const DPArgs &a, const LayerTab &tb, con
 // equals dp_node's.  Every lane of the group must call it; lane 0 writes the state.
 constexpr int kGroup = 8;
 
+// Lane exchanges inside an aligned group of 8 lanes (half a DPP row of 16), as DPP moves on
+// the VALU instead of general lane shuffles through the LDS crossbar.  A move from a lane
+// outside the group (a shift at the group's edge) keeps the lane's own value; callers ignore it.
+namespace gx {
+constexpr int kRowShl = 0x100, kRowShr = 0x110, kHalfMirror = 0x141;
+constexpr int quad(int a, int b, int c, int d) { return a | b << 2 | c << 4 | d << 6; }
+template <int CTRL>
+__device__ __forceinline__ int32_t mov(int32_t x)
+{
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint32_t mov(uint32_t x)
+{
+    return (uint32_t)mov<CTRL>((int32_t)x);
+}
+template <int CTRL>
+__device__ __forceinline__ int64_t mov(int64_t x)
+{
+    const uint32_t lo = (uint32_t)mov<CTRL>((int32_t)(uint32_t)x), hi = (uint32_t)mov<CTRL>((int32_t)(x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+// value of group lane I in every lane of the group (sub = this lane's index in it)
+template <int I, class T>
+__device__ __forceinline__ T bcast(T x, int sub)
+{
+    constexpr int qi = I & 3, qj = (7 - I) & 3;
+    const T a = mov<quad(qi, qi, qi, qi)>(x);                 // lane I, seen from its own quad
+    const T b = mov<quad(qj, qj, qj, qj)>(mov<kHalfMirror>(x)); // lane I, seen from the other quad
+    return (sub >> 2) == (I >> 2) ? a : b;
+}
+template <int I, class F>
+__device__ __forceinline__ void each_lane(F &&f)
+{
+    if constexpr (I < kGroup) {
+        f(std::integral_constant<int, I>{});
+        each_lane<I + 1>(f);
+    }
+}
+}  // namespace gx
+
+// inclusive prefix minimum over the group's lanes 0..sub
 __device__ __forceinline__ int64_t grp_min_up(int64_t x, int sub)
 {
-#pragma unroll
-    for (int d = 1; d < kGroup; d <<= 1) {
-        const int64_t o = __shfl_up(x, d, kGroup);
-        if (sub >= d) x = o < x ? o : x;
-    }
+    int64_t o = gx::mov<gx::kRowShr + 1>(x);
+    if (sub >= 1) x = o < x ? o : x;
+    o = gx::mov<gx::kRowShr + 2>(x);
+    if (sub >= 2) x = o < x ? o : x;
+    o = gx::mov<gx::kRowShr + 4>(x);
+    if (sub >= 4) x = o < x ? o : x;
     return x;
 }
 
+// inclusive suffix minimum over the group's lanes sub..7
 __device__ __forceinline__ int64_t grp_min_down(int64_t x, int sub)
 {
-#pragma unroll
-    for (int d = 1; d < kGroup; d <<= 1) {
-        const int64_t o = __shfl_down(x, d, kGroup);
-        if (sub + d < kGroup) x = o < x ? o : x;
-    }
+    int64_t o = gx::mov<gx::kRowShl + 1>(x);
+    if (sub + 1 < kGroup) x = o < x ? o : x;
+    o = gx::mov<gx::kRowShl + 2>(x);
+    if (sub + 2 < kGroup) x = o < x ? o : x;
+    o = gx::mov<gx::kRowShl + 4>(x);
+    if (sub + 4 < kGroup) x = o < x ? o : x;
     return x;
 }
 
@@ -568,8 +615,8 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
     if (k == 1) {
         // layer l0 is a candidate when no lower layer inside its hull has a key <= its key
         // and no higher one a smaller key (exclusive scans over the lanes in layer order)
-        const int64_t below = __shfl_up(grp_min_up(v0 && l0 >= lo ? k0 : INT64_MAX, sub), 1, kGroup);
-        const int64_t above = __shfl_down(grp_min_down(v0 && l0 <= hi ? k0 : INT64_MAX, sub), 1, kGroup);
+        const int64_t below = gx::mov<gx::kRowShr + 1>(grp_min_up(v0 && l0 >= lo ? k0 : INT64_MAX, sub));
+        const int64_t above = gx::mov<gx::kRowShl + 1>(grp_min_down(v0 && l0 <= hi ? k0 : INT64_MAX, sub));
         const bool ok = v0 && (l0 < lo || sub == 0 || k0 < below) && (l0 > hi || sub == kGroup - 1 || k0 <= above);
         if (ok) {
             const ChildVZ v = child_vz_j(tb, st, wd, c0, l, l0, sub);
@@ -588,26 +635,26 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
         const int l1 = tb.lay[c1.dir][v1 ? sub : 0];
         const int64_t k1 = v1 ? child_key_j(tb, st, wd, c1, l, l1, sub) : INT64_MAX;
         int lb0 = -1, ub0 = 16, lb1 = -1, ub1 = 16;
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-            const int64_t ki0 = __shfl(k0, i, kGroup), ki1 = __shfl(k1, i, kGroup);
+        gx::each_lane<0>([&](auto I_) {
+            constexpr int i = decltype(I_)::value;
+            const int64_t ki0 = gx::bcast<i>(k0, sub), ki1 = gx::bcast<i>(k1, sub);
             const int li0 = tb.lay[c0.dir][i < kMaxA ? i : 0], li1 = tb.lay[c1.dir][i < kMaxA ? i : 0];
             if (i < n0 && i < sub && ki0 <= k0) lb0 = li0;
             if (i < n1 && i < sub && ki1 <= k1) lb1 = li1;
             if (i < n0 && i > sub && ki0 < k0 && ub0 == 16) ub0 = li0;
             if (i < n1 && i > sub && ki1 < k1 && ub1 == 16) ub1 = li1;
-        }
+        });
         // child 1's layer, bounds and validity of every index, for the pairs of this lane
         const uint32_t pack1 = (uint32_t)l1 | (uint32_t)(lb1 + 1) << 4 | (uint32_t)(ub1 + 1) << 9 | (v1 ? 1u << 14 : 0u);
         // each lane's own contributions; child 1's reach the pairs by broadcast
         ChildVZ z0{0, 0}, z1o{0, 0};
         if (v0) z0 = child_vz_j(tb, st, wd, c0, l, l0, sub);
         if (v1) z1o = child_vz_j(tb, st, wd, c1, l, l1, sub);
-#pragma unroll
-        for (int i = 0; i < kGroup; ++i) {
-            const uint32_t p = __shfl(pack1, i, kGroup);
-            const ChildVZ z1{__shfl(z1o.V, i, kGroup), (uint32_t)__shfl((int32_t)z1o.Z, i, kGroup)};
-            if (!v0 || !((p >> 14) & 1u)) continue;
+        gx::each_lane<0>([&](auto I_) {
+            constexpr int i = decltype(I_)::value;
+            const uint32_t p = gx::bcast<i>(pack1, sub);
+            const ChildVZ z1{gx::bcast<i>(z1o.V, sub), gx::bcast<i>(z1o.Z, sub)};
+            if (!v0 || !((p >> 14) & 1u)) return;
             const int L2 = (int)(p & 15u), lb2 = (int)((p >> 4) & 31u) - 1, ub2 = (int)((p >> 9) & 31u) - 1;
             const int b = min(lo, min(l0, L2)), t = max(hi, max(l0, L2));
             if (lb0 < b && t < ub0 && lb2 < b && t < ub2) {
@@ -621,7 +668,7 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
                     sel = (uint32_t)l0 | (uint32_t)L2 << 4;
                 }
             }
-        }
+        });
     } else {
         // three children: every lane builds each child's key row from the group (one key per
         // lane), its block bounds and single-child candidates, as the serial hull order does;
@@ -641,12 +688,14 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
             int64_t ky[NAMAX];
             int ly[NAMAX];
             lyp[q] = 0;
-#pragma unroll
-            for (int i = 0; i < NAMAX; ++i) {
-                ky[i] = __shfl(kq, i, kGroup);
-                ly[i] = tb.lay[cq[q].dir][i];
-                lyp[q] |= (uint32_t)ly[i] << (4 * i);
-            }
+            gx::each_lane<0>([&](auto I_) {
+                constexpr int i = decltype(I_)::value;
+                if constexpr (i < NAMAX) {
+                    ky[i] = gx::bcast<i>(kq, sub);
+                    ly[i] = tb.lay[cq[q].dir][i];
+                    lyp[q] |= (uint32_t)ly[i] << (4 * i);
+                }
+            });
             bnd[q] = block_bounds<NAMAX>(ky, ly, nq[q]);
             cand[q] = hull_min_mask<NAMAX>(ky, ly, nq[q], lo, hi);
         }
@@ -683,18 +732,23 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
             }
         }
     }
-    // group argmin over (f', b, t)
-#pragma unroll
-    for (int m = 1; m < kGroup; m <<= 1) {
-        const int64_t ofp = __shfl_xor(fp, m, kGroup);
-        const uint32_t obt = __shfl_xor(bt, m, kGroup), oX = __shfl_xor(X, m, kGroup), osel = __shfl_xor(sel, m, kGroup);
+    // group argmin over (f', b, t, lane): a total order, so every lane ends with the same
+    // candidate whatever the exchange pattern -- on equal (f', b, t) the lowest lane, i.e. the
+    // lowest first-child layer (and each lane already kept the lowest other choices)
+    bt |= (uint32_t)sub << 8;
+    auto take = [&](int64_t ofp, uint32_t obt, uint32_t oX, uint32_t osel) {
         if (ofp < fp || (ofp == fp && obt < bt)) {
             fp = ofp;
             bt = obt;
             X = oX;
             sel = osel;
         }
-    }
+    };
+    constexpr int kX1 = gx::quad(1, 0, 3, 2), kX2 = gx::quad(2, 3, 0, 1), kX4 = gx::kHalfMirror;
+    take(gx::mov<kX1>(fp), gx::mov<kX1>(bt), gx::mov<kX1>(X), gx::mov<kX1>(sel));
+    take(gx::mov<kX2>(fp), gx::mov<kX2>(bt), gx::mov<kX2>(X), gx::mov<kX2>(sel));
+    take(gx::mov<kX4>(fp), gx::mov<kX4>(bt), gx::mov<kX4>(X), gx::mov<kX4>(sel));
+    bt &= 0xffu;
     if (sub == 0) {
         st.F(s, j) = fp;
         st.S(s, j) = (int32_t)X;
