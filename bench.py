@@ -93,6 +93,19 @@ def main():
                          **weights)
         la.la_elmore(b, delay)
 
+    # the batched form's launch configuration, tuned once on this instance (outside the timed
+    # steps) with the first iteration's adjoint weights
+    tuning = None
+    if any(n.startswith("batched") for n in args.forms.split(",")):
+        t0 = time.time()
+        la.la_reset(b)
+        H.zero_()
+        la.la_elmore(b, delay)
+        la.la_timing_weights(b, delay, la.LA_WEIGHTS_ADJOINT, sw, pw, lam, tier)
+        tuning = la.la_tune(b, sw, pw, lam, H, net_tier=tier, num_tiers=11)
+        b.dp_ops_big_per_round = la.la_batch_info(b)["dp_ops_big_per_round"]
+        log("la_tune: %s in %.2fs" % (tuning, time.time() - t0))
+
     results = {}
     for name in args.forms.split(","):
         form = la.LA_FORM_PLAIN if name == "plain" else la.LA_FORM_BATCHED
@@ -107,14 +120,17 @@ def main():
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        g0 = la.la_batch_info(b)["graph_instantiations"]
         ev0.record()
         for _ in range(args.steps):
             step(form, mode)
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.steps
+        graphs_timed = la.la_batch_info(b)["graph_instantiations"] - g0
         tns, wns = la.la_timing_summary(b, delay)
-        results[name] = dict(ms=ms, nets_per_s=inst.num_nets * R_ROUNDS * I_ITERS / (ms * 1e-3), tns=tns, wns=wns)
+        results[name] = dict(ms=ms, nets_per_s=inst.num_nets * R_ROUNDS * I_ITERS / (ms * 1e-3), tns=tns, wns=wns,
+                             graphs_timed=graphs_timed)
         log("form %s: %.2f ms/step, %.3e nets/s, TNS %.1f ps, WNS %.2f ps" % (name, ms, results[name]["nets_per_s"],
                                                                           tns, wns))
         # one more step on the same stream with every hot launch bracketed by HIP events
@@ -175,9 +191,10 @@ def main():
                                % (args.config, inst.num_nets, inst.X, inst.Y, inst.L,
                                   "batched+adjoint" if main_form == "batched" else "plain", R_ROUNDS, I_ITERS),
                    "nets": inst.num_nets, "la_nodes": b.nodes, "rounds": R_ROUNDS, "iterations": I_ITERS,
-                   "form": main_form},
+                   "form": main_form, "tuning": tuning},
         "forms": {k: {"nets_per_s": v["nets_per_s"], "ms_per_step": v["ms"], "tns_ps": v["tns"], "wns_ps": v["wns"],
                       "roofline": roof[k], "elmore": elmore_rate(b, v["kernels"]),
+                      "graph_instantiations_in_timed_steps": v["graphs_timed"],
                       "kernel_ms_per_step": {n: round(t, 4) for n, (c, t) in v["kernels"].items()}}
                   for k, v in results.items()},
         "roofline": roof[main_form],

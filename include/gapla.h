@@ -100,6 +100,17 @@ typedef struct {
 la_status la_build_batch(const la_nets *nets, const la_grid *grid, const la_layer_rc *layer_rc,
                          const uint8_t *edge_caps, void *stream, la_batch **out);
 
+/* Launch configuration of the batched form (see la_tune). */
+typedef struct {
+    int32_t tile_nodes;   /* nodes of one workgroup's LDS tile: 192, or 128 / 256 at 5-6 routable
+                             layers per direction; nets with more nodes run in the big-net kernel */
+    int32_t claim_units;  /* work-queue claim size, sum over its nets of (nodes + 3): 96..316   */
+    int32_t workgroups;   /* persistent workgroups per launch, 0 = as many as fit the GPU        */
+    int32_t fuse_nets;    /* a batch with at least this many small nets moves its demand from
+                             its DP kernel (otherwise through a changed-segment list)            */
+    int32_t tuned;        /* output: 1 when la_tune chose the values                            */
+} la_tuning;
+
 typedef struct {
     int64_t nets, nodes, sinks, rc_edges, grid_edges;
     int32_t levels;               /* tree height + 1 over all nets                          */
@@ -113,9 +124,12 @@ typedef struct {
      * (6 per child + 10), and the compulsory bytes (node inputs, congestion gathers of 9 B per
      * GCell edge and routable layer, outputs).  Elmore: compulsory bytes of one forward and one
      * reverse sweep.  dp_ops_big_per_round: the part of dp_ops_per_round from nets of more than
-     * 192 nodes, which the batched form runs in its own kernel with the DP state in HBM. */
+     * tuning.tile_nodes nodes, which the batched form runs in its own kernel with the DP state
+     * in HBM. */
     double dp_ops_per_round, dp_bytes_per_round, elmore_fwd_bytes, elmore_bwd_bytes;
     double dp_ops_big_per_round;
+    int64_t graph_instantiations; /* round graphs the batched form has instantiated so far       */
+    la_tuning tuning;             /* the batched form's current launch configuration            */
 } la_info;
 la_status la_batch_info(const la_batch *b, la_info *out);
 
@@ -160,6 +174,24 @@ typedef struct {
  * Layers are bit-identical for both forms and any launch configuration.
  */
 la_status la_assign(la_batch *b, const la_weights *w, int32_t *history, uint8_t *out_layers);
+
+/*
+ * la_tune -- the autotuner of the batched form (Alg. 2's batch loop as one persistent launch
+ * per batch): times, on this instance, one negotiation round of the given weights, batches and
+ * history (host order, device [Y*X*L], read only) for each tile size built for the batch's
+ * routable-layer count and three claim sizes around it, then two fused-commit thresholds for
+ * the fastest, and keeps the fastest configuration for the batch's later la_assign calls.
+ * Every configuration gives the same layers, bit for bit.  The demand map, previous layers,
+ * via spans and round flag are restored afterwards, so la_tune changes no result.  The choice
+ * is cached per instance shape (nets, nodes, grid, layers, levels, wire length) in the process:
+ * a later batch of the same shape takes it without timing.  Synchronises.  Allocates
+ * temporaries for the saved state.  `out` (HOST, may be NULL) receives the choice.
+ */
+la_status la_tune(la_batch *b, const la_weights *w, const int32_t *history, la_tuning *out);
+/* Sets the batched form's configuration explicitly (tuned = 0); LA_ERR_INVALID_ARG for a tile
+ * size not built for this batch's layer count or values out of range. */
+la_status la_set_tuning(la_batch *b, const la_tuning *t);
+la_status la_get_tuning(const la_batch *b, la_tuning *out);
 
 /* Via span (lowest, highest layer) at every node of the last assignment: device [nodes][2]. */
 la_status la_vias(la_batch *b, uint8_t *out_lo_hi);

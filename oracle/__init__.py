@@ -87,6 +87,8 @@ def _load():
         lib.oracle_edge_weights.argtypes = [V, ctypes.POINTER(_OParams), V, V, V]
         lib.oracle_adjoint_weights.argtypes = [V] * 7
         lib.oracle_set_num_threads.argtypes = [I32]
+        lib.oracle_get_batches.argtypes = [V, I32, I32, V, I32, V]
+        lib.oracle_get_batches.restype = I64
         lib.oracle_quality.argtypes = [V, I32, I32, I32] + [V] * 7 + [ctypes.POINTER(ctypes.c_double)] + \
             [ctypes.POINTER(I64)] * 4
         lib.oracle_quality.restype = None
@@ -257,6 +259,17 @@ def quality(tree: Tree, layers, vlo, vhi, D, ofw=None) -> dict:
                        ctypes.byref(o2), ctypes.byref(n2), ctypes.byref(nv), ctypes.byref(wc))
     return {"tof": tof.value, "overflow_sum": o2.value, "overflow_edges": n2.value, "vias": nv.value,
             "wire_cap_af": wc.value}
+
+
+def get_batches(tree: Tree, X: int, Y: int, subset, nsub: int):
+    """Classical batching (Alg. 1, GetBatch): per subset, in net order, a net joins the lowest
+    batch whose nets' boxes share no GCell with its own.  Returns (batch per net, count)."""
+    sub = np.ascontiguousarray(subset, np.int32)
+    out = np.empty(max(tree.nets, 1), np.int32)
+    n = int(_load().oracle_get_batches(tree.handle, int(X), int(Y), _p(sub), int(nsub), _p(out)))
+    if n < 0:
+        raise MemoryError("oracle_get_batches")
+    return out[:tree.nets], n
 
 
 def num_threads() -> int:

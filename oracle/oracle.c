@@ -857,6 +857,64 @@ void oracle_adjoint_weights(const otree *T, const double *G, const double *Sig, 
     }
 }
 
+/* Classical batching (Alg. 1, GetBatch: the batching of the routers the paper cites for it).
+ * A net's box is the GCell rectangle its nodes span.  Within each subset, in increasing net
+ * order, a net joins the lowest-numbered batch in which no net's box shares a GCell with its
+ * own (then no two nets of a batch share a GCell edge).  Subsets are batched one after another
+ * and never share a batch: the batches of subset s follow those of subsets 0..s-1.  A net with
+ * subset < 0 (or >= nsub) gets batch -1.  One X x Y occupancy grid per open batch.  Returns the
+ * number of batches, or -1 when memory runs out. */
+int64_t oracle_get_batches(const otree *T, int32_t X, int32_t Y, const int32_t *subset, int32_t nsub, int32_t *batch)
+{
+    const int64_t N = T->nets;
+    int32_t *box = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)(N > 0 ? N : 1));
+    if (!box) return -1;
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t x0 = INT32_MAX, x1 = -1, y0 = INT32_MAX, y1 = -1;
+        for (int64_t v = T->net_ptr[i]; v < T->net_ptr[i + 1]; ++v) {
+            if (T->x[v] < x0) x0 = T->x[v];
+            if (T->x[v] > x1) x1 = T->x[v];
+            if (T->y[v] < y0) y0 = T->y[v];
+            if (T->y[v] > y1) y1 = T->y[v];
+        }
+        box[4 * i] = x0; box[4 * i + 1] = x1; box[4 * i + 2] = y0; box[4 * i + 3] = y1;
+        batch[i] = -1;
+    }
+    int64_t base = 0, ok = 1;
+    for (int32_t s = 0; s < nsub && ok; ++s) {
+        uint8_t **grid = NULL;   /* occupancy of each open batch of this subset */
+        int64_t nb = 0;
+        for (int64_t i = 0; i < N && ok; ++i) {
+            if (subset[i] != s) continue;
+            const int32_t *b = &box[4 * i];
+            for (int64_t k = 0;; ++k) {
+                if (k == nb) {
+                    uint8_t **g2 = (uint8_t **)realloc(grid, sizeof(uint8_t *) * (size_t)(nb + 1));
+                    if (!g2) { ok = 0; break; }
+                    grid = g2;
+                    grid[nb] = (uint8_t *)calloc((size_t)X * Y, 1);
+                    if (!grid[nb]) { ok = 0; break; }
+                    ++nb;
+                }
+                int free_here = 1;
+                for (int32_t y = b[2]; y <= b[3] && free_here; ++y)
+                    for (int32_t x = b[0]; x <= b[1]; ++x)
+                        if (grid[k][(int64_t)y * X + x]) { free_here = 0; break; }
+                if (!free_here) continue;
+                for (int32_t y = b[2]; y <= b[3]; ++y)
+                    for (int32_t x = b[0]; x <= b[1]; ++x) grid[k][(int64_t)y * X + x] = 1;
+                batch[i] = (int32_t)(base + k);
+                break;
+            }
+        }
+        for (int64_t k = 0; k < nb; ++k) free(grid[k]);
+        free(grid);
+        base += nb;
+    }
+    free(box);
+    return ok ? base : -1;
+}
+
 /* Threads the OpenMP loops above use (for reporting timings), and a way to change it (the
  * results do not depend on it: per-net work is independent and commits are integer). */
 int oracle_num_threads(void) { return omp_get_max_threads(); }

@@ -27,6 +27,7 @@ EXPORTS = ["la_build_batch", "la_batch_info", "la_assign", "la_vias", "la_demand
            "la_quality_report",
            "la_timing_weights",
            "la_default_cong_lut", "la_save_state", "la_load_state", "la_sync", "la_profile_begin", "la_profile_end",
+           "la_tune", "la_set_tuning", "la_get_tuning",
            "la_free_batch", "la_status_str", "la_last_error"]
 
 V, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -46,12 +47,20 @@ class la_layer_rc(ctypes.Structure):
     _fields_ = [("r_mohm", V), ("c_af", V), ("via_r_mohm", V)]
 
 
+class la_tuning(ctypes.Structure):
+    _fields_ = [("tile_nodes", I32), ("claim_units", I32), ("workgroups", I32), ("fuse_nets", I32), ("tuned", I32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class la_info(ctypes.Structure):
     _fields_ = [("nets", I64), ("nodes", I64), ("sinks", I64), ("rc_edges", I64), ("grid_edges", I64),
                 ("levels", I32), ("max_net_nodes", I32), ("gcell_edges", I64), ("node_parent", V),
                 ("node_net", V), ("sink_node", V), ("dp_ops_per_round", ctypes.c_double),
                 ("dp_bytes_per_round", ctypes.c_double), ("elmore_fwd_bytes", ctypes.c_double),
-                ("elmore_bwd_bytes", ctypes.c_double), ("dp_ops_big_per_round", ctypes.c_double)]
+                ("elmore_bwd_bytes", ctypes.c_double), ("dp_ops_big_per_round", ctypes.c_double),
+                ("graph_instantiations", I64), ("tuning", la_tuning)]
 
 
 class la_kernel_stat(ctypes.Structure):
@@ -115,6 +124,9 @@ def _load():
         lib.la_default_cong_lut.argtypes = [I32, V, V]
         lib.la_save_state.argtypes = [V, V, ctypes.POINTER(ctypes.c_size_t)]
         lib.la_load_state.argtypes = [V, V, ctypes.c_size_t]
+        lib.la_tune.argtypes = [V, ctypes.POINTER(la_weights), V, ctypes.POINTER(la_tuning)]
+        lib.la_set_tuning.argtypes = [V, ctypes.POINTER(la_tuning)]
+        lib.la_get_tuning.argtypes = [V, ctypes.POINTER(la_tuning)]
         lib.la_sync.argtypes = [V]
         lib.la_profile_begin.argtypes = [V]
         lib.la_profile_end.argtypes = [V, ctypes.POINTER(la_kernel_stat), I32, ctypes.POINTER(I32)]
@@ -234,6 +246,36 @@ def la_assign(b: Batch, seg_w_q10, pin_w_q10, lambda_mohm, history, out_layers, 
     w = la_weights(w_cong, w_cap, w_d, w_via, _dev(seg_w_q10), _dev(pin_w_q10), _dev(lambda_mohm), _dev(net_tier),
                    _dev(cong_lut), rounds, hist_inc, form, num_tiers)
     _chk(_load().la_assign(_on(b), ctypes.byref(w), _dev(history), _dev(out_layers)), "la_assign")
+
+
+def la_tune(b: Batch, seg_w_q10, pin_w_q10, lambda_mohm, history, net_tier=None, num_tiers=1, w_cong=W_CONG,
+            w_cap=W_CAP, w_d=W_D, w_via=W_VIA, hist_inc=HIST_INC, cong_lut=None) -> dict:
+    """Autotune the batched form on this instance (one round per candidate, state restored)."""
+    w = la_weights(w_cong, w_cap, w_d, w_via, _dev(seg_w_q10), _dev(pin_w_q10), _dev(lambda_mohm), _dev(net_tier),
+                   _dev(cong_lut), 1, hist_inc, LA_FORM_BATCHED, num_tiers)
+    t = la_tuning()
+    _chk(_load().la_tune(_on(b), ctypes.byref(w), _dev(history), ctypes.byref(t)), "la_tune")
+    return t.as_dict()
+
+
+def la_set_tuning(b: Batch, tile_nodes=192, claim_units=220, workgroups=0, fuse_nets=16384):
+    t = la_tuning(tile_nodes, claim_units, workgroups, fuse_nets, 0)
+    _chk(_load().la_set_tuning(b.h, ctypes.byref(t)), "la_set_tuning")
+
+
+def la_get_tuning(b: Batch) -> dict:
+    t = la_tuning()
+    _chk(_load().la_get_tuning(b.h, ctypes.byref(t)), "la_get_tuning")
+    return t.as_dict()
+
+
+def la_batch_info(b: Batch) -> dict:
+    """The batch's sizes, work figures, graph count and launch configuration."""
+    info = la_info()
+    _chk(_load().la_batch_info(b.h, ctypes.byref(info)), "la_batch_info")
+    out = {k: getattr(info, k) for k, _ in la_info._fields_ if k not in ("node_parent", "node_net", "sink_node", "tuning")}
+    out["tuning"] = info.tuning.as_dict()
+    return out
 
 
 def la_vias(b: Batch, out_lo_hi):

@@ -24,7 +24,6 @@ la_status hip_fail(hipError_t e, const char *what)
 
 la_status build_batch(const la_nets *, const la_grid *, const la_layer_rc *, const uint8_t *, void *, la_batch **);
 la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers);
-la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers);
 la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t *seg_w, uint16_t *pin_w,
                          int32_t *lam, uint8_t *tier);
 la_status timing_summary(la_batch *b, const float *delay, double *tns, double *wns);
@@ -56,6 +55,15 @@ KernelTimer::~KernelTimer()
 {
     if (rec_ == SIZE_MAX) return;
     (void)hipEventRecord(b_->prof_ev[2 * rec_ + 1], s_);
+}
+
+static void fill_tuning(const Tuning &t, la_tuning *o)
+{
+    o->tile_nodes = t.tile_nodes;
+    o->claim_units = t.claim_units;
+    o->workgroups = t.workgroups;
+    o->fuse_nets = t.fuse_nets;
+    o->tuned = t.tuned;
 }
 
 static la_status set_device(const la_batch *b)
@@ -129,26 +137,74 @@ la_status la_batch_info(const la_batch *b, la_info *o)
     o->dp_bytes_per_round = b->dp_bytes;
     o->elmore_fwd_bytes = b->el_fwd_bytes;
     o->elmore_bwd_bytes = b->el_bwd_bytes;
-    o->dp_ops_big_per_round = b->dp_ops_big;
+    int ci = 0;
+    while (ci < 2 && kTileCaps[ci] != b->tune.tile_nodes) ++ci;
+    o->dp_ops_big_per_round = b->dp_ops_above[ci];
+    o->graph_instantiations = b->graph_instantiations;
+    fill_tuning(b->tune, &o->tuning);
+    return LA_OK;
+}
+
+static la_status check_weights(const la_batch *b, const la_weights *w, const int32_t *history, const char *who)
+{
+    const std::string n(who);
+    if (!b || !w || !history) return set_error(LA_ERR_INVALID_ARG, n + ": NULL batch, weights or history");
+    if (!w->seg_w_q10 || !w->lambda_mohm || (b->sinks > 0 && !w->pin_w_q10))
+        return set_error(LA_ERR_INVALID_ARG, n + ": weight arrays must be given");
+    if (w->w_cong < 0 || w->w_cap < 0 || w->w_d < 0 || w->w_via < 0 || w->rounds < 1 || w->hist_inc < 0)
+        return set_error(LA_ERR_INVALID_ARG, n + ": weights must be >= 0 and rounds >= 1");
+    if (w->form != LA_FORM_PLAIN && w->form != LA_FORM_BATCHED)
+        return set_error(LA_ERR_INVALID_ARG, n + ": unknown form");
+    if (w->net_tier && (w->num_tiers < 1 || w->num_tiers > 256))
+        return set_error(LA_ERR_INVALID_ARG, n + ": num_tiers must be in 1..256");
+    const double bound = (double)w->w_cong * b->bnd_cong + (double)w->w_cap * b->bnd_cap +
+                         (double)w->w_via * b->bnd_via + (double)w->w_d * b->bnd_d;
+    if (!(bound < 4.0e18) || w->w_d >= (int64_t(1) << 20))
+        return set_error(LA_ERR_RANGE, n + ": weights could overflow a net's int64 cost");
+    return LA_OK;
+}
+
+la_status la_tune(la_batch *b, const la_weights *w, const int32_t *history, la_tuning *out)
+{
+    la_status s = check_weights(b, w, history, "la_tune");
+    if (s != LA_OK) return s;
+    s = set_device(b);
+    if (s != LA_OK) return s;
+    if (b->nodes > 0) {
+        s = tune_batched(b, w, history, w->cong_lut ? w->cong_lut : b->lut, true);
+        if (s != LA_OK) return s;
+    }
+    if (out) fill_tuning(b->tune, out);
+    return LA_OK;
+}
+
+la_status la_set_tuning(la_batch *b, const la_tuning *t)
+{
+    if (!b || !t) return set_error(LA_ERR_INVALID_ARG, "la_set_tuning: NULL argument");
+    if (!tile_size_supported(b->NAmax, t->tile_nodes))
+        return set_error(LA_ERR_INVALID_ARG, "la_set_tuning: tile size not built for this layer count");
+    if (t->claim_units < kClaimUnitsMin || t->claim_units > kClaimUnitsMax || t->workgroups < 0 || t->fuse_nets < 1)
+        return set_error(LA_ERR_INVALID_ARG, "la_set_tuning: claim units, workgroups or fuse threshold out of range");
+    b->tune.tile_nodes = t->tile_nodes;
+    b->tune.claim_units = t->claim_units;
+    b->tune.workgroups = t->workgroups;
+    b->tune.fuse_nets = t->fuse_nets;
+    b->tune.tuned = 0;
+    return LA_OK;
+}
+
+la_status la_get_tuning(const la_batch *b, la_tuning *out)
+{
+    if (!b || !out) return set_error(LA_ERR_INVALID_ARG, "la_get_tuning: NULL argument");
+    fill_tuning(b->tune, out);
     return LA_OK;
 }
 
 la_status la_assign(la_batch *b, const la_weights *w, int32_t *history, uint8_t *out_layers)
 {
-    if (!b || !w || !history) return set_error(LA_ERR_INVALID_ARG, "la_assign: NULL batch, weights or history");
-    if (!w->seg_w_q10 || !w->lambda_mohm || (b->sinks > 0 && !w->pin_w_q10))
-        return set_error(LA_ERR_INVALID_ARG, "la_assign: weight arrays must be given");
-    if (w->w_cong < 0 || w->w_cap < 0 || w->w_d < 0 || w->w_via < 0 || w->rounds < 1 || w->hist_inc < 0)
-        return set_error(LA_ERR_INVALID_ARG, "la_assign: weights must be >= 0 and rounds >= 1");
-    if (w->form != LA_FORM_PLAIN && w->form != LA_FORM_BATCHED)
-        return set_error(LA_ERR_INVALID_ARG, "la_assign: unknown form");
-    if (w->net_tier && (w->num_tiers < 1 || w->num_tiers > 256))
-        return set_error(LA_ERR_INVALID_ARG, "la_assign: num_tiers must be in 1..256");
-    const double bound = (double)w->w_cong * b->bnd_cong + (double)w->w_cap * b->bnd_cap +
-                         (double)w->w_via * b->bnd_via + (double)w->w_d * b->bnd_d;
-    if (!(bound < 4.0e18) || w->w_d >= (int64_t(1) << 20))
-        return set_error(LA_ERR_RANGE, "la_assign: weights could overflow a net's int64 cost");
-    la_status s = set_device(b);
+    la_status s = check_weights(b, w, history, "la_assign");
+    if (s != LA_OK) return s;
+    s = set_device(b);
     if (s != LA_OK) return s;
     const int32_t *lut = w->cong_lut ? w->cong_lut : b->lut;
     if (b->nodes == 0) return LA_OK;
@@ -345,7 +401,7 @@ void la_free_batch(la_batch *b)
                     b->e_tile, b->e_big_nodes, b->e_big_ptr, b->qofw, b->qpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
 }

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "dp_device.h"
@@ -23,13 +25,18 @@ DPArgs make_dp_args(la_batch *b, const la_weights *w, const int32_t *H, const in
 la_status commit_changed(la_batch *b, int32_t *D);
 la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t inc);
 
+// tile sizes built for a routable-layer count per direction (every count takes kCap)
+bool tile_size_supported(int NA, int cap)
+{
+    return cap == kCap || (NA > 4 && NA <= 6 && (cap == 128 || cap == 256));
+}
+
 namespace {
 
 constexpr int kThreads = 256;
 constexpr int kBook = 10 * kClaimNets + 8;  // ints of per-claim bookkeeping
 constexpr int kHB = kHeightClasses;   // height classes of small nets per batch
 constexpr int kNB = kPartBuckets;     // partition buckets per batch
-constexpr int32_t kFuseNets = 16384;   // batches with this many small nets commit from their DP kernel
 constexpr int32_t kMergeNets = 64;     // batches of at most this many small nets may share a launch
 
 // DP state and per-node inputs of one LDS tile, indexed by tile-local node id.  ZW: every net
@@ -63,32 +70,32 @@ struct LdsState {
 
 // LDS layout of one tile (byte offsets), shared by the host launch and the kernel.  The
 // congestion table (L x 2 x 64 int32) follows at LUT; the launch sizes it by L.
-template <int NAMAX>
+template <int NAMAX, int CAP>
 struct Tile {
-    static constexpr int nkey = 4 * kCap + 4;                       // (height, child class) buckets
+    static constexpr int nkey = 4 * CAP + 4;                       // (height, child class) buckets
     // F holds kappa_n(l) until the DP item (n, l) reads it and overwrites it with f
-    static constexpr size_t F = 0;                                  // int64 [kCap][NAMAX]
-    static constexpr size_t REC = F + (size_t)kCap * NAMAX * 8;     // uint4 [kCap] per-node inputs
-    static constexpr size_t S = REC + (size_t)kCap * 16;            // int32 [kCap][NAMAX]
-    static constexpr size_t GID = S + (size_t)kCap * NAMAX * 4;     // int32 [kCap]
-    static constexpr size_t LEN = GID + (size_t)kCap * 4;           // int32 [kCap+1] prefix of segment lengths
-    static constexpr size_t G0 = LEN + (size_t)(kCap + 1) * 4;      // int32 [kCap] in-plane position of the first edge
-    static constexpr size_t KEYS = G0 + (size_t)kCap * 4;           // int32 [nkey] bucket starts
+    static constexpr size_t F = 0;                                  // int64 [CAP][NAMAX]
+    static constexpr size_t REC = F + (size_t)CAP * NAMAX * 8;     // uint4 [CAP] per-node inputs
+    static constexpr size_t S = REC + (size_t)CAP * 16;            // int32 [CAP][NAMAX]
+    static constexpr size_t GID = S + (size_t)CAP * NAMAX * 4;     // int32 [CAP]
+    static constexpr size_t LEN = GID + (size_t)CAP * 4;           // int32 [CAP+1] prefix of segment lengths
+    static constexpr size_t G0 = LEN + (size_t)(CAP + 1) * 4;      // int32 [CAP] in-plane position of the first edge
+    static constexpr size_t KEYS = G0 + (size_t)CAP * 4;           // int32 [nkey] bucket starts
     static constexpr size_t BOOK = KEYS + (size_t)nkey * 4;         // int32 [kBook]
-    static constexpr size_t PAR = BOOK + (size_t)kBook * 4;         // int16 [kCap]
-    static constexpr size_t CHP = PAR + (size_t)kCap * 2;           // int16 [kCap+2]
-    static constexpr size_t CHL = CHP + (size_t)(kCap + 2) * 2;     // int16 [kCap]
-    static constexpr size_t ORD = CHL + (size_t)kCap * 2;           // int16 [kCap]
-    static constexpr size_t KEY = ORD + (size_t)kCap * 2;           // int16 [kCap] bucket of each node
-    static constexpr size_t PINW = KEY + (size_t)kCap * 2;          // uint16 [kCap]
-    static constexpr size_t BT = PINW + (size_t)kCap * 2;           // uint8 [kCap][NAMAX] b << 4 | t
-    static constexpr size_t SEL = BT + (size_t)kCap * NAMAX;        // uint8 [kCap][NAMAX]
-    static constexpr size_t ENT = SEL + (size_t)kCap * NAMAX;       // uint8 [kCap] entering-layer index
-    static constexpr size_t FLD = ENT + (size_t)kCap;               // uint8 [kCap] flags | dir << 4
-    static constexpr size_t PRV = FLD + (size_t)kCap;               // uint8 [kCap] previous layer (255: none)
-    static constexpr size_t NEWL = PRV + (size_t)kCap;              // uint8 [kCap] new layer of a moved segment, else 255
-    static constexpr size_t SMAP = NEWL + (size_t)kCap;             // uint8 [kCap * NAMAX] GCell step -> segment
-    static constexpr size_t LUT = (SMAP + (size_t)kCap * NAMAX + 15) & ~(size_t)15;
+    static constexpr size_t PAR = BOOK + (size_t)kBook * 4;         // int16 [CAP]
+    static constexpr size_t CHP = PAR + (size_t)CAP * 2;           // int16 [CAP+2]
+    static constexpr size_t CHL = CHP + (size_t)(CAP + 2) * 2;     // int16 [CAP]
+    static constexpr size_t ORD = CHL + (size_t)CAP * 2;           // int16 [CAP]
+    static constexpr size_t KEY = ORD + (size_t)CAP * 2;           // int16 [CAP] bucket of each node
+    static constexpr size_t PINW = KEY + (size_t)CAP * 2;          // uint16 [CAP]
+    static constexpr size_t BT = PINW + (size_t)CAP * 2;           // uint8 [CAP][NAMAX] b << 4 | t
+    static constexpr size_t SEL = BT + (size_t)CAP * NAMAX;        // uint8 [CAP][NAMAX]
+    static constexpr size_t ENT = SEL + (size_t)CAP * NAMAX;       // uint8 [CAP] entering-layer index
+    static constexpr size_t FLD = ENT + (size_t)CAP;               // uint8 [CAP] flags | dir << 4
+    static constexpr size_t PRV = FLD + (size_t)CAP;               // uint8 [CAP] previous layer (255: none)
+    static constexpr size_t NEWL = PRV + (size_t)CAP;              // uint8 [CAP] new layer of a moved segment, else 255
+    static constexpr size_t SMAP = NEWL + (size_t)CAP;             // uint8 [CAP * NAMAX] GCell step -> segment
+    static constexpr size_t LUT = (SMAP + (size_t)CAP * NAMAX + 15) & ~(size_t)15;
     static size_t bytes(int L) { return LUT + (size_t)L * 2 * kNDelta * 4; }
 };
 
@@ -140,10 +147,10 @@ __device__ __forceinline__ void block_scan(int32_t *x, int32_t n, int32_t *tmp)
     }
 }
 
-template <int NAMAX>
-__global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPArgs a, BArgs ba)
+template <int NAMAX, int CAP>
+__global__ void __launch_bounds__(kThreads, NAMAX > 6 || CAP > 192 ? 3 : 4) k_batched_dp(DPArgs a, BArgs ba)
 {
-    using TL = Tile<NAMAX>;
+    using TL = Tile<NAMAX, CAP>;
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ LayerTab tb;
     __shared__ int32_t scan_tmp[kThreads / 64];
@@ -182,7 +189,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
     int32_t *s_lb = book + 8 + 6 * Q, *s_cb = book + 8 + 7 * Q;
     int32_t *s_zn = book + 8 + 8 * Q, *s_tz = book + 8 + 9 * Q;
     static_assert(kBook >= 8 + 10 * kClaimNets && kClaimNets <= kThreads, "bookkeeping layout");
-    static_assert(kClaimUnits / (1 + kNetUnits) + 1 <= kClaimNets, "nets per claim");
+    static_assert(kClaimUnitsMax / (1 + kNetUnits) + 1 <= kClaimNets, "nets per claim");
 
     const int L = tb.L;
     for (int i = threadIdx.x; i < L * 2 * kNDelta; i += blockDim.x) lut[i] = a.w.lut[i];
@@ -214,12 +221,12 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            // split the claimed nets (each of at most kCap nodes) into tiles of at most kCap;
+            // split the claimed nets (each of at most CAP nodes) into tiles of at most CAP;
             // a claim can be empty (a net longer than one claim's units spans several)
             int32_t ns = 0, nodes = 0, kids = 0;
             for (int32_t i = 0; i < nclaim; ++i) {
                 const int32_t n = s_nn[i];
-                if (i == 0 || nodes + n > kCap) {
+                if (i == 0 || nodes + n > CAP) {
                     if (i) {
                         s_sub1[ns - 1] = i;
                         s_tn[ns - 1] = nodes;
@@ -313,8 +320,8 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 ? 3 : 4) k_batched_dp(DPAr
             // (height, class) order; kst[q] ends as the end of bucket q = start of q+1.  The
             // step -> segment map serves the gather and the demand moves.
             const int32_t steps = lenp[nn];
-            static_assert(kCap <= 256, "the step map holds tile-local node ids in one byte");
-            const bool mapped = steps <= kCap * NAMAX;
+            static_assert(CAP <= 256, "the step map holds tile-local node ids in one byte");
+            const bool mapped = steps <= CAP * NAMAX;
             // the segment of GCell step pidx: the last u with lenp[u] <= pidx
             auto seg_of = [&](int32_t pidx) -> int32_t {
                 if (mapped) return smap[pidx];
@@ -608,7 +615,7 @@ __global__ void k_net_zero_weights(TreeDev T, const uint16_t *seg_w, const uint1
 
 constexpr int kLdsNB = 2048;   // buckets counted in LDS; more go straight to HBM counters
 
-__global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big,
+__global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, int32_t cap,
                              const uint8_t *zw, const int32_t *net_ptr, const int32_t *height, int32_t *cnt,
                              int32_t *bad)
 {
@@ -624,7 +631,7 @@ __global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, c
             atomicAdd(bad, 1);
             continue;
         }
-        const int32_t q = net_bucket(t, net_big[i] >= 0, zw[i] != 0, height[net_ptr[i]]);
+        const int32_t q = net_bucket(t, net_ptr[i + 1] - net_ptr[i] > cap, zw[i] != 0, height[net_ptr[i]]);
         atomicAdd(local ? &hist[q] : &cnt[q], 1);
     }
     __syncthreads();
@@ -645,7 +652,7 @@ __global__ void k_tier_offsets(const int32_t *cnt, int32_t nb, int32_t *off, int
     for (int32_t i = threadIdx.x; i < nclaim; i += blockDim.x) claim[i] = 0;
 }
 
-__global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets, const int32_t *net_big,
+__global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets, int32_t cap,
                                const uint8_t *zw, const int32_t *net_ptr, const int32_t *height, int32_t *cur,
                                int32_t *out)
 {
@@ -657,7 +664,8 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
              i += (int64_t)gridDim.x * blockDim.x) {
             const int t = tier ? tier[i] : 0;
             if (t >= ntier) continue;
-            out[atomicAdd(&cur[net_bucket(t, net_big[i] >= 0, zw[i] != 0, height[net_ptr[i]])], 1)] = (int32_t)i;
+            out[atomicAdd(&cur[net_bucket(t, net_ptr[i + 1] - net_ptr[i] > cap, zw[i] != 0, height[net_ptr[i]])], 1)] =
+                (int32_t)i;
         }
         return;
     }
@@ -670,7 +678,7 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
         if (i < nets) {
             const int t = tier ? tier[i] : 0;
             if (t < ntier) {
-                q = net_bucket(t, net_big[i] >= 0, zw[i] != 0, height[net_ptr[i]]);
+                q = net_bucket(t, net_ptr[i + 1] - net_ptr[i] > cap, zw[i] != 0, height[net_ptr[i]]);
                 r = atomicAdd(&hist[q], 1);
             }
         }
@@ -723,13 +731,14 @@ __global__ void k_scan_add(int32_t *x, int64_t n, const int32_t *blk)
     }
 }
 
-// batch t gets n_t = ceil(units / kClaimUnits) claims and one end slot, from cl_off[t]
-__global__ void k_claim_offsets(const int32_t *tier_off, int32_t ntier, const int32_t *pre, int32_t *cl_off)
+// batch t gets n_t = ceil(its units / units) claims and one end slot, from cl_off[t]
+__global__ void k_claim_offsets(const int32_t *tier_off, int32_t ntier, const int32_t *pre, int32_t units,
+                                int32_t *cl_off)
 {
     __shared__ int32_t tmp[1024 / 64];
     for (int t = threadIdx.x; t < ntier; t += blockDim.x) {
         const int32_t s0 = tier_off[t * kNB + 1], s1 = tier_off[(t + 1) * kNB];
-        cl_off[t + 1] = s1 > s0 ? (pre[s1] - pre[s0] + kClaimUnits - 1) / kClaimUnits + 1 : 0;
+        cl_off[t + 1] = s1 > s0 ? (pre[s1] - pre[s0] + units - 1) / units + 1 : 0;
     }
     if (threadIdx.x == 0) cl_off[0] = 0;
     __syncthreads();
@@ -737,9 +746,9 @@ __global__ void k_claim_offsets(const int32_t *tier_off, int32_t ntier, const in
 }
 
 // claim c of batch t holds the small nets whose unit prefix, counted from the batch's first
-// small net, lies in [c, c + 1) * kClaimUnits; slot n_t holds the batch's end
+// small net, lies in [c, c + 1) * units; slot n_t holds the batch's end
 __global__ void k_claim_starts(const int32_t *tier_off, int32_t ntier, int64_t nets, const int32_t *pre,
-                               const int32_t *cl_off, int32_t *cl_start)
+                               int32_t units, const int32_t *cl_off, int32_t *cl_start)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets; i += (int64_t)gridDim.x * blockDim.x) {
         int32_t lo = 0, hi = ntier;   // batch of position i: tier_off[t*kNB] <= i < tier_off[(t+1)*kNB]
@@ -752,8 +761,8 @@ __global__ void k_claim_starts(const int32_t *tier_off, int32_t ntier, int64_t n
         const int32_t s0 = tier_off[t * kNB + 1], s1 = tier_off[(t + 1) * kNB];
         if (i < s0 || i >= s1) continue;   // a big net (its own kernel)
         const int32_t base = cl_off[t], nt = cl_off[t + 1] - base - 1;
-        const int32_t c = (pre[i] - pre[s0]) / kClaimUnits;
-        const int32_t cp = i == s0 ? -1 : (pre[i - 1] - pre[s0]) / kClaimUnits;
+        const int32_t c = (pre[i] - pre[s0]) / units;
+        const int32_t cp = i == s0 ? -1 : (pre[i - 1] - pre[s0]) / units;
         for (int32_t q = cp + 1; q <= c; ++q) cl_start[base + q] = (int32_t)i;
         if (i == s1 - 1)
             for (int32_t q = c + 1; q <= nt; ++q) cl_start[base + q] = s1;
@@ -780,28 +789,48 @@ inline int grid1d(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
 }
 
-template <int NAMAX>
-la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t nbig, int32_t nsmall, hipStream_t s)
-{
-    if (nbig > 0)
-        LA_TIMED(b, "k_batched_big", s,
-                 hipLaunchKernelGGL(k_batched_big<NAMAX>, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, s, a, ba));
-    if (nsmall > 0)
-        LA_TIMED(b, "k_batched_dp", s,
-                 hipLaunchKernelGGL(k_batched_dp<NAMAX>, dim3(b->grid_batched), dim3(kThreads),
-                                    Tile<NAMAX>::bytes(b->tab.L), s, a, ba));
-    LA_HIP(hipGetLastError());
-    return LA_OK;
-}
-
-template <int NAMAX>
+// workgroups of the tile kernel that fit the GPU at once (its LDS tile and registers)
+template <int NAMAX, int CAP>
 int occupancy_grid(int L)
 {
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_dp<NAMAX>, kThreads, Tile<NAMAX>::bytes(L));
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_dp<NAMAX, CAP>, kThreads,
+                                                       Tile<NAMAX, CAP>::bytes(L));
     return std::max(1, cus) * std::max(1, per);
+}
+
+template <int NAMAX, int CAP>
+la_status launch_tiles(la_batch *b, const DPArgs &a, const BArgs &ba, hipStream_t s)
+{
+    const int full = occupancy_grid<NAMAX, CAP>(b->tab.L);
+    const int grid = b->tune.workgroups > 0 ? std::min(b->tune.workgroups, full) : full;
+    auto kern = k_batched_dp<NAMAX, CAP>;
+    const size_t lds = Tile<NAMAX, CAP>::bytes(b->tab.L);
+    LA_TIMED(b, "k_batched_dp", s, hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, a, ba));
+    return LA_OK;
+}
+
+la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t nbig, int32_t nsmall, hipStream_t s)
+{
+    const int NA = b->NAmax, cap = b->tune.tile_nodes;
+    if (nbig > 0) {
+        auto big = NA <= 4 ? k_batched_big<4> : (NA <= 6 ? k_batched_big<6> : k_batched_big<8>);
+        LA_TIMED(b, "k_batched_big", s,
+                 hipLaunchKernelGGL(big, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, s, a, ba));
+    }
+    if (nsmall > 0) {
+        la_status st = LA_OK;
+        if (NA <= 4) st = launch_tiles<4, kCap>(b, a, ba, s);
+        else if (NA <= 6)
+            st = cap == 128 ? launch_tiles<6, 128>(b, a, ba, s)
+                            : (cap == 256 ? launch_tiles<6, 256>(b, a, ba, s) : launch_tiles<6, kCap>(b, a, ba, s));
+        else st = launch_tiles<8, kCap>(b, a, ba, s);
+        if (st != LA_OK) return st;
+    }
+    LA_HIP(hipGetLastError());
+    return LA_OK;
 }
 
 // small nets of batch t in the partition counts
@@ -839,7 +868,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
                 nsmall += small_nets(cnt, q);
             }
             if (nbig + nsmall == 0) continue;
-            const bool fused = nsmall >= kFuseNets;
+            const bool fused = nsmall >= b->tune.fuse_nets;
             a.D = dcur;
             if (fused)
                 LA_TIMED(b, "k_copy_i32", s,
@@ -871,10 +900,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             ba.has_prev = has_prev ? 1 : 0;
             ba.cl = ChangeList{b->chg_node, b->chg_old, b->chg_new, b->chg_count};
             ba.Dw = fused ? dalt : nullptr;
-            const int NA = b->NAmax;
-            st = NA <= 4   ? launch_batched<4>(b, a, ba, nbig, nsmall, s)
-                 : NA <= 6 ? launch_batched<6>(b, a, ba, nbig, nsmall, s)
-                           : launch_batched<8>(b, a, ba, nbig, nsmall, s);
+            st = launch_batched(b, a, ba, nbig, nsmall, s);
             // the change list holds the big nets' moves (and, unfused, the small nets')
             if (st == LA_OK) st = commit_changed(b, fused ? dalt : dcur);
             if (fused) std::swap(dcur, dalt);
@@ -890,7 +916,8 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
 
 }  // namespace
 
-la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers)
+la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
+                         bool direct)
 {
     const int32_t ntier = w->net_tier ? w->num_tiers : 1;
     const int32_t nb = ntier * kNB;
@@ -902,11 +929,6 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
             return set_error(LA_ERR_OOM, "claim counters");
         b->claim_cap = R * ntier;
     }
-    if (!b->grid_batched) {
-        const int NA = b->NAmax;
-        const int L = b->tab.L;
-        b->grid_batched = NA <= 4 ? occupancy_grid<4>(L) : (NA <= 6 ? occupancy_grid<6>(L) : occupancy_grid<8>(L));
-    }
     // partition the nets by batch (big nets first, then nets with timing weights, then those
     // without, each by height) and check the batch indices
     LA_TIMED(b, "k_net_zero_weights", b->stream, {
@@ -917,13 +939,13 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb + 1);
     LA_TIMED(b, "k_tier_count", b->stream,
              hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
-                                b->nets, b->net_big, b->net_zw, b->net_ptr, b->height, b->tier_cnt,
+                                b->nets, b->tune.tile_nodes, b->net_zw, b->net_ptr, b->height, b->tier_cnt,
                                 b->tier_cnt + nb));
     hipLaunchKernelGGL(k_tier_offsets, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb, b->tier_off, b->tier_cur,
                        b->claim, R * ntier);
     LA_TIMED(b, "k_tier_scatter", b->stream,
              hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
-                                b->nets, b->net_big, b->net_zw, b->net_ptr, b->height, b->tier_cur,
+                                b->nets, b->tune.tile_nodes, b->net_zw, b->net_ptr, b->height, b->tier_cur,
                                 b->tier_nets));
     // work-queue claims of each batch's small nets
     {
@@ -935,9 +957,9 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, b->stream, b->cl_blk, nchunk);
         hipLaunchKernelGGL(k_scan_add, dim3(grid1d(n)), dim3(256), 0, b->stream, b->cl_pre, n, b->cl_blk);
         hipLaunchKernelGGL(k_claim_offsets, dim3(1), dim3(256), 0, b->stream, b->tier_off, ntier, b->cl_pre,
-                           b->cl_off);
+                           b->tune.claim_units, b->cl_off);
         hipLaunchKernelGGL(k_claim_starts, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, b->tier_off, ntier,
-                           b->nets, b->cl_pre, b->cl_off, b->cl_start);
+                           b->nets, b->cl_pre, b->tune.claim_units, b->cl_off, b->cl_start);
     }
     LA_HIP(hipGetLastError());
     std::vector<int32_t> cnt(nb + 1);
@@ -1003,7 +1025,7 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
 
     // the rounds, as one graph: per batch the persistent DP, then the commit; history per round.
     // While kernels are being timed the same launches go straight to the batch's stream.
-    if (b->prof_on) {
+    if (b->prof_on || direct) {
         hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->claim, R * ntier);
         la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, groups, b->stream);
         if (st != LA_OK) return st;
@@ -1012,15 +1034,19 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     }
     std::vector<int64_t> key = {R, ntier, b->has_prev, w->w_cong, w->w_cap, w->w_d, w->w_via, w->hist_inc,
                                 (int64_t)w->seg_w_q10, (int64_t)w->pin_w_q10, (int64_t)w->lambda_mohm,
-                                (int64_t)lut, (int64_t)H, (int64_t)out_layers};
+                                (int64_t)lut, (int64_t)H, (int64_t)out_layers, b->tune.tile_nodes,
+                                b->tune.claim_units, b->tune.workgroups, b->tune.fuse_nets};
     for (int32_t t = 0; t < ntier; ++t) {
         key.push_back(cnt[t * kNB]);
         key.push_back(small_nets(cnt, t) > 0);
     }
     key.insert(key.end(), groups.begin(), groups.end());
-    if (!b->gexec || key != b->gkey) {
-        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
+    // a few graphs stay instantiated (most recently used first): the calls of a schedule
+    // alternate between a handful of keys (the first call after a reset has no previous layers)
+    auto &cache = b->graphs;
+    size_t hit = 0;
+    while (hit < cache.size() && cache[hit].first != key) ++hit;
+    if (hit == cache.size()) {
         if (!b->cap_stream) LA_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         hipStream_t s = b->cap_stream;
         LA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1032,19 +1058,153 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
             return st;
         }
         if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            b->gexec = nullptr;
-            return hip_fail(e, "hipGraphInstantiate");
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        if (cache.size() >= kGraphSlots) {
+            (void)hipGraphExecDestroy(cache.back().second);
+            cache.pop_back();
         }
-        b->gkey = key;
+        cache.insert(cache.begin(), std::make_pair(key, ex));
+        b->graph_instantiations += 1;
     } else {
+        std::rotate(cache.begin(), cache.begin() + hit, cache.begin() + hit + 1);
         // replay: the work-queue counters start from zero again
         hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->claim, R * ntier);
     }
-    LA_HIP(hipGraphLaunch(b->gexec, b->stream));
+    LA_HIP(hipGraphLaunch(cache.front().second, b->stream));
     b->has_prev = true;
+    return LA_OK;
+}
+
+// ---- autotuner ------------------------------------------------------------------------
+// la_tune times the launch configurations of the batched form on the instance itself: every
+// tile size built for its routable-layer count, claim sizes around each tile size, then the
+// fused-commit threshold of the fastest.  Each candidate runs one negotiation round of the
+// caller's weights and batches from the same saved state (demand, previous layers, via spans,
+// history), directly rather than from a graph; a first untimed pass loads every kernel.  The
+// state is restored at the end, so la_tune changes nothing but the configuration, which is
+// cached per instance shape for later batches of the same shape.  Every candidate gives the
+// same layers, bit for bit (each net's result depends only on its own inputs and its batch's
+// demand snapshot).
+namespace {
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, Tuning> g_tune_cache;
+
+std::vector<int64_t> shape_key(const la_batch *b)
+{
+    return {b->device, b->nets, b->nodes, b->tab.L, b->tab.X, b->tab.Y, b->NAmax, b->levels, b->max_net_nodes,
+            b->gcell_edges};
+}
+
+struct Saved {
+    int32_t *D = nullptr, *Hi = nullptr;
+    uint8_t *cur = nullptr, *vlo = nullptr, *vhi = nullptr;
+    ~Saved()
+    {
+        for (void *p : {(void *)D, (void *)Hi, (void *)cur, (void *)vlo, (void *)vhi})
+            if (p) (void)hipFree(p);
+    }
+};
+}  // namespace
+
+la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history, const int32_t *lut, bool use_cache)
+{
+    const std::vector<int64_t> key = shape_key(b);
+    if (use_cache) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            b->tune = it->second;
+            return LA_OK;
+        }
+    }
+    const int64_t M = std::max<int64_t>(b->nodes, 1);
+    Saved sv;
+    if (hipMalloc((void **)&sv.D, b->Eg * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&sv.Hi, b->Eg * sizeof(int32_t)) != hipSuccess || hipMalloc((void **)&sv.cur, M) != hipSuccess ||
+        hipMalloc((void **)&sv.vlo, M) != hipSuccess || hipMalloc((void **)&sv.vhi, M) != hipSuccess)
+        return set_error(LA_ERR_OOM, "la_tune: saved state");
+    la_status st = grid_to_planes(b, history, b->Hi);
+    if (st != LA_OK) return st;
+    const hipStream_t s = b->stream;
+    LA_HIP(hipMemcpyAsync(sv.D, b->D, b->Eg * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    LA_HIP(hipMemcpyAsync(sv.Hi, b->Hi, b->Eg * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    LA_HIP(hipMemcpyAsync(sv.cur, b->cur_layer, M, hipMemcpyDeviceToDevice, s));
+    LA_HIP(hipMemcpyAsync(sv.vlo, b->vlo, M, hipMemcpyDeviceToDevice, s));
+    LA_HIP(hipMemcpyAsync(sv.vhi, b->vhi, M, hipMemcpyDeviceToDevice, s));
+    const bool prev0 = b->has_prev;
+    auto restore = [&]() -> la_status {
+        LA_HIP(hipMemcpyAsync(b->D, sv.D, b->Eg * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        LA_HIP(hipMemcpyAsync(b->Hi, sv.Hi, b->Eg * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        LA_HIP(hipMemcpyAsync(b->cur_layer, sv.cur, M, hipMemcpyDeviceToDevice, s));
+        LA_HIP(hipMemcpyAsync(b->vlo, sv.vlo, M, hipMemcpyDeviceToDevice, s));
+        LA_HIP(hipMemcpyAsync(b->vhi, sv.vhi, M, hipMemcpyDeviceToDevice, s));
+        b->has_prev = prev0;
+        return LA_OK;
+    };
+    la_weights w1 = *w;
+    w1.rounds = 1;
+    const Tuning keep = b->tune;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LA_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(LA_ERR_HIP, "la_tune: event");
+    }
+    // one round of candidate t from the saved state: its time (ms), or < 0 on failure
+    auto run = [&](const Tuning &t, bool timed) -> double {
+        if (restore() != LA_OK) return -1.0;
+        b->tune = t;
+        if (timed && hipEventRecord(e0, s) != hipSuccess) return -1.0;
+        if (assign_batched(b, &w1, b->Hi, lut, nullptr, true) != LA_OK) return -1.0;
+        if (timed && hipEventRecord(e1, s) != hipSuccess) return -1.0;
+        if (hipStreamSynchronize(s) != hipSuccess) return -1.0;
+        float ms = 0.f;
+        if (timed && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+        return ms;
+    };
+    std::vector<Tuning> cand;
+    for (int cap : kTileCaps) {
+        if (!tile_size_supported(b->NAmax, cap)) continue;
+        for (double f : {0.85, 1.15, 1.5}) {
+            Tuning t = keep;
+            t.tile_nodes = cap;
+            t.claim_units = std::max(kClaimUnitsMin, std::min(kClaimUnitsMax, (int)(f * cap)));
+            t.tuned = 0;
+            cand.push_back(t);
+        }
+    }
+    Tuning best = cand.front();
+    double best_ms = -1.0;
+    for (const Tuning &t : cand) (void)run(t, false);   // loads every kernel variant
+    auto consider = [&](const Tuning &t) {
+        const double ms = run(t, true);
+        if (ms >= 0.0 && (best_ms < 0.0 || ms < best_ms)) {
+            best_ms = ms;
+            best = t;
+        }
+    };
+    for (const Tuning &t : cand) consider(t);
+    const Tuning base = best;
+    for (int32_t fuse : {4096, 65536}) {
+        Tuning t = base;
+        t.fuse_nets = fuse;
+        consider(t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st = restore();
+    if (st == LA_OK) LA_HIP(hipStreamSynchronize(s));
+    if (st != LA_OK || best_ms < 0.0) {
+        b->tune = keep;
+        return st != LA_OK ? st : set_error(LA_ERR_HIP, "la_tune: no candidate ran");
+    }
+    best.tuned = 1;
+    b->tune = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
     return LA_OK;
 }
 

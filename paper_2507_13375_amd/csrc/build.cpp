@@ -392,7 +392,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     std::vector<int32_t> net_big(std::max<int32_t>(N, 1), -1), bn_order, bn_lvl, bn_lvl_off, bn_nlev;
     for (int32_t i = 0; i < N; ++i) {
         const int32_t b0 = net_ptr[i], n = net_ptr[i + 1] - b0;
-        if (n <= kCap) continue;
+        if (n <= kBigMin) continue;
         net_big[i] = (int32_t)bn_nlev.size();
         int32_t hmax = 0;
         for (int32_t v = b0; v < b0 + n; ++v) hmax = std::max(hmax, height[v]);
@@ -413,7 +413,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     // add and compare/select, 6 VALU ops) and prices the stack (10 ops).  Bytes: node
     // inputs, congestion gathers (demand 4 B, capacity 1 B, history 4 B per GCell edge and
     // routable layer, Eq. 3) and the chosen layer and via span.
-    double dp_ops = 0, dp_bytes = 0, dp_ops_big = 0;
+    double dp_ops = 0, dp_bytes = 0, dp_ops_above[3] = {0, 0, 0};
     for (int32_t i = 0; i < N; ++i) {
         double ops = 0;
         for (int64_t v = net_ptr[i]; v < net_ptr[i + 1]; ++v) {
@@ -434,7 +434,8 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
             dp_bytes += 25.0 + 3.0 + ((flags[v] & kSink) ? 6.0 : 0.0);
         }
         dp_ops += ops;
-        if (net_ptr[i + 1] - net_ptr[i] > kCap) dp_ops_big += ops;
+        for (int c = 0; c < 3; ++c)
+            if (net_ptr[i + 1] - net_ptr[i] > kTileCaps[c]) dp_ops_above[c] += ops;
     }
     dp_bytes += 9.0 * (double)N;
 
@@ -442,7 +443,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     la_batch *b = new la_batch();
     b->dp_ops = dp_ops;
     b->dp_bytes = dp_bytes;
-    b->dp_ops_big = dp_ops_big;
+    for (int c = 0; c < 3; ++c) b->dp_ops_above[c] = dp_ops_above[c];
     b->el_fwd_bytes = 28.0 * (double)(M + S);
     b->el_bwd_bytes = 40.0 * (double)(M + S);
     b->stream = (hipStream_t)stream;
@@ -558,7 +559,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     // claims: every claim but the last of a batch covers kClaimUnits units
     chk(alloc(&b->cl_pre, (size_t)N + 1));
     chk(alloc(&b->cl_blk, (size_t)N / 1024 + 2));
-    b->cl_start_cap = (M + (int64_t)kNetUnits * N) / kClaimUnits + 2 * 256 + 2;
+    b->cl_start_cap = (M + (int64_t)kNetUnits * N) / kClaimUnitsMin + 2 * 256 + 2;
     chk(alloc(&b->cl_start, (size_t)b->cl_start_cap));
     chk(alloc(&b->cl_off, 256 + 2));
     chk(upload(&b->caps, caps));

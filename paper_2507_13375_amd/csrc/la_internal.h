@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/gapla.h"
@@ -16,10 +17,24 @@ constexpr int kQPartials = 2048 * 5;   // quality report: workgroups x partial s
 constexpr int kQSpan = 64;             // quality report: e^{s x} tabulated for integer x in [-kQSpan, kQSpan]
 constexpr int kETile = 1024;        // nodes of one Elmore tile (whole nets, swept in one workgroup)
 constexpr int kEMaxH = 128;         // tree heights an Elmore tile handles
-constexpr int kCap = 192;          // nodes of one batched-form workgroup's LDS tile
-constexpr int kClaimUnits = 220;   // work-queue claim size: sum over its nets of (nodes + kNetUnits)
+constexpr int kCap = 192;          // default nodes of one batched-form workgroup's LDS tile
+constexpr int kTileCaps[3] = {128, 192, 256};   // tile sizes the batched form is built for
+constexpr int kBigMin = 128;       // smallest tile: nets above it get their own level lists
+constexpr int kClaimUnits = 220;   // default work-queue claim size: sum over its nets of (nodes + kNetUnits)
 constexpr int kNetUnits = 3;
-constexpr int kClaimNets = 64;     // bound on the nets of one claim (kClaimUnits / (1 + kNetUnits) + 1)
+constexpr int kClaimUnitsMin = 96, kClaimUnitsMax = 316;   // claim sizes the autotuner may pick
+constexpr int kClaimNets = 80;     // bound on the nets of one claim (kClaimUnitsMax / (1 + kNetUnits) + 1)
+constexpr int32_t kFuseDefault = 16384;   // batches with this many small nets commit from their DP kernel
+constexpr size_t kGraphSlots = 4;         // round graphs kept instantiated per batch
+
+// Launch configuration of the batched form (la_tune picks it per instance shape).
+struct Tuning {
+    int32_t tile_nodes = kCap;        // LDS tile capacity; nets above it run in the big-net kernel
+    int32_t claim_units = kClaimUnits;
+    int32_t workgroups = 0;           // persistent workgroups per launch; 0 = as many as fit the GPU
+    int32_t fuse_nets = kFuseDefault;
+    int32_t tuned = 0;                // 1 once la_tune chose it
+};
 constexpr int kMaxA = 8;           // routable layers per direction
 constexpr int kHeightClasses = 32;   // batched work queue: height classes of small nets per batch
 // partition buckets per batch: its big nets, then its small nets with a non-zero timing weight,
@@ -176,10 +191,10 @@ struct la_batch {
     // claim offsets
     int32_t *cl_pre = nullptr, *cl_blk = nullptr, *cl_start = nullptr, *cl_off = nullptr;
     int64_t cl_start_cap = 0;
-    int32_t grid_batched = 0;       // persistent workgroups per batched launch
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    std::vector<int64_t> gkey;
+    // instantiated round graphs of the batched form by call key, most recently used first
+    std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
+    int64_t graph_instantiations = 0;
 
     // RC and Elmore state
     float *R = nullptr, *C = nullptr;   // batch RC views [nodes+sinks]
@@ -196,8 +211,11 @@ struct la_batch {
     double *qpart = nullptr;            // [kQPartials] its workgroup partial sums
     int32_t red_blocks = 0;
 
-    // algorithmic work per DP round and per Elmore sweep (computed at build)
-    double dp_ops = 0, dp_bytes = 0, el_fwd_bytes = 0, el_bwd_bytes = 0, dp_ops_big = 0;
+    // algorithmic work per DP round and per Elmore sweep (computed at build); the part of the
+    // DP work in nets above each tile size of kTileCaps
+    double dp_ops = 0, dp_bytes = 0, el_fwd_bytes = 0, el_bwd_bytes = 0;
+    double dp_ops_above[3] = {0, 0, 0};
+    gapla::Tuning tune;
 
     // kernel timing (la_profile_begin/end): an event pair per bracketed launch
     bool prof_on = false;
@@ -251,6 +269,11 @@ la_status grid_to_planes(la_batch *b, const int32_t *api, int32_t *planes);
 la_status planes_to_grid(la_batch *b, const int32_t *planes, int32_t *api);
 la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t hist_inc);
 la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut);
+la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
+                         bool direct = false);
+bool tile_size_supported(int NA, int cap);
+// picks b->tune on the instance (or from the cache of instance shapes); state is unchanged
+la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history, const int32_t *lut, bool use_cache);
 // the static scratch of the allocation-free entry point: its address on `device` (once per device)
 la_status scratch_setup(int device);
 la_status timing_summary_noalloc(la_batch *b, const float *delay, double *tns, double *wns);
