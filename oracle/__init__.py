@@ -195,7 +195,7 @@ def assign(tree: Tree, P: Params, state: State, net_tier=None, rounds: int = 1, 
     vhi = np.zeros(tree.nodes, np.uint8)
     froot = np.zeros(tree.nets, np.int64)
     hp = ctypes.c_int32(state.has_prev)
-    tier = None if net_tier is None else np.ascontiguousarray(net_tier, np.uint8)
+    tier = None if net_tier is None else np.ascontiguousarray(net_tier, np.int32)
     rc = lib.oracle_assign(tree.handle, ctypes.byref(P.s), _p(caps), _p(state.D), _p(state.H), _p(state.prev),
                            ctypes.byref(hp), _p(tier), rounds, hist_inc, _p(lay), _p(vlo), _p(vhi), _p(froot))
     if rc != OK:

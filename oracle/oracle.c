@@ -494,28 +494,44 @@ static void add_seg(const oparams *P, const otree *T, int64_t v, int l, int32_t 
  * the DP excludes each segment's own previous demand and commits move demand.
  */
 int oracle_assign(const otree *T, const oparams *P, const uint8_t *cap, int32_t *D, int32_t *H, uint8_t *prev,
-                  int32_t *has_prev, const uint8_t *net_tier, int32_t rounds, int32_t hist_inc, uint8_t *out_layer,
+                  int32_t *has_prev, const int32_t *net_tier, int32_t rounds, int32_t hist_inc, uint8_t *out_layer,
                   uint8_t *out_vlo, uint8_t *out_vhi, int64_t *out_froot)
 {
+    /* the nets of each batch, in net order (batches are 0..ntier-1) */
     int32_t ntier = 1;
     if (net_tier)
-        for (int64_t i = 0; i < T->nets; ++i) if (net_tier[i] + 1 > ntier) ntier = net_tier[i] + 1;
+        for (int64_t i = 0; i < T->nets; ++i) {
+            if (net_tier[i] < 0) return O_ERR_INVALID_ARG;
+            if (net_tier[i] + 1 > ntier) ntier = net_tier[i] + 1;
+        }
+    int64_t *bstart = (int64_t *)calloc((size_t)ntier + 1, sizeof(int64_t));
+    int64_t *bnets = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T->nets > 0 ? T->nets : 1));
+    if (!bstart || !bnets) { free(bstart); free(bnets); return O_ERR_OOM; }
+    for (int64_t i = 0; i < T->nets; ++i) bstart[(net_tier ? net_tier[i] : 0) + 1]++;
+    for (int32_t k = 0; k < ntier; ++k) bstart[k + 1] += bstart[k];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ntier);
+        if (!fill) { free(bstart); free(bnets); return O_ERR_OOM; }
+        for (int32_t k = 0; k < ntier; ++k) fill[k] = bstart[k];
+        for (int64_t i = 0; i < T->nets; ++i) bnets[fill[net_tier ? net_tier[i] : 0]++] = i;
+        free(fill);
+    }
     int64_t E = (int64_t)P->X * P->Y * P->L;
     for (int32_t r = 0; r < rounds; ++r) {
         for (int32_t k = 0; k < ntier; ++k) {
             int err = O_OK;
             #pragma omp parallel for schedule(dynamic, 64)
-            for (int64_t i = 0; i < T->nets; ++i) {
-                if ((net_tier ? net_tier[i] : 0) != k) continue;
+            for (int64_t q = bstart[k]; q < bstart[k + 1]; ++q) {
+                const int64_t i = bnets[q];
                 int e = dp_net(T, P, i, D, cap, H, *has_prev ? prev : NULL, out_layer, out_vlo, out_vhi, &out_froot[i]);
                 if (e != O_OK) {
                     #pragma omp critical
                     err = e;
                 }
             }
-            if (err != O_OK) return err;
-            for (int64_t i = 0; i < T->nets; ++i) {
-                if ((net_tier ? net_tier[i] : 0) != k) continue;
+            if (err != O_OK) { free(bstart); free(bnets); return err; }
+            for (int64_t q = bstart[k]; q < bstart[k + 1]; ++q) {
+                const int64_t i = bnets[q];
                 for (int64_t v = T->net_ptr[i]; v < T->net_ptr[i + 1]; ++v) {
                     if (T->parent[v] < 0) continue;
                     if (*has_prev) {
@@ -536,6 +552,8 @@ int oracle_assign(const otree *T, const oparams *P, const uint8_t *cap, int32_t 
             }
         }
     }
+    free(bstart);
+    free(bnets);
     return O_OK;
 }
 

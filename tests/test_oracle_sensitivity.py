@@ -15,7 +15,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_FILES = ["tests/test_oracle_dp.py", "tests/test_oracle_weights.py", "tests/test_oracle_elmore.py",
-             "tests/test_oracle_quality.py", "tests/test_oracle_tree.py"]
+             "tests/test_oracle_quality.py", "tests/test_oracle_tree.py", "tests/test_oracle_batches.py"]
 
 TIE = "if (bl < 0 || key < bkey) { bl = lc; bkey = key; }"
 
@@ -56,6 +56,12 @@ MUTANTS = {
     "adjoint_pinw_scale": ("double q = nearbyint(-1024.0 * gbar[k]);", "double q = nearbyint(-1000.0 * gbar[k]);",
                            None),
     "adjoint_lambda_scale": ("nearbyint(-Sig[p] * 1e6)", "nearbyint(-Sig[p] * 1e3)", None),
+    # classical batching: boxes that touch at one GCell, a box one GCell short, subsets sharing
+    # batches
+    "batch_touching_allowed": ("for (int32_t y = b[2]; y <= b[3] && free_here; ++y)",
+                               "for (int32_t y = b[2] + 1; y <= b[3] && free_here; ++y)", None),
+    "batch_box_short": ("if (T->x[v] > x1) x1 = T->x[v];", "if (T->x[v] > x1) x1 = T->x[v] - 1;", None),
+    "batch_subsets_shared": ("base += nb;", "base += 0;", None),
 }
 
 
