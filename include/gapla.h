@@ -144,7 +144,10 @@ typedef struct {
     int32_t rounds;               /* negotiation rounds, >= 1                                */
     int32_t hist_inc;             /* history increment per unit of overflow, >= 0            */
     int32_t form;                 /* LA_FORM_PLAIN or LA_FORM_BATCHED (same results)          */
-    int32_t num_tiers;            /* batches are 0..num_tiers-1 (ignored when net_tier is NULL) */
+    int32_t num_tiers;            /* batches are 0..num_tiers-1 (ignored when net_tier and
+                                     net_batch are NULL); up to 256 for net_tier, 65536 for net_batch */
+    const int32_t *net_batch;     /* dev [nets] int32 batch of each net (e.g. from la_get_batches);
+                                     when given it replaces net_tier                              */
 } la_weights;
 
 #define LA_FORM_PLAIN 0    /* the paper's Alg. 2 shape: one launch per tree level per batch     */
@@ -192,6 +195,23 @@ la_status la_tune(la_batch *b, const la_weights *w, const int32_t *history, la_t
  * size not built for this batch's layer count or values out of range. */
 la_status la_set_tuning(la_batch *b, const la_tuning *t);
 la_status la_get_tuning(const la_batch *b, la_tuning *out);
+
+/*
+ * la_get_batches -- classical batching (Alg. 1, GetBatch, lines 6-8: the batching of the
+ * routers the paper cites for it).  A net's box is the GCell rectangle its tree spans.  Within
+ * each subset, in increasing net order, a net joins the lowest batch in which no net's box
+ * shares a GCell with its own (so the nets of a batch share no GCell edge); subsets are batched
+ * one after another and never share a batch: subset s's batches follow those of subsets
+ * 0..s-1.  The result is that of the sequential first-fit, bit for bit.
+ *  net_subset:  device [nets] int32 subset of each net (0..num_subsets-1; any other value leaves
+ *               the net out, batch -1)
+ *  out_batch:   device [nets] int32 batch of each net, for la_weights.net_batch
+ *  num_batches: HOST, receives the number of batches.
+ * At most 1024 batches in all (LA_ERR_RANGE beyond).  num_subsets in 1..256.  Allocates
+ * temporaries (the GCell grid's batch bits, 136 B per GCell), synchronises.
+ */
+la_status la_get_batches(la_batch *b, const int32_t *net_subset, int32_t num_subsets, int32_t *out_batch,
+                         int32_t *num_batches);
 
 /* Via span (lowest, highest layer) at every node of the last assignment: device [nodes][2]. */
 la_status la_vias(la_batch *b, uint8_t *out_lo_hi);

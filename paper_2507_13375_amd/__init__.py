@@ -27,7 +27,7 @@ EXPORTS = ["la_build_batch", "la_batch_info", "la_assign", "la_vias", "la_demand
            "la_quality_report",
            "la_timing_weights",
            "la_default_cong_lut", "la_save_state", "la_load_state", "la_sync", "la_profile_begin", "la_profile_end",
-           "la_tune", "la_set_tuning", "la_get_tuning",
+           "la_tune", "la_set_tuning", "la_get_tuning", "la_get_batches",
            "la_free_batch", "la_status_str", "la_last_error"]
 
 V, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -80,7 +80,7 @@ class la_quality(ctypes.Structure):
 class la_weights(ctypes.Structure):
     _fields_ = [("w_cong", I64), ("w_cap", I64), ("w_d", I64), ("w_via", I64), ("seg_w_q10", V),
                 ("pin_w_q10", V), ("lambda_mohm", V), ("net_tier", V), ("cong_lut", V), ("rounds", I32),
-                ("hist_inc", I32), ("form", I32), ("num_tiers", I32)]
+                ("hist_inc", I32), ("form", I32), ("num_tiers", I32), ("net_batch", V)]
 
 
 class LAError(RuntimeError):
@@ -127,6 +127,7 @@ def _load():
         lib.la_tune.argtypes = [V, ctypes.POINTER(la_weights), V, ctypes.POINTER(la_tuning)]
         lib.la_set_tuning.argtypes = [V, ctypes.POINTER(la_tuning)]
         lib.la_get_tuning.argtypes = [V, ctypes.POINTER(la_tuning)]
+        lib.la_get_batches.argtypes = [V, V, I32, V, ctypes.POINTER(I32)]
         lib.la_sync.argtypes = [V]
         lib.la_profile_begin.argtypes = [V]
         lib.la_profile_end.argtypes = [V, ctypes.POINTER(la_kernel_stat), I32, ctypes.POINTER(I32)]
@@ -242,17 +243,18 @@ def la_free_batch(b: Batch):
 
 def la_assign(b: Batch, seg_w_q10, pin_w_q10, lambda_mohm, history, out_layers, net_tier=None, num_tiers=1,
               w_cong=W_CONG, w_cap=W_CAP, w_d=W_D, w_via=W_VIA, rounds=1, hist_inc=HIST_INC, form=LA_FORM_PLAIN,
-              cong_lut=None):
+              cong_lut=None, net_batch=None):
+    """net_tier: u8 batch per net (<= 256 batches); net_batch: int32 batch per net (replaces it)."""
     w = la_weights(w_cong, w_cap, w_d, w_via, _dev(seg_w_q10), _dev(pin_w_q10), _dev(lambda_mohm), _dev(net_tier),
-                   _dev(cong_lut), rounds, hist_inc, form, num_tiers)
+                   _dev(cong_lut), rounds, hist_inc, form, num_tiers, _dev(net_batch))
     _chk(_load().la_assign(_on(b), ctypes.byref(w), _dev(history), _dev(out_layers)), "la_assign")
 
 
 def la_tune(b: Batch, seg_w_q10, pin_w_q10, lambda_mohm, history, net_tier=None, num_tiers=1, w_cong=W_CONG,
-            w_cap=W_CAP, w_d=W_D, w_via=W_VIA, hist_inc=HIST_INC, cong_lut=None) -> dict:
+            w_cap=W_CAP, w_d=W_D, w_via=W_VIA, hist_inc=HIST_INC, cong_lut=None, net_batch=None) -> dict:
     """Autotune the batched form on this instance (one round per candidate, state restored)."""
     w = la_weights(w_cong, w_cap, w_d, w_via, _dev(seg_w_q10), _dev(pin_w_q10), _dev(lambda_mohm), _dev(net_tier),
-                   _dev(cong_lut), 1, hist_inc, LA_FORM_BATCHED, num_tiers)
+                   _dev(cong_lut), 1, hist_inc, LA_FORM_BATCHED, num_tiers, _dev(net_batch))
     t = la_tuning()
     _chk(_load().la_tune(_on(b), ctypes.byref(w), _dev(history), ctypes.byref(t)), "la_tune")
     return t.as_dict()
@@ -276,6 +278,14 @@ def la_batch_info(b: Batch) -> dict:
     out = {k: getattr(info, k) for k, _ in la_info._fields_ if k not in ("node_parent", "node_net", "sink_node", "tuning")}
     out["tuning"] = info.tuning.as_dict()
     return out
+
+
+def la_get_batches(b: Batch, net_subset, num_subsets, out_batch) -> int:
+    """Classical batching (Alg. 1 GetBatch) of the nets by subset; returns the batch count."""
+    n = I32()
+    _chk(_load().la_get_batches(_on(b), _dev(net_subset), int(num_subsets), _dev(out_batch), ctypes.byref(n)),
+         "la_get_batches")
+    return n.value
 
 
 def la_vias(b: Batch, out_lo_hi):

@@ -23,7 +23,6 @@ la_status hip_fail(hipError_t e, const char *what)
 }
 
 la_status build_batch(const la_nets *, const la_grid *, const la_layer_rc *, const uint8_t *, void *, la_batch **);
-la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers);
 la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t *seg_w, uint16_t *pin_w,
                          int32_t *lam, uint8_t *tier);
 la_status timing_summary(la_batch *b, const float *delay, double *tns, double *wns);
@@ -155,7 +154,9 @@ static la_status check_weights(const la_batch *b, const la_weights *w, const int
         return set_error(LA_ERR_INVALID_ARG, n + ": weights must be >= 0 and rounds >= 1");
     if (w->form != LA_FORM_PLAIN && w->form != LA_FORM_BATCHED)
         return set_error(LA_ERR_INVALID_ARG, n + ": unknown form");
-    if (w->net_tier && (w->num_tiers < 1 || w->num_tiers > 256))
+    if (w->net_batch && (w->num_tiers < 1 || w->num_tiers > kMaxBatches))
+        return set_error(LA_ERR_INVALID_ARG, n + ": num_tiers must be in 1..65536 with net_batch");
+    if (!w->net_batch && w->net_tier && (w->num_tiers < 1 || w->num_tiers > 256))
         return set_error(LA_ERR_INVALID_ARG, n + ": num_tiers must be in 1..256");
     const double bound = (double)w->w_cong * b->bnd_cong + (double)w->w_cap * b->bnd_cap +
                          (double)w->w_via * b->bnd_via + (double)w->w_d * b->bnd_d;
@@ -171,7 +172,10 @@ la_status la_tune(la_batch *b, const la_weights *w, const int32_t *history, la_t
     s = set_device(b);
     if (s != LA_OK) return s;
     if (b->nodes > 0) {
-        s = tune_batched(b, w, history, w->cong_lut ? w->cong_lut : b->lut, true);
+        const int32_t *batch = nullptr;
+        s = batch_indices(b, w, &batch);
+        if (s != LA_OK) return s;
+        s = tune_batched(b, w, history, w->cong_lut ? w->cong_lut : b->lut, batch, true);
         if (s != LA_OK) return s;
     }
     if (out) fill_tuning(b->tune, out);
@@ -193,6 +197,18 @@ la_status la_set_tuning(la_batch *b, const la_tuning *t)
     return LA_OK;
 }
 
+la_status la_get_batches(la_batch *b, const int32_t *net_subset, int32_t num_subsets, int32_t *out_batch,
+                         int32_t *num_batches)
+{
+    if (!b || !num_batches || (b->nets > 0 && (!net_subset || !out_batch)))
+        return set_error(LA_ERR_INVALID_ARG, "la_get_batches: NULL argument");
+    if (num_subsets < 1 || num_subsets > 256)
+        return set_error(LA_ERR_INVALID_ARG, "la_get_batches: num_subsets must be in 1..256");
+    const la_status s = set_device(b);
+    if (s != LA_OK) return s;
+    return get_batches(b, net_subset, num_subsets, out_batch, num_batches);
+}
+
 la_status la_get_tuning(const la_batch *b, la_tuning *out)
 {
     if (!b || !out) return set_error(LA_ERR_INVALID_ARG, "la_get_tuning: NULL argument");
@@ -211,8 +227,11 @@ la_status la_assign(la_batch *b, const la_weights *w, int32_t *history, uint8_t 
     // the kernels read and update the history in the plane layout
     s = grid_to_planes(b, history, b->Hi);
     if (s != LA_OK) return s;
-    s = (w->form == LA_FORM_PLAIN) ? assign_plain(b, w, b->Hi, lut, out_layers)
-                                   : assign_batched(b, w, b->Hi, lut, out_layers);
+    const int32_t *batch = nullptr;
+    s = batch_indices(b, w, &batch);
+    if (s != LA_OK) return s;
+    s = (w->form == LA_FORM_PLAIN) ? assign_plain(b, w, b->Hi, lut, out_layers, batch)
+                                   : assign_batched(b, w, b->Hi, lut, out_layers, batch);
     if (s != LA_OK) return s;
     s = planes_to_grid(b, b->Hi, history);
     if (s != LA_OK) return s;
@@ -395,7 +414,7 @@ void la_free_batch(la_batch *b)
                     b->F, b->S, b->bt, b->sel, b->bucket_nodes, b->bucket_cnt, b->bucket_cur,
                     b->chg_node, b->chg_count, b->chg_old, b->chg_new, b->lut, b->R, b->C, b->el_S,
                     b->el_Slo, b->el_t, b->el_tlo, b->el_G, b->el_Glo, b->el_Sig, b->el_Siglo, b->slack,
-                    b->scratch_f, b->wns_bits, b->red, b->net_big, b->net_zw, b->nrec, b->dynrec, b->cnet, b->bn_order, b->bn_lvl, b->bn_lvl_off,
+                    b->scratch_f, b->wns_bits, b->red, b->net_big, b->net_zw, b->nrec, b->dynrec, b->cnet, b->bbox, b->batch_i32, b->bn_order, b->bn_lvl, b->bn_lvl_off,
                     b->bn_nlev, b->tier_nets, b->tier_off, b->tier_cur, b->tier_cnt, b->claim,
                     b->cl_pre, b->cl_blk, b->cl_start, b->cl_off, b->D_alt, b->Hi,
                     b->e_tile, b->e_big_nodes, b->e_big_ptr, b->qofw, b->qpart};

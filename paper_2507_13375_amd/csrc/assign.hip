@@ -130,7 +130,7 @@ __device__ __forceinline__ int64_t bucket_key(const TreeDev &T, const int32_t *h
     return ((((int64_t)t * levels + height[v]) << 2) | (k < 3 ? k : 3));
 }
 
-__global__ void k_bucket_count(TreeDev T, const int32_t *height, const uint8_t *tier, int32_t ntier, int32_t levels,
+__global__ void k_bucket_count(TreeDev T, const int32_t *height, const int32_t *tier, int32_t ntier, int32_t levels,
                                int32_t *counts, int32_t *bad)
 {
     __shared__ int32_t hist[kLdsBuckets];
@@ -141,7 +141,7 @@ __global__ void k_bucket_count(TreeDev T, const int32_t *height, const uint8_t *
     __syncthreads();
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x) {
         const int t = tier ? tier[T.net[v]] : 0;
-        if (t >= ntier) {
+        if (t < 0 || t >= ntier) {
             atomicAdd(bad, 1);
             continue;
         }
@@ -155,7 +155,7 @@ __global__ void k_bucket_count(TreeDev T, const int32_t *height, const uint8_t *
             if (hist[i]) atomicAdd(&counts[i], hist[i]);
 }
 
-__global__ void k_bucket_scatter(TreeDev T, const int32_t *height, const uint8_t *tier, int32_t ntier, int32_t levels,
+__global__ void k_bucket_scatter(TreeDev T, const int32_t *height, const int32_t *tier, int32_t ntier, int32_t levels,
                                  int32_t *cursor, int32_t *out)
 {
     __shared__ int32_t hist[kLdsBuckets];
@@ -165,7 +165,7 @@ __global__ void k_bucket_scatter(TreeDev T, const int32_t *height, const uint8_t
         for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes;
              v += (int64_t)gridDim.x * blockDim.x) {
             const int t = tier ? tier[T.net[v]] : 0;
-            if (t >= ntier) continue;
+            if (t < 0 || t >= ntier) continue;
             out[atomicAdd(&cursor[bucket_key(T, height, t, levels, v)], 1)] = (int32_t)v;
         }
         return;
@@ -179,7 +179,7 @@ __global__ void k_bucket_scatter(TreeDev T, const int32_t *height, const uint8_t
         int32_t r = 0;
         if (v < T.nodes) {
             const int t = tier ? tier[T.net[v]] : 0;
-            if (t < ntier) {
+            if (t >= 0 && t < ntier) {
                 q = bucket_key(T, height, t, levels, v);
                 r = atomicAdd(&hist[q], 1);
             }
@@ -282,7 +282,7 @@ la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t inc)
 }
 
 // Group nodes by (batch, height, child class); returns the per-bucket counts on the host.
-la_status bucket_nodes(la_batch *b, const uint8_t *tier, int32_t ntier, std::vector<int32_t> &counts)
+la_status bucket_nodes(la_batch *b, const int32_t *tier, int32_t ntier, std::vector<int32_t> &counts)
 {
     const int32_t Hh = b->levels;
     const size_t need = (size_t)ntier * Hh * 4;
@@ -307,7 +307,7 @@ la_status bucket_nodes(la_batch *b, const uint8_t *tier, int32_t ntier, std::vec
                           b->stream));
     LA_HIP(hipStreamSynchronize(b->stream));
     if (counts[need] != 0)
-        return set_error(LA_ERR_INVALID_ARG, "net_tier holds a batch index >= num_tiers");
+        return set_error(LA_ERR_INVALID_ARG, "a net's batch index is outside 0..num_tiers-1");
     counts.pop_back();
     std::vector<int32_t> off(need, 0);
     int64_t acc = 0;
@@ -325,11 +325,12 @@ la_status bucket_nodes(la_batch *b, const uint8_t *tier, int32_t ntier, std::vec
     return LA_OK;
 }
 
-la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers)
+la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
+                       const int32_t *batch)
 {
-    const int32_t ntier = w->net_tier ? w->num_tiers : 1;
+    const int32_t ntier = batch ? w->num_tiers : 1;
     std::vector<int32_t> counts;
-    la_status s = bucket_nodes(b, w->net_tier, ntier, counts);
+    la_status s = bucket_nodes(b, batch, ntier, counts);
     if (s != LA_OK) return s;
     const int32_t Hh = b->levels;
     std::vector<int64_t> off(counts.size() + 1, 0);

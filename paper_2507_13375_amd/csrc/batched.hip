@@ -615,7 +615,7 @@ __global__ void k_net_zero_weights(TreeDev T, const uint16_t *seg_w, const uint1
 
 constexpr int kLdsNB = 2048;   // buckets counted in LDS; more go straight to HBM counters
 
-__global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, int32_t cap,
+__global__ void k_tier_count(const int32_t *tier, int32_t ntier, int64_t nets, int32_t cap,
                              const uint8_t *zw, const int32_t *net_ptr, const int32_t *height, int32_t *cnt,
                              int32_t *bad)
 {
@@ -627,7 +627,7 @@ __global__ void k_tier_count(const uint8_t *tier, int32_t ntier, int64_t nets, i
     __syncthreads();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets; i += (int64_t)gridDim.x * blockDim.x) {
         const int t = tier ? tier[i] : 0;
-        if (t >= ntier) {
+        if (t < 0 || t >= ntier) {
             atomicAdd(bad, 1);
             continue;
         }
@@ -652,7 +652,7 @@ __global__ void k_tier_offsets(const int32_t *cnt, int32_t nb, int32_t *off, int
     for (int32_t i = threadIdx.x; i < nclaim; i += blockDim.x) claim[i] = 0;
 }
 
-__global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets, int32_t cap,
+__global__ void k_tier_scatter(const int32_t *tier, int32_t ntier, int64_t nets, int32_t cap,
                                const uint8_t *zw, const int32_t *net_ptr, const int32_t *height, int32_t *cur,
                                int32_t *out)
 {
@@ -663,7 +663,7 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets;
              i += (int64_t)gridDim.x * blockDim.x) {
             const int t = tier ? tier[i] : 0;
-            if (t >= ntier) continue;
+            if (t < 0 || t >= ntier) continue;
             out[atomicAdd(&cur[net_bucket(t, net_ptr[i + 1] - net_ptr[i] > cap, zw[i] != 0, height[net_ptr[i]])], 1)] =
                 (int32_t)i;
         }
@@ -677,7 +677,7 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
         int32_t q = -1, r = 0;
         if (i < nets) {
             const int t = tier ? tier[i] : 0;
-            if (t < ntier) {
+            if (t >= 0 && t < ntier) {
                 q = net_bucket(t, net_ptr[i + 1] - net_ptr[i] > cap, zw[i] != 0, height[net_ptr[i]]);
                 r = atomicAdd(&hist[q], 1);
             }
@@ -694,10 +694,17 @@ __global__ void k_tier_scatter(const uint8_t *tier, int32_t ntier, int64_t nets,
 // ---- claims: slices of each batch's sorted small nets by units (nodes + kNetUnits) -------
 // pre[0] = 0, pre[i + 1] = units of the net at sorted position i
 // (and the record a claim reads per net position: first node, nodes, first child entry, zero flag)
-__global__ void k_claim_units(const int32_t *tier_nets, int64_t nets, const int32_t *net_ptr, const int32_t *ch_ptr,
-                              const uint8_t *zw, int32_t *pre, int4 *cnet)
+// (positions at or after *listed, the end of the partitioned net list, hold no net: 0 units)
+__global__ void k_claim_units(const int32_t *tier_nets, int64_t nets, const int32_t *listed, const int32_t *net_ptr,
+                              const int32_t *ch_ptr, const uint8_t *zw, int32_t *pre, int4 *cnet)
 {
+    const int64_t n_listed = *listed;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nets; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i == 0) pre[0] = 0;
+        if (i >= n_listed) {
+            pre[i + 1] = 0;
+            continue;
+        }
         const int32_t net = tier_nets[i];
         const int32_t n0 = net_ptr[net], nn = net_ptr[net + 1] - n0;
         pre[i + 1] = nn + kNetUnits;
@@ -846,9 +853,9 @@ int32_t small_nets(const std::vector<int32_t> &cnt, int32_t t)
 // small nets commits them from its DP kernel into a copy of the demand map (its DP reads the
 // map as it was before the batch); the copy then becomes the current map.
 la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
-                         const std::vector<int32_t> &cnt, const std::vector<int32_t> &groups, hipStream_t s)
+                         int32_t ntier, const std::vector<int32_t> &cnt, const std::vector<int32_t> &groups,
+                         hipStream_t s)
 {
-    const int32_t ntier = w->net_tier ? w->num_tiers : 1;
     const int32_t ngroup = (int32_t)groups.size() / 2;
     const int32_t R = w->rounds;
     la_status st = LA_OK;
@@ -917,9 +924,9 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
 }  // namespace
 
 la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
-                         bool direct)
+                         const int32_t *batch, bool direct)
 {
-    const int32_t ntier = w->net_tier ? w->num_tiers : 1;
+    const int32_t ntier = batch ? w->num_tiers : 1;
     const int32_t nb = ntier * kNB;
     const int32_t R = w->rounds;
     if (b->claim_cap < R * ntier) {
@@ -928,6 +935,27 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         if (hipMalloc((void **)&b->claim, (size_t)R * ntier * sizeof(int32_t)) != hipSuccess)
             return set_error(LA_ERR_OOM, "claim counters");
         b->claim_cap = R * ntier;
+    }
+    // partition and claim arrays hold every batch (more than the 256 la_build_batch sized them for
+    // when the caller hands over its own batches)
+    if (b->part_cap < ntier) {
+        for (int32_t **p : {&b->tier_off, &b->tier_cur, &b->tier_cnt, &b->cl_off, &b->cl_start}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        const int64_t starts = (b->nodes + (int64_t)kNetUnits * b->nets) / kClaimUnitsMin + 2 * (int64_t)ntier + 2;
+        if (hipMalloc((void **)&b->tier_off, ((size_t)ntier * kNB + 2) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void **)&b->tier_cur, ((size_t)ntier * kNB + 2) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void **)&b->tier_cnt, ((size_t)ntier * kNB + 2) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void **)&b->cl_off, ((size_t)ntier + 2) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void **)&b->cl_start, (size_t)starts * sizeof(int32_t)) != hipSuccess) {
+            b->part_cap = 0;
+            return set_error(LA_ERR_OOM, "batch partition arrays");
+        }
+        b->part_cap = ntier;
+        b->cl_start_cap = starts;
+        for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);   // they hold the old arrays
+        b->graphs.clear();
     }
     // partition the nets by batch (big nets first, then nets with timing weights, then those
     // without, each by height) and check the batch indices
@@ -938,13 +966,20 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     });
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb + 1);
     LA_TIMED(b, "k_tier_count", b->stream,
-             hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
+             hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, batch, ntier,
                                 b->nets, b->tune.tile_nodes, b->net_zw, b->net_ptr, b->height, b->tier_cnt,
                                 b->tier_cnt + nb));
+    // the counts (and the count of nets whose batch index is out of range) before anything reads
+    // the partition: the net list holds only the nets of valid batches
+    LA_HIP(hipGetLastError());
+    std::vector<int32_t> cnt(nb + 1);
+    LA_HIP(hipMemcpyAsync(cnt.data(), b->tier_cnt, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
+    LA_HIP(hipStreamSynchronize(b->stream));
+    if (cnt[nb]) return set_error(LA_ERR_INVALID_ARG, "a net's batch index is outside 0..num_tiers-1");
     hipLaunchKernelGGL(k_tier_offsets, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb, b->tier_off, b->tier_cur,
                        b->claim, R * ntier);
     LA_TIMED(b, "k_tier_scatter", b->stream,
-             hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, ntier,
+             hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, batch, ntier,
                                 b->nets, b->tune.tile_nodes, b->net_zw, b->net_ptr, b->height, b->tier_cur,
                                 b->tier_nets));
     // work-queue claims of each batch's small nets
@@ -952,7 +987,7 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         const int64_t n = b->nets + 1;
         const int32_t nchunk = (int32_t)((n + 1023) / 1024);
         hipLaunchKernelGGL(k_claim_units, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, b->tier_nets, b->nets,
-                           b->net_ptr, b->ch_ptr, b->net_zw, b->cl_pre, (int4 *)b->cnet);
+                           b->tier_off + nb, b->net_ptr, b->ch_ptr, b->net_zw, b->cl_pre, (int4 *)b->cnet);
         hipLaunchKernelGGL(k_scan_chunks, dim3(nchunk), dim3(256), 0, b->stream, b->cl_pre, n, b->cl_blk);
         hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, b->stream, b->cl_blk, nchunk);
         hipLaunchKernelGGL(k_scan_add, dim3(grid1d(n)), dim3(256), 0, b->stream, b->cl_pre, n, b->cl_blk);
@@ -962,10 +997,6 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
                            b->nets, b->cl_pre, b->tune.claim_units, b->cl_off, b->cl_start);
     }
     LA_HIP(hipGetLastError());
-    std::vector<int32_t> cnt(nb + 1);
-    LA_HIP(hipMemcpyAsync(cnt.data(), b->tier_cnt, (nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
-    LA_HIP(hipStreamSynchronize(b->stream));
-    if (cnt[nb]) return set_error(LA_ERR_INVALID_ARG, "net_tier holds a batch index >= num_tiers");
 
     // Consecutive batches of at most kMergeNets small nets whose bounding boxes are pairwise
     // disjoint run as one launch: no net of a later batch reads a GCell edge that an earlier
@@ -1027,14 +1058,14 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     // While kernels are being timed the same launches go straight to the batch's stream.
     if (b->prof_on || direct) {
         hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(256), 0, b->stream, b->claim, R * ntier);
-        la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, groups, b->stream);
+        la_status st = enqueue_rounds(b, w, H, lut, out_layers, ntier, cnt, groups, b->stream);
         if (st != LA_OK) return st;
         b->has_prev = true;
         return LA_OK;
     }
     std::vector<int64_t> key = {R, ntier, b->has_prev, w->w_cong, w->w_cap, w->w_d, w->w_via, w->hist_inc,
                                 (int64_t)w->seg_w_q10, (int64_t)w->pin_w_q10, (int64_t)w->lambda_mohm,
-                                (int64_t)lut, (int64_t)H, (int64_t)out_layers, b->tune.tile_nodes,
+                                (int64_t)lut, (int64_t)H, (int64_t)out_layers, (int64_t)batch, b->tune.tile_nodes,
                                 b->tune.claim_units, b->tune.workgroups, b->tune.fuse_nets};
     for (int32_t t = 0; t < ntier; ++t) {
         key.push_back(cnt[t * kNB]);
@@ -1050,7 +1081,7 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         if (!b->cap_stream) LA_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         hipStream_t s = b->cap_stream;
         LA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const la_status st = enqueue_rounds(b, w, H, lut, out_layers, cnt, groups, s);
+        const la_status st = enqueue_rounds(b, w, H, lut, out_layers, ntier, cnt, groups, s);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(s, &g);
         if (st != LA_OK) {
@@ -1075,6 +1106,29 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     }
     LA_HIP(hipGraphLaunch(cache.front().second, b->stream));
     b->has_prev = true;
+    return LA_OK;
+}
+
+// ---- batch indices --------------------------------------------------------------------
+namespace {
+__global__ void k_widen_u8(const uint8_t *in, int32_t *out, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+}  // namespace
+
+la_status batch_indices(la_batch *b, const la_weights *w, const int32_t **out)
+{
+    *out = nullptr;
+    if (w->net_batch) {
+        *out = w->net_batch;
+    } else if (w->net_tier) {
+        hipLaunchKernelGGL(k_widen_u8, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, w->net_tier, b->batch_i32,
+                           b->nets);
+        LA_HIP(hipGetLastError());
+        *out = b->batch_i32;
+    }
     return LA_OK;
 }
 
@@ -1109,7 +1163,8 @@ struct Saved {
 };
 }  // namespace
 
-la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history, const int32_t *lut, bool use_cache)
+la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history, const int32_t *lut,
+                       const int32_t *batch, bool use_cache)
 {
     const std::vector<int64_t> key = shape_key(b);
     if (use_cache) {
@@ -1158,7 +1213,7 @@ la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history,
         if (restore() != LA_OK) return -1.0;
         b->tune = t;
         if (timed && hipEventRecord(e0, s) != hipSuccess) return -1.0;
-        if (assign_batched(b, &w1, b->Hi, lut, nullptr, true) != LA_OK) return -1.0;
+        if (assign_batched(b, &w1, b->Hi, lut, nullptr, batch, true) != LA_OK) return -1.0;
         if (timed && hipEventRecord(e1, s) != hipSuccess) return -1.0;
         if (hipStreamSynchronize(s) != hipSuccess) return -1.0;
         float ms = 0.f;

@@ -540,6 +540,8 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
             }
         }
         chk(upload(&b->nrec, rec));
+    chk(upload(&b->bbox, b->h_bbox));
+    chk(alloc(&b->batch_i32, std::max<int64_t>(N, 1)));
     }
     chk(alloc(&b->dynrec, (size_t)std::max<int64_t>(M, 1) * 2));
     chk(alloc(&b->cnet, (size_t)std::max<int64_t>(N, 1) * 4));

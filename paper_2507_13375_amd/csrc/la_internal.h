@@ -26,6 +26,7 @@ constexpr int kClaimUnitsMin = 96, kClaimUnitsMax = 316;   // claim sizes the au
 constexpr int kClaimNets = 80;     // bound on the nets of one claim (kClaimUnitsMax / (1 + kNetUnits) + 1)
 constexpr int32_t kFuseDefault = 16384;   // batches with this many small nets commit from their DP kernel
 constexpr size_t kGraphSlots = 4;         // round graphs kept instantiated per batch
+constexpr int32_t kMaxBatches = 65536;    // batches of one la_assign call given as int32 indices
 
 // Launch configuration of the batched form (la_tune picks it per instance shape).
 struct Tuning {
@@ -141,6 +142,7 @@ struct la_batch {
     std::vector<int32_t> h_ebig_ptr;    // [levels+1]
     std::vector<int32_t> h_net_ptr;
     std::vector<int16_t> h_bbox;        // [nets][4] x min, x max, y min, y max of the net's nodes
+    int16_t *bbox = nullptr;            // the same on the device
 
     // device tree
     int32_t *parent = nullptr, *ch_ptr = nullptr, *ch = nullptr, *net = nullptr, *net_ptr = nullptr;
@@ -191,6 +193,8 @@ struct la_batch {
     // claim offsets
     int32_t *cl_pre = nullptr, *cl_blk = nullptr, *cl_start = nullptr, *cl_off = nullptr;
     int64_t cl_start_cap = 0;
+    int32_t part_cap = 256;         // batches the partition and claim arrays hold
+    int32_t *batch_i32 = nullptr;   // [nets] u8 batch indices widened for the kernels
     hipStream_t cap_stream = nullptr;
     // instantiated round graphs of the batched form by call key, most recently used first
     std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
@@ -268,12 +272,19 @@ la_status commit_changed(la_batch *b, int32_t *D);
 la_status grid_to_planes(la_batch *b, const int32_t *api, int32_t *planes);
 la_status planes_to_grid(la_batch *b, const int32_t *planes, int32_t *api);
 la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t hist_inc);
-la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut);
+la_status assign_plain(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
+                       const int32_t *batch);
+// batch: device [nets] int32 batch of each net (NULL: one batch)
 la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int32_t *lut, uint8_t *out_layers,
-                         bool direct = false);
+                         const int32_t *batch, bool direct = false);
 bool tile_size_supported(int NA, int cap);
+// classical batching (Alg. 1 GetBatch) of the nets by subset; synchronises
+la_status get_batches(la_batch *b, const int32_t *subset, int32_t nsub, int32_t *out_batch, int32_t *num_batches);
 // picks b->tune on the instance (or from the cache of instance shapes); state is unchanged
-la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history, const int32_t *lut, bool use_cache);
+la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history, const int32_t *lut,
+                       const int32_t *batch, bool use_cache);
+// the batch indices the forms read: the caller's int32 array, a widened copy of its u8 tiers, or NULL
+la_status batch_indices(la_batch *b, const la_weights *w, const int32_t **out);
 // the static scratch of the allocation-free entry point: its address on `device` (once per device)
 la_status scratch_setup(int device);
 la_status timing_summary_noalloc(la_batch *b, const float *delay, double *tns, double *wns);
