@@ -70,6 +70,9 @@ def _load():
         lib.gen_sizes.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3
         lib.gen_export.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 16
         lib.gen_counter_u64.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+        lib.gen_timing_graph.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -176,6 +179,31 @@ def config(c: int, num_nets: int | None = None) -> Instance:
     n = p.pop("num_nets")
     X, Y, L = p.pop("X"), p.pop("Y"), p.pop("L")
     return generate(n, X, Y, L, CONFIG_SEED[c], name="c%d" % c, **p)
+
+
+def timing_graph(inst: Instance, levels: int = 24, po_frac: float = 0.2, dmin_fs: int = 8000, dmax_fs: int = 25000,
+                 seed: int = 2507133750 + 100, clock_fs: int = 1000000) -> dict:
+    """Synthetic gate-level timing graph over the nets of `inst` (for Alg. 1's critical-path
+    ordering): per net a logic level and the delay of its driving gate (fs); per sink (node
+    order) the net whose gate it feeds, or -1 for a primary output; the clock period (required
+    time at every primary output).  1 ns leaves about a quarter of the outputs violating on the
+    2M-net workload before assignment."""
+    lib = _load()
+    nptr = np.ascontiguousarray(inst.net_node_ptr, np.int32)
+    flags = np.ascontiguousarray(inst.node_flags, np.uint8)
+    n = int(inst.num_nets)
+    sinks = int(np.count_nonzero(flags & 1))
+    lvl = np.empty(max(n, 1), np.int32)
+    nxt = np.empty(max(sinks, 1), np.int32)
+    gd = np.empty(max(n, 1), np.int32)
+    sd = seed
+    rc = lib.gen_timing_graph(n, nptr.ctypes.data_as(ctypes.c_void_p), flags.ctypes.data_as(ctypes.c_void_p),
+                              int(levels), float(po_frac), int(dmin_fs), int(dmax_fs), ctypes.c_uint64(sd & (2**64 - 1)),
+                              lvl.ctypes.data_as(ctypes.c_void_p), nxt.ctypes.data_as(ctypes.c_void_p),
+                              gd.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise ValueError("gen_timing_graph failed (%d)" % rc)
+    return dict(net_level=lvl[:n], sink_next=nxt[:sinks], gate_delay_fs=gd[:n], levels=levels, clock_fs=int(clock_fs))
 
 
 def counter_u64(seed: int, n: int, start: int = 0) -> np.ndarray:

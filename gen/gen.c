@@ -385,3 +385,62 @@ void gen_counter_u64(uint64_t seed, int64_t start, int64_t n, uint64_t *out)
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) out[i] = sm64_at(seed, (uint64_t)(start + i));
 }
+
+/*
+ * Synthetic gate-level timing graph over the nets, for the critical-path net ordering of
+ * Alg. 1: every net is driven by one gate whose delay is uniform in {dmin..dmax} fs; every
+ * net gets a logic level uniform in {0..levels-1}; every sink of a net at level h feeds the
+ * gate of a net drawn uniformly from the nets at level h + 1 (sink_next = that net), unless
+ * the net is at the last level or, with probability po_frac, the sink is a primary output
+ * (sink_next = -1).  Sinks are numbered in node order (the sink-flagged input nodes in net and
+ * node order).  Structure only: no delay or timing arithmetic.
+ */
+int gen_timing_graph(int64_t nets, const int32_t *net_node_ptr, const uint8_t *node_flags, int32_t levels,
+                     double po_frac, int32_t dmin_fs, int32_t dmax_fs, uint64_t seed, int32_t *net_level,
+                     int32_t *sink_next, int32_t *gate_delay_fs)
+{
+    if (nets < 0 || levels < 1 || dmin_fs < 0 || dmax_fs < dmin_fs || !(po_frac >= 0.0 && po_frac <= 1.0))
+        return GEN_ERR_ARG;
+    uint64_t s = seed ^ 0x74696d696e674441ull;   /* a stream of its own */
+    int64_t *cnt = (int64_t *)calloc((size_t)levels + 1, sizeof(int64_t));
+    int64_t *by_level = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nets > 0 ? nets : 1));
+    if (!cnt || !by_level) {
+        free(cnt);
+        free(by_level);
+        return GEN_ERR_OOM;
+    }
+    for (int64_t i = 0; i < nets; ++i) {
+        net_level[i] = (int32_t)uint_range(&s, 0, levels - 1);
+        gate_delay_fs[i] = (int32_t)uint_range(&s, dmin_fs, dmax_fs);
+        cnt[net_level[i] + 1]++;
+    }
+    for (int32_t h = 0; h < levels; ++h) cnt[h + 1] += cnt[h];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)levels);
+        if (!fill) {
+            free(cnt);
+            free(by_level);
+            return GEN_ERR_OOM;
+        }
+        for (int32_t h = 0; h < levels; ++h) fill[h] = cnt[h];
+        for (int64_t i = 0; i < nets; ++i) by_level[fill[net_level[i]]++] = i;
+        free(fill);
+    }
+    int64_t k = 0;
+    for (int64_t i = 0; i < nets; ++i) {
+        const int32_t h = net_level[i];
+        const int64_t n_next = h + 1 < levels ? cnt[h + 2] - cnt[h + 1] : 0;
+        for (int32_t v = net_node_ptr[i]; v < net_node_ptr[i + 1]; ++v) {
+            if (!(node_flags[v] & 1)) continue;
+            const double u = u01(&s);
+            if (n_next == 0 || u < po_frac) {
+                sink_next[k++] = -1;
+            } else {
+                sink_next[k++] = (int32_t)by_level[cnt[h + 1] + uint_range(&s, 0, n_next - 1)];
+            }
+        }
+    }
+    free(cnt);
+    free(by_level);
+    return GEN_OK;
+}

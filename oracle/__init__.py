@@ -89,6 +89,9 @@ def _load():
         lib.oracle_set_num_threads.argtypes = [I32]
         lib.oracle_get_batches.argtypes = [V, I32, I32, V, I32, V]
         lib.oracle_get_batches.restype = I64
+        lib.oracle_sta.argtypes = [V, V, V, I32, V, V, V, ctypes.POINTER(ctypes.c_float)]
+        lib.oracle_alg1_subsets.argtypes = [V, V, V, ctypes.c_float, V]
+        lib.oracle_alg1_subsets.restype = I32
         lib.oracle_quality.argtypes = [V, I32, I32, I32] + [V] * 7 + [ctypes.POINTER(ctypes.c_double)] + \
             [ctypes.POINTER(I64)] * 4
         lib.oracle_quality.restype = None
@@ -270,6 +273,30 @@ def get_batches(tree: Tree, X: int, Y: int, subset, nsub: int):
     if n < 0:
         raise MemoryError("oracle_get_batches")
     return out[:tree.nets], n
+
+
+def sta(tree: Tree, sink_next, gate_delay_fs, clock_fs: int, delay):
+    """Static timing of the gate graph over the nets (Alg. 1 line 1) in single precision, and the
+    critical-path counts of line 2.  delay: per-sink Elmore delay (ps, float32).  Returns
+    (slack per sink, critical paths per net, WNS)."""
+    sl = np.empty(max(tree.sinks, 1), np.float32)
+    cr = np.empty(max(tree.nets, 1), np.int32)
+    w = ctypes.c_float()
+    rc = _load().oracle_sta(tree.handle, _p(np.ascontiguousarray(sink_next, np.int32)),
+                            _p(np.ascontiguousarray(gate_delay_fs, np.int32)), int(clock_fs),
+                            _p(np.ascontiguousarray(delay, np.float32)), _p(sl), _p(cr), ctypes.byref(w))
+    if rc != OK:
+        raise OracleError(rc, "sta")
+    return sl[:tree.sinks], cr[:tree.nets], w.value
+
+
+def alg1_subsets(tree: Tree, slack, crit, wns: float):
+    """Alg. 1 lines 3-5: the ordered subsets (critical by path count, semi-critical by slack,
+    then the rest).  Returns (subset per net, number of subsets)."""
+    out = np.empty(max(tree.nets, 1), np.int32)
+    n = _load().oracle_alg1_subsets(tree.handle, _p(np.ascontiguousarray(slack, np.float32)),
+                                    _p(np.ascontiguousarray(crit, np.int32)), ctypes.c_float(wns), _p(out))
+    return out[:tree.nets], int(n)
 
 
 def num_threads() -> int:

@@ -933,6 +933,160 @@ int64_t oracle_get_batches(const otree *T, int32_t X, int32_t Y, const int32_t *
     return ok ? base : -1;
 }
 
+/*
+ * Static timing of a gate-level graph over the nets (Alg. 1 line 1) and the critical-path
+ * count of line 2.  Each net is driven by one gate (delay gate_fs); each sink feeds the gate of
+ * net sink_next (or is a primary output, -1).  Single precision, each value rounded once as
+ * written (max and min are exact), so decisions taken from it (a gate's latest input, the bins
+ * of Alg. 1) come out the same in any evaluation order:
+ *   arrival at the driver of net m:  AD[m] = gd[m] + (max over sinks s feeding m of AS[s]; 0 if none)
+ *   arrival at sink s of net n:     AS[s] = AD[n] + delay[s]
+ *   required at sink s:             RS[s] = clock (primary output) or RD[next[s]] - gd[next[s]]
+ *   required at the driver of n:    RD[n] = min over n's sinks s of (RS[s] - delay[s])
+ *   slack[s] = RS[s] - AS[s];  WNS = min over primary outputs of their slack.
+ * gd and clock in ps, each (float)(fs * 1e-3).  The top-1 critical path of every primary output
+ * with slack < 0.7 WNS (only when WNS < 0): its net, then back through each gate's latest input
+ * (the lowest sink on equal arrival) to a primary input; crit[n] counts the paths through net n.
+ * Returns O_ERR_INVALID_ARG for a cycle or a sink_next outside the nets.
+ */
+int oracle_sta(const otree *T, const int32_t *sink_next, const int32_t *gate_fs, int32_t clock_fs,
+               const float *delay, float *slack, int32_t *crit, float *wns_out)
+{
+    const int64_t N = T->nets, S = T->sinks;
+    int64_t *indeg = (int64_t *)calloc((size_t)N + 1, sizeof(int64_t));
+    int64_t *fin_ptr = (int64_t *)calloc((size_t)N + 1, sizeof(int64_t));
+    int64_t *fin = (int64_t *)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
+    int64_t *topo = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+    float *AD = (float *)malloc(sizeof(float) * (size_t)(N > 0 ? N : 1));
+    float *RD = (float *)malloc(sizeof(float) * (size_t)(N > 0 ? N : 1));
+    float *AS = (float *)malloc(sizeof(float) * (size_t)(S > 0 ? S : 1));
+    float *RS = (float *)malloc(sizeof(float) * (size_t)(S > 0 ? S : 1));
+    int rc = O_OK;
+    if (!indeg || !fin_ptr || !fin || !topo || !AD || !RD || !AS || !RS) { rc = O_ERR_OOM; goto done; }
+    /* fan-in of each net's gate: the sinks that feed it, ascending */
+    for (int64_t k = 0; k < S; ++k) {
+        if (sink_next[k] >= N || sink_next[k] < -1) { rc = O_ERR_INVALID_ARG; goto done; }
+        if (sink_next[k] >= 0) fin_ptr[sink_next[k] + 1]++;
+    }
+    for (int64_t m = 0; m < N; ++m) fin_ptr[m + 1] += fin_ptr[m];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+        if (!fill) { rc = O_ERR_OOM; goto done; }
+        for (int64_t m = 0; m < N; ++m) fill[m] = fin_ptr[m];
+        for (int64_t k = 0; k < S; ++k)
+            if (sink_next[k] >= 0) fin[fill[sink_next[k]]++] = k;
+        free(fill);
+    }
+    /* topological order of the nets (Kahn): a net after every net whose sink feeds its gate */
+    for (int64_t m = 0; m < N; ++m) indeg[m] = fin_ptr[m + 1] - fin_ptr[m];
+    {
+        int64_t head = 0, tail = 0;
+        for (int64_t m = 0; m < N; ++m) if (indeg[m] == 0) topo[tail++] = m;
+        while (head < tail) {
+            const int64_t n = topo[head++];
+            for (int64_t v = T->net_ptr[n]; v < T->net_ptr[n + 1]; ++v) {
+                const int64_t k = T->sink_of[v];
+                if (k < 0 || sink_next[k] < 0) continue;
+                if (--indeg[sink_next[k]] == 0) topo[tail++] = sink_next[k];
+            }
+        }
+        if (tail != N) { rc = O_ERR_INVALID_ARG; goto done; }
+    }
+    /* arrival times in topological order */
+    for (int64_t q = 0; q < N; ++q) {
+        const int64_t m = topo[q];
+        float in = 0.0f;
+        for (int64_t j = fin_ptr[m]; j < fin_ptr[m + 1]; ++j) if (AS[fin[j]] > in) in = AS[fin[j]];
+        AD[m] = (float)((double)gate_fs[m] * 1e-3) + in;
+        for (int64_t v = T->net_ptr[m]; v < T->net_ptr[m + 1]; ++v)
+            if (T->sink_of[v] >= 0) AS[T->sink_of[v]] = AD[m] + delay[T->sink_of[v]];
+    }
+    /* required times in reverse topological order */
+    const float clock = (float)((double)clock_fs * 1e-3);
+    for (int64_t q = N - 1; q >= 0; --q) {
+        const int64_t n = topo[q];
+        float rd = INFINITY;
+        for (int64_t v = T->net_ptr[n]; v < T->net_ptr[n + 1]; ++v) {
+            const int64_t k = T->sink_of[v];
+            if (k < 0) continue;
+            const int32_t m = sink_next[k];
+            RS[k] = m < 0 ? clock : RD[m] - (float)((double)gate_fs[m] * 1e-3);
+            const float r = RS[k] - delay[k];
+            if (r < rd) rd = r;
+        }
+        RD[n] = rd;
+    }
+    float wns = INFINITY;
+    for (int64_t k = 0; k < S; ++k) {
+        slack[k] = RS[k] - AS[k];
+        if (sink_next[k] < 0 && slack[k] < wns) wns = slack[k];
+    }
+    *wns_out = wns;
+    for (int64_t n = 0; n < N; ++n) crit[n] = 0;
+    if (wns < 0.0f) {
+        const float lim = 0.7f * wns;
+        for (int64_t k = 0; k < S; ++k) {
+            if (sink_next[k] >= 0 || !(slack[k] < lim)) continue;
+            int64_t n = T->net_of[T->sink_node[k]];
+            for (;;) {
+                crit[n] += 1;
+                int64_t best = -1;
+                for (int64_t j = fin_ptr[n]; j < fin_ptr[n + 1]; ++j)
+                    if (best < 0 || AS[fin[j]] > AS[best]) best = fin[j];   /* fin is ascending */
+                if (best < 0) break;
+                n = T->net_of[T->sink_node[best]];
+            }
+        }
+    }
+done:
+    free(indeg); free(fin_ptr); free(fin); free(topo); free(AD); free(RD); free(AS); free(RS);
+    return rc;
+}
+
+/*
+ * Alg. 1 lines 3-5: divide the nets and partition the timing-critical ones into ordered
+ * subsets.  Net slack = the minimum slack over the net's sinks.  Critical nets (N_c): more than
+ * three counted critical paths; with C the largest count, subset k holds the counts c with
+ * C / 2^k <= c < C / 2^(k-1) (subset 0: c = C).  Semi-critical nets (N_s): the other nets whose
+ * net slack is below 0.7 WNS, by rho = slack / WNS: 1, [0.99, 1), [0.96, 0.99), [0.91, 0.96),
+ * [0.84, 0.91), [0.75, 0.84), [0.7, 0.75) (single precision, as the bins of the weights).  The
+ * rest (N_n) form one subset.  Subsets: the critical ones 0..kc-1, the seven slack bins, then
+ * the non-critical one; returns their number (kc + 8).
+ */
+int32_t oracle_alg1_subsets(const otree *T, const float *slack, const int32_t *crit, float wns, int32_t *subset)
+{
+    const int64_t N = T->nets;
+    int32_t C = 0;
+    for (int64_t n = 0; n < N; ++n) if (crit[n] > 3 && crit[n] > C) C = crit[n];
+    int32_t kc = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        if (crit[n] <= 3) continue;
+        int32_t k = 0;
+        while (((int64_t)crit[n] << k) < C) ++k;
+        if (k + 1 > kc) kc = k + 1;
+    }
+    static const float lo[7] = {1.0f, 0.99f, 0.96f, 0.91f, 0.84f, 0.75f, 0.7f};
+    for (int64_t n = 0; n < N; ++n) {
+        if (crit[n] > 3) {
+            int32_t k = 0;
+            while (((int64_t)crit[n] << k) < C) ++k;
+            subset[n] = k;
+            continue;
+        }
+        float ns = INFINITY;
+        for (int64_t v = T->net_ptr[n]; v < T->net_ptr[n + 1]; ++v)
+            if (T->sink_of[v] >= 0 && slack[T->sink_of[v]] < ns) ns = slack[T->sink_of[v]];
+        int32_t b = 7;   /* non-critical */
+        if (wns < 0.0f && ns < 0.7f * wns) {
+            const float rho = ns / wns;
+            b = 6;
+            for (int j = 0; j < 7; ++j) if (rho >= lo[j]) { b = j; break; }
+        }
+        subset[n] = kc + b;
+    }
+    return kc + 8;
+}
+
 /* Threads the OpenMP loops above use (for reporting timings), and a way to change it (the
  * results do not depend on it: per-net work is independent and commits are integer). */
 int oracle_num_threads(void) { return omp_get_max_threads(); }

@@ -15,7 +15,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_FILES = ["tests/test_oracle_dp.py", "tests/test_oracle_weights.py", "tests/test_oracle_elmore.py",
-             "tests/test_oracle_quality.py", "tests/test_oracle_tree.py", "tests/test_oracle_batches.py"]
+             "tests/test_oracle_quality.py", "tests/test_oracle_tree.py", "tests/test_oracle_batches.py",
+             "tests/test_oracle_sta.py"]
 
 TIE = "if (bl < 0 || key < bkey) { bl = lc; bkey = key; }"
 
@@ -62,6 +63,15 @@ MUTANTS = {
                                "for (int32_t y = b[2] + 1; y <= b[3] && free_here; ++y)", None),
     "batch_box_short": ("if (T->x[v] > x1) x1 = T->x[v];", "if (T->x[v] > x1) x1 = T->x[v] - 1;", None),
     "batch_subsets_shared": ("base += nb;", "base += 0;", None),
+    # static timing of the gate graph and Alg. 1's division
+    "sta_gate_delay_dropped": ("AD[m] = (float)((double)gate_fs[m] * 1e-3) + in;", "AD[m] = in;", None),
+    "sta_required_max": ("if (r < rd) rd = r;", "if (r > rd || rd == INFINITY) rd = r;", None),
+    "sta_tie_last_input": ("if (best < 0 || AS[fin[j]] > AS[best]) best = fin[j];",
+                           "if (best < 0 || AS[fin[j]] >= AS[best]) best = fin[j];", None),
+    "sta_path_threshold": ("const float lim = 0.7f * wns;", "const float lim = 0.75f * wns;", None),
+    "alg1_critical_from_three": ("        if (crit[n] > 3) {\n            int32_t k = 0;",
+                                 "        if (crit[n] >= 3) {\n            int32_t k = 0;", None),
+    "alg1_semi_threshold": ("if (wns < 0.0f && ns < 0.7f * wns) {", "if (wns < 0.0f && ns < 0.5f * wns) {", None),
 }
 
 
