@@ -213,6 +213,38 @@ la_status la_get_tuning(const la_batch *b, la_tuning *out);
 la_status la_get_batches(la_batch *b, const int32_t *net_subset, int32_t num_subsets, int32_t *out_batch,
                          int32_t *num_batches);
 
+/*
+ * Critical-path net ordering (Sec. III-A; Alg. 1 lines 1-5) on a gate-level graph over the nets.
+ * la_timing_graph sets the graph: each net is driven by one gate (gate_delay_fs: HOST [nets]);
+ * sink k (node order) feeds the gate of net sink_next[k] (HOST [sinks]), or is a primary output
+ * (-1) whose required time is clock_fs.  Copied; ordered topologically on the host.
+ * LA_ERR_INVALID_ARG for an index out of range, a negative delay or a cycle.
+ */
+la_status la_timing_graph(la_batch *b, const int32_t *sink_next, const int32_t *gate_delay_fs, int32_t clock_fs);
+/*
+ * la_sta -- static timing with the given sink delays (DEVICE [sinks] ps, e.g. from la_elmore) in
+ * single precision, each value rounded once as written: arrival at a net's driver = gate delay +
+ * the latest arrival among the sinks feeding the gate (0 if none); at a sink = its driver's +
+ * its delay; required at an output = clock, at a sink feeding net m = required at m's driver -
+ * m's gate delay, at a driver = min over its sinks of (required - delay).
+ *  out_slack: DEVICE [sinks] required - arrival;  *wns: HOST, the least output slack.
+ *  out_crit:  DEVICE [nets] int32, the number of top-1 critical paths through each net: one per
+ *             primary output with slack < 0.7 WNS (when WNS < 0), from its net back through
+ *             each gate's latest input (the lowest sink on equal arrival) to a primary input.
+ * Synchronises.  LA_ERR_STATE without la_timing_graph.
+ */
+la_status la_sta(la_batch *b, const float *sink_delay, float *out_slack, int32_t *out_crit, float *wns);
+/*
+ * la_alg1_subsets -- Alg. 1 lines 3-5: critical nets (more than three counted paths) by count
+ * against the largest, C: subset k holds C / 2^k <= count < C / 2^(k-1); the other nets whose
+ * net slack (least over its sinks) is below 0.7 WNS by rho = slack / WNS in the bins 1,
+ * [0.99, 1), [0.96, 0.99), [0.91, 0.96), [0.84, 0.91), [0.75, 0.84), [0.7, 0.75); then the rest.
+ * Subsets: critical 0..kc-1, the seven slack bins, the rest; *num_subsets = kc + 8 (HOST).
+ * out_subset: DEVICE [nets] int32, for la_get_batches.  Synchronises.
+ */
+la_status la_alg1_subsets(la_batch *b, const float *slack, const int32_t *crit, float wns, int32_t *out_subset,
+                          int32_t *num_subsets);
+
 /* Via span (lowest, highest layer) at every node of the last assignment: device [nodes][2]. */
 la_status la_vias(la_batch *b, uint8_t *out_lo_hi);
 

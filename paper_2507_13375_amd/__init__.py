@@ -27,7 +27,8 @@ EXPORTS = ["la_build_batch", "la_batch_info", "la_assign", "la_vias", "la_demand
            "la_quality_report",
            "la_timing_weights",
            "la_default_cong_lut", "la_save_state", "la_load_state", "la_sync", "la_profile_begin", "la_profile_end",
-           "la_tune", "la_set_tuning", "la_get_tuning", "la_get_batches",
+           "la_tune", "la_set_tuning", "la_get_tuning", "la_get_batches", "la_timing_graph", "la_sta",
+           "la_alg1_subsets",
            "la_free_batch", "la_status_str", "la_last_error"]
 
 V, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -128,6 +129,9 @@ def _load():
         lib.la_set_tuning.argtypes = [V, ctypes.POINTER(la_tuning)]
         lib.la_get_tuning.argtypes = [V, ctypes.POINTER(la_tuning)]
         lib.la_get_batches.argtypes = [V, V, I32, V, ctypes.POINTER(I32)]
+        lib.la_timing_graph.argtypes = [V, V, V, I32]
+        lib.la_sta.argtypes = [V, V, V, V, ctypes.POINTER(ctypes.c_float)]
+        lib.la_alg1_subsets.argtypes = [V, V, V, ctypes.c_float, V, ctypes.POINTER(I32)]
         lib.la_sync.argtypes = [V]
         lib.la_profile_begin.argtypes = [V]
         lib.la_profile_end.argtypes = [V, ctypes.POINTER(la_kernel_stat), I32, ctypes.POINTER(I32)]
@@ -285,6 +289,28 @@ def la_get_batches(b: Batch, net_subset, num_subsets, out_batch) -> int:
     n = I32()
     _chk(_load().la_get_batches(_on(b), _dev(net_subset), int(num_subsets), _dev(out_batch), ctypes.byref(n)),
          "la_get_batches")
+    return n.value
+
+
+def la_timing_graph(b: Batch, sink_next, gate_delay_fs, clock_fs: int):
+    """Gate graph over the nets for Alg. 1 (host arrays: net fed by each sink or -1; gate delays, fs)."""
+    nxt = np.ascontiguousarray(sink_next, np.int32)
+    gd = np.ascontiguousarray(gate_delay_fs, np.int32)
+    _chk(_load().la_timing_graph(b.h, V(nxt.ctypes.data), V(gd.ctypes.data), int(clock_fs)), "la_timing_graph")
+
+
+def la_sta(b: Batch, sink_delay, out_slack, out_crit) -> float:
+    """Static timing of the gate graph and critical-path counts (Alg. 1 lines 1-2); returns WNS."""
+    w = ctypes.c_float()
+    _chk(_load().la_sta(_on(b), _dev(sink_delay), _dev(out_slack), _dev(out_crit), ctypes.byref(w)), "la_sta")
+    return w.value
+
+
+def la_alg1_subsets(b: Batch, slack, crit, wns: float, out_subset) -> int:
+    """Alg. 1 lines 3-5: ordered subsets of the nets; returns their number."""
+    n = I32()
+    _chk(_load().la_alg1_subsets(_on(b), _dev(slack), _dev(crit), ctypes.c_float(wns), _dev(out_subset),
+                                 ctypes.byref(n)), "la_alg1_subsets")
     return n.value
 
 

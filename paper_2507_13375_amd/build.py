@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgapla.so")
-SOURCES = ["api.cpp", "build.cpp", "elmore.hip", "assign.hip", "batched.hip", "quality.hip", "batches.hip"]
+SOURCES = ["api.cpp", "build.cpp", "elmore.hip", "assign.hip", "batched.hip", "quality.hip", "batches.hip", "sta.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -209,6 +209,34 @@ la_status la_get_batches(la_batch *b, const int32_t *net_subset, int32_t num_sub
     return get_batches(b, net_subset, num_subsets, out_batch, num_batches);
 }
 
+la_status la_timing_graph(la_batch *b, const int32_t *sink_next, const int32_t *gate_delay_fs, int32_t clock_fs)
+{
+    if (!b || (b->sinks > 0 && !sink_next) || (b->nets > 0 && !gate_delay_fs))
+        return set_error(LA_ERR_INVALID_ARG, "la_timing_graph: NULL argument");
+    const la_status s = set_device(b);
+    if (s != LA_OK) return s;
+    return timing_graph(b, sink_next, gate_delay_fs, clock_fs);
+}
+
+la_status la_sta(la_batch *b, const float *sink_delay, float *out_slack, int32_t *out_crit, float *wns)
+{
+    if (!b || !wns || (b->sinks > 0 && (!sink_delay || !out_slack)) || (b->nets > 0 && !out_crit))
+        return set_error(LA_ERR_INVALID_ARG, "la_sta: NULL argument");
+    const la_status s = set_device(b);
+    if (s != LA_OK) return s;
+    return sta(b, sink_delay, out_slack, out_crit, wns);
+}
+
+la_status la_alg1_subsets(la_batch *b, const float *slack, const int32_t *crit, float wns, int32_t *out_subset,
+                          int32_t *num_subsets)
+{
+    if (!b || !num_subsets || (b->nets > 0 && (!slack || !crit || !out_subset)))
+        return set_error(LA_ERR_INVALID_ARG, "la_alg1_subsets: NULL argument");
+    const la_status s = set_device(b);
+    if (s != LA_OK) return s;
+    return alg1_subsets(b, slack, crit, wns, out_subset, num_subsets);
+}
+
 la_status la_get_tuning(const la_batch *b, la_tuning *out)
 {
     if (!b || !out) return set_error(LA_ERR_INVALID_ARG, "la_get_tuning: NULL argument");
@@ -414,7 +442,8 @@ void la_free_batch(la_batch *b)
                     b->F, b->S, b->bt, b->sel, b->bucket_nodes, b->bucket_cnt, b->bucket_cur,
                     b->chg_node, b->chg_count, b->chg_old, b->chg_new, b->lut, b->R, b->C, b->el_S,
                     b->el_Slo, b->el_t, b->el_tlo, b->el_G, b->el_Glo, b->el_Sig, b->el_Siglo, b->slack,
-                    b->scratch_f, b->wns_bits, b->red, b->net_big, b->net_zw, b->nrec, b->dynrec, b->cnet, b->bbox, b->batch_i32, b->bn_order, b->bn_lvl, b->bn_lvl_off,
+                    b->scratch_f, b->wns_bits, b->red, b->net_big, b->net_zw, b->nrec, b->dynrec, b->cnet, b->bbox, b->batch_i32, b->sta_next, b->sta_fin_ptr, b->sta_fin,
+                    b->sta_order, b->sta_gd, b->sta_f, b->sta_i, b->bn_order, b->bn_lvl, b->bn_lvl_off,
                     b->bn_nlev, b->tier_nets, b->tier_off, b->tier_cur, b->tier_cnt, b->claim,
                     b->cl_pre, b->cl_blk, b->cl_start, b->cl_off, b->D_alt, b->Hi,
                     b->e_tile, b->e_big_nodes, b->e_big_ptr, b->qofw, b->qpart};

@@ -510,6 +510,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->sink_id, sink_id));
     chk(upload(&b->sink_node, sink_node));
     chk(upload(&b->net_sink_ptr, net_sink_ptr));
+    b->h_net_sink_ptr = net_sink_ptr;
     chk(upload(&b->rest, rest));
     chk(upload(&b->budget_fs, budget));
     chk(upload(&b->rdrv, rdrv));

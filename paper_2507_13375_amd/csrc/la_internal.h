@@ -195,6 +195,17 @@ struct la_batch {
     int64_t cl_start_cap = 0;
     int32_t part_cap = 256;         // batches the partition and claim arrays hold
     int32_t *batch_i32 = nullptr;   // [nets] u8 batch indices widened for the kernels
+
+    // gate-level timing graph of Alg. 1 (la_timing_graph): per sink the net it feeds, the fan-in
+    // sinks of each net's gate, the nets in topological order (level starts on the host), gate
+    // delays (ps); work arrays of the timing (AD, RD per net, AS, RS per sink; latest input)
+    int32_t *sta_next = nullptr, *sta_fin_ptr = nullptr, *sta_fin = nullptr, *sta_order = nullptr;
+    float *sta_gd = nullptr, *sta_f = nullptr;
+    int32_t *sta_i = nullptr;
+    std::vector<int32_t> sta_lvl;
+    float sta_clock = 0.f;
+    bool sta_ready = false;
+    std::vector<int32_t> h_net_sink_ptr;   // [nets+1] host copy
     hipStream_t cap_stream = nullptr;
     // instantiated round graphs of the batched form by call key, most recently used first
     std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
@@ -285,6 +296,11 @@ la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history,
                        const int32_t *batch, bool use_cache);
 // the batch indices the forms read: the caller's int32 array, a widened copy of its u8 tiers, or NULL
 la_status batch_indices(la_batch *b, const la_weights *w, const int32_t **out);
+// Alg. 1 lines 1-5 on a gate graph over the nets (sta.hip)
+la_status timing_graph(la_batch *b, const int32_t *sink_next, const int32_t *gate_fs, int32_t clock_fs);
+la_status sta(la_batch *b, const float *delay, float *slack, int32_t *crit, float *wns_out);
+la_status alg1_subsets(la_batch *b, const float *slack, const int32_t *crit, float wns, int32_t *subset,
+                       int32_t *num_subsets);
 // the static scratch of the allocation-free entry point: its address on `device` (once per device)
 la_status scratch_setup(int device);
 la_status timing_summary_noalloc(la_batch *b, const float *delay, double *tns, double *wns);
