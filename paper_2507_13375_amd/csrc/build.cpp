@@ -351,16 +351,41 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
         for (int64_t v = 0; v < M; ++v) level_nodes[fill[height[v]]++] = (int32_t)v;
     }
 
-    // ---- Elmore tiles: runs of whole nets in canonical order, at most kETile nodes and
-    // heights below kEMaxH; the other nets' nodes grouped by height ------------------------
-    std::vector<int32_t> etile, ebig_ptr(max_h + 2, 0), ebig_nodes;
+    // ---- Elmore tiles: runs of whole nets in canonical order -- one wavefront's run of at
+    // most kWTile nodes for nets of at most kWTile nodes, one workgroup's run of at most kETile
+    // nodes (heights below kEMaxH) for the larger ones; the other nets' nodes grouped by height
+    std::vector<int32_t> etile, wtile, ebig_ptr(max_h + 2, 0), ebig_nodes;
     {
         std::vector<char> ebig(std::max<int32_t>(N, 1), 0);
-        int32_t t0 = -1, tn = 0;
+        int32_t t0 = -1, tn = 0, w0 = -1, wn = 0;
         for (int32_t i = 0; i < N; ++i) {
             const int32_t b0 = net_ptr[i], n = net_ptr[i + 1] - b0;
             int32_t hm = 0;
             for (int32_t v = b0; v < b0 + n; ++v) hm = std::max(hm, height[v]);
+            // a run is a contiguous node range: a net of the other class closes it
+            if (n <= kWTile) {
+                if (t0 >= 0) {
+                    etile.push_back(t0);
+                    etile.push_back(t0 + tn);
+                    t0 = -1;
+                    tn = 0;
+                }
+                if (w0 >= 0 && wn + n > kWTile) {
+                    wtile.push_back(w0);
+                    wtile.push_back(w0 + wn);
+                    w0 = -1;
+                    wn = 0;
+                }
+                if (w0 < 0) w0 = b0;
+                wn += n;
+                continue;
+            }
+            if (w0 >= 0) {
+                wtile.push_back(w0);
+                wtile.push_back(w0 + wn);
+                w0 = -1;
+                wn = 0;
+            }
             const bool big = n > kETile || hm >= kEMaxH;
             if (t0 >= 0 && (big || tn + n > kETile)) {
                 etile.push_back(t0);
@@ -379,6 +404,10 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
         if (t0 >= 0) {
             etile.push_back(t0);
             etile.push_back(t0 + tn);
+        }
+        if (w0 >= 0) {
+            wtile.push_back(w0);
+            wtile.push_back(w0 + wn);
         }
         for (int h = 0; h <= max_h; ++h) ebig_ptr[h + 1] += ebig_ptr[h];
         ebig_nodes.resize(std::max<int32_t>(ebig_ptr[max_h + 1], 1));
@@ -471,6 +500,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     b->h_level_ptr = level_ptr;
     b->h_ebig_ptr = ebig_ptr;
     b->e_ntiles = (int32_t)(etile.size() / 2);
+    b->e_nwtiles = (int32_t)(wtile.size() / 2);
     b->h_net_ptr = net_ptr;
     b->h_bbox.resize((size_t)4 * N);
     for (int32_t i = 0; i < N; ++i) {
@@ -519,6 +549,13 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->level_nodes, level_nodes));
     chk(upload(&b->level_ptr, level_ptr));
     chk(upload(&b->e_tile, etile));
+    chk(upload(&b->e_wtile, wtile));
+    {
+        // pin loads in fF as single precision, rounded once from the exact product
+        std::vector<float> cf(std::max<int64_t>(M, 1), 0.f);
+        for (int64_t v = 0; v < M; ++v) cf[v] = (float)((double)cpin[v] * 1e-3);
+        chk(upload(&b->cpin_ff, cf));
+    }
     chk(upload(&b->e_big_nodes, ebig_nodes));
     chk(upload(&b->e_big_ptr, ebig_ptr));
     chk(upload(&b->height, height));

@@ -135,7 +135,7 @@ __device__ __forceinline__ void elm_up(const TreeDev &T, int32_t v, const float 
     const int32_t k = T.sink_id[v];
     if (k >= 0) {
         s = ff_add(s, C[T.nodes + k]);
-        s = ff_add(s, (float)((double)T.cpin[v] * 1e-3));
+        s = ff_add(s, T.cpin_ff[v]);
     }
     for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) {
         const int32_t c = T.ch[q];
@@ -159,7 +159,7 @@ __device__ __forceinline__ void elm_down(const TreeDev &T, int32_t v, const floa
     const int32_t k = T.sink_id[v];
     if (k >= 0) {
         const int64_t e = T.nodes + k;
-        ff pl = ff_add(ff{0.5f * C[e], 0.f}, (float)((double)T.cpin[v] * 1e-3));
+        ff pl = ff_add(ff{0.5f * C[e], 0.f}, T.cpin_ff[v]);
         delay[k] = ff_val(ff_add(tv, ff_mul(R[e], pl)));
     }
 }
@@ -199,7 +199,7 @@ __device__ __forceinline__ void adj_down(const TreeDev &T, int32_t v, const floa
     if (k >= 0) {
         const int64_t e = T.nodes + k;
         const float gk = gbar[k];
-        if (dR) dR[e] = gk * (0.5f * C[e] + (float)((double)T.cpin[v] * 1e-3));
+        if (dR) dR[e] = gk * (0.5f * C[e] + T.cpin_ff[v]);
         if (dC) dC[e] = ff_val(ff_add(sv, 0.5f * R[e] * gk));
     }
 }
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(kEThreads) k_elmore_tiles(TreeDev T, const int
                 const int32_t k = T.sink_id[v];
                 if (k >= 0) {
                     x = ff_add(x, C[T.nodes + k]);
-                    x = ff_add(x, (float)((double)T.cpin[v] * 1e-3));
+                    x = ff_add(x, T.cpin_ff[v]);
                 }
                 for (int32_t q = T.ch_ptr[v]; q < T.ch_ptr[v + 1]; ++q) {
                     const int32_t c = T.ch[q], cu = c - n0;
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(kEThreads) k_elmore_tiles(TreeDev T, const int
                 const int32_t k = T.sink_id[v];
                 if (k >= 0) {
                     const int64_t e = T.nodes + k;
-                    const ff pl = ff_add(ff{0.5f * C[e], 0.f}, (float)((double)T.cpin[v] * 1e-3));
+                    const ff pl = ff_add(ff{0.5f * C[e], 0.f}, T.cpin_ff[v]);
                     delay[k] = ff_val(ff_add(tv, ff_mul(R[e], pl)));
                 }
             }
@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(kEThreads) k_adj_tiles(TreeDev T, const int32_
                 if (k >= 0) {
                     const int64_t e = T.nodes + k;
                     const float gk = gbar[k];
-                    if (dR) dR[e] = gk * (0.5f * C[e] + (float)((double)T.cpin[v] * 1e-3));
+                    if (dR) dR[e] = gk * (0.5f * C[e] + T.cpin_ff[v]);
                     if (dC) dC[e] = ff_val(ff_add(sv, 0.5f * R[e] * gk));
                 }
             }
@@ -439,6 +439,246 @@ __global__ void __launch_bounds__(kEThreads) k_edge_w_tiles(TreeDev T, const int
         }
         for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) seg_w[n0 + u] = wl[u];
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront runs: the nets of at most kWTile nodes, a run of whole nets per one-wavefront
+// workgroup.  Lane i keeps nodes i, i + 64, i + 128 and i + 192 of the run in registers (their
+// records are read coalesced, once), the child lists as run-local ids and the sweep state sit in
+// LDS, and each level costs one barrier of a single wavefront.  Per node the operations are those
+// of the per-level kernels, in the same order.
+// ---------------------------------------------------------------------------
+constexpr int kWPer = kWTile / 64;
+
+__device__ __forceinline__ int32_t wave_max(int32_t x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
+    return x;
+}
+
+struct WaveRun {
+    int32_t n0, nn, maxh;
+    int32_t hgt[kWPer];   // height, -1 past the run's end
+    int32_t par[kWPer];   // run-local parent, -1 at the root
+    int32_t sk[kWPer];    // sink id or -1
+    int32_t c0[kWPer], c1[kWPer];   // child entries [c0, c1) of the run-local child list
+};
+
+// The run's node records into lane slots, its child list into `chl` (run-local ids).
+__device__ __forceinline__ void wave_run_load(const TreeDev &T, const int32_t *height, const int32_t *runs,
+                                              int32_t ri, WaveRun &w, int16_t *chl)
+{
+    const int lane = threadIdx.x;
+    w.n0 = runs[2 * ri];
+    w.nn = runs[2 * ri + 1] - w.n0;
+    const int32_t q0 = T.ch_ptr[w.n0], nq = T.ch_ptr[w.n0 + w.nn] - q0;
+    int32_t mh = 0;
+#pragma unroll
+    for (int j = 0; j < kWPer; ++j) {
+        const int32_t u = lane + 64 * j, v = w.n0 + u;
+        w.hgt[j] = -1;
+        w.par[j] = -1;
+        w.sk[j] = -1;
+        w.c0[j] = w.c1[j] = 0;
+        if (u < w.nn) {
+            w.hgt[j] = height[v];
+            const int32_t p = T.parent[v];
+            w.par[j] = p < 0 ? -1 : p - w.n0;
+            w.sk[j] = T.sink_id[v];
+            w.c0[j] = T.ch_ptr[v] - q0;
+            w.c1[j] = T.ch_ptr[v + 1] - q0;
+            mh = max(mh, w.hgt[j]);
+        }
+    }
+    for (int32_t i = lane; i < nq; i += 64) chl[i] = (int16_t)(T.ch[q0 + i] - w.n0);
+    w.maxh = wave_max(mh);
+}
+
+__global__ void __launch_bounds__(64) k_elmore_wave(TreeDev T, const int32_t *runs, int32_t nruns,
+                                                    const int32_t *height, const float *R, const float *C, float *S,
+                                                    float *Slo, float *delay)
+{
+    __shared__ float cc[kWTile], sh[kWTile], sl[kWTile], th[kWTile], tl[kWTile];
+    __shared__ int16_t chl[kWTile];
+    const int lane = threadIdx.x;
+    for (int32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
+        WaveRun w;
+        wave_run_load(T, height, runs, ri, w, chl);
+        float r[kWPer], c[kWPer], ce[kWPer], re[kWPer], cp[kWPer], xh[kWPer], xl[kWPer];
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) {
+            const int32_t u = lane + 64 * j, v = w.n0 + u;
+            r[j] = c[j] = ce[j] = re[j] = cp[j] = xh[j] = xl[j] = 0.f;
+            if (u < w.nn) {
+                r[j] = R[v];
+                c[j] = C[v];
+                cc[u] = c[j];
+                if (w.sk[j] >= 0) {
+                    ce[j] = C[T.nodes + w.sk[j]];
+                    re[j] = R[T.nodes + w.sk[j]];
+                    cp[j] = T.cpin_ff[v];
+                }
+            }
+        }
+        __syncthreads();
+        // S(v) = sum over RC children of (C + S), bottom-up
+        for (int32_t h = 0; h <= w.maxh; ++h) {
+#pragma unroll
+            for (int j = 0; j < kWPer; ++j) {
+                if (w.hgt[j] != h) continue;
+                const int32_t u = lane + 64 * j;
+                ff x{0.f, 0.f};
+                if (w.sk[j] >= 0) {
+                    x = ff_add(x, ce[j]);
+                    x = ff_add(x, cp[j]);
+                }
+                for (int32_t q = w.c0[j]; q < w.c1[j]; ++q) {
+                    const int32_t cu = chl[q];
+                    x = ff_add(x, cc[cu]);
+                    x = ff_add(x, ff{sh[cu], sl[cu]});
+                }
+                x = ff_norm(x);
+                sh[u] = xh[j] = x.hi;
+                sl[u] = xl[j] = x.lo;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) {
+            const int32_t u = lane + 64 * j;
+            if (u < w.nn) {
+                S[w.n0 + u] = xh[j];
+                Slo[w.n0 + u] = xl[j];
+            }
+        }
+        // t(v) = t(parent) + R_v (C_v/2 + S_v), top-down; delay at sink pins
+        for (int32_t h = w.maxh; h >= 0; --h) {
+#pragma unroll
+            for (int j = 0; j < kWPer; ++j) {
+                if (w.hgt[j] != h) continue;
+                const int32_t u = lane + 64 * j, p = w.par[j];
+                const ff up = p < 0 ? ff{0.f, 0.f} : ff{th[p], tl[p]};
+                const ff load = ff_add(ff{xh[j], xl[j]}, 0.5f * c[j]);
+                const ff tv = ff_norm(ff_add(up, ff_mul(r[j], load)));
+                th[u] = tv.hi;
+                tl[u] = tv.lo;
+                if (w.sk[j] >= 0) {
+                    const ff pl = ff_add(ff{0.5f * ce[j], 0.f}, cp[j]);
+                    delay[w.sk[j]] = ff_val(ff_add(tv, ff_mul(re[j], pl)));
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) k_adj_wave(TreeDev T, const int32_t *runs, int32_t nruns,
+                                                 const int32_t *height, const float *R, const float *C,
+                                                 const float *S, const float *Slo, const float *gbar, float *G,
+                                                 float *Glo, float *Sig, float *Siglo, float *dR, float *dC)
+{
+    __shared__ float gh[kWTile], gl[kWTile], qh[kWTile], ql[kWTile];
+    __shared__ int16_t chl[kWTile];
+    const int lane = threadIdx.x;
+    const bool grads = dR != nullptr || dC != nullptr;
+    for (int32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
+        WaveRun w;
+        wave_run_load(T, height, runs, ri, w, chl);
+        float r[kWPer], gk[kWPer], xh[kWPer], xl[kWPer];
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) {
+            const int32_t u = lane + 64 * j;
+            r[j] = gk[j] = xh[j] = xl[j] = 0.f;
+            if (u < w.nn) {
+                r[j] = R[w.n0 + u];
+                if (w.sk[j] >= 0) gk[j] = gbar[w.sk[j]];
+            }
+        }
+        __syncthreads();
+        // G(v) = sum of g below v, bottom-up
+        for (int32_t h = 0; h <= w.maxh; ++h) {
+#pragma unroll
+            for (int j = 0; j < kWPer; ++j) {
+                if (w.hgt[j] != h) continue;
+                const int32_t u = lane + 64 * j;
+                ff g{0.f, 0.f};
+                if (w.sk[j] >= 0) g = ff_add(g, gk[j]);
+                for (int32_t q = w.c0[j]; q < w.c1[j]; ++q) {
+                    const int32_t cu = chl[q];
+                    g = ff_add(g, ff{gh[cu], gl[cu]});
+                }
+                g = ff_norm(g);
+                gh[u] = xh[j] = g.hi;
+                gl[u] = xl[j] = g.lo;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) {
+            const int32_t u = lane + 64 * j;
+            if (u < w.nn) {
+                G[w.n0 + u] = xh[j];
+                Glo[w.n0 + u] = xl[j];
+            }
+        }
+        // Sig(v) = Sig(parent) + R_v G(v), top-down, and the R / C gradients
+        for (int32_t h = w.maxh; h >= 0; --h) {
+#pragma unroll
+            for (int j = 0; j < kWPer; ++j) {
+                if (w.hgt[j] != h) continue;
+                const int32_t u = lane + 64 * j, v = w.n0 + u, p = w.par[j];
+                const ff up = p < 0 ? ff{0.f, 0.f} : ff{qh[p], ql[p]};
+                const ff g{xh[j], xl[j]};
+                const ff sv = ff_norm(ff_add(up, ff_mul(r[j], g)));
+                qh[u] = sv.hi;
+                ql[u] = sv.lo;
+                Sig[v] = sv.hi;
+                Siglo[v] = sv.lo;
+                if (grads) {
+                    const float cv = C[v];
+                    if (dR) dR[v] = ff_val(ff_mul(ff_val(g), ff_add(ff{S[v], Slo[v]}, 0.5f * cv)));
+                    if (dC) dC[v] = ff_val(ff_add(up, 0.5f * r[j] * ff_val(g)));
+                    const int32_t k = w.sk[j];
+                    if (k >= 0) {
+                        const int64_t e = T.nodes + k;
+                        if (dR) dR[e] = gk[j] * (0.5f * C[e] + T.cpin_ff[v]);
+                        if (dC) dC[e] = ff_val(ff_add(sv, 0.5f * R[e] * gk[j]));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Eq. 5 on the wavefront runs: the largest pin weight below each segment, bottom-up in LDS
+__global__ void __launch_bounds__(64) k_edge_w_wave(TreeDev T, const int32_t *runs, int32_t nruns,
+                                                    const int32_t *height, const uint16_t *pin_w, uint16_t *seg_w)
+{
+    __shared__ uint16_t wl[kWTile];
+    __shared__ int16_t chl[kWTile];
+    const int lane = threadIdx.x;
+    for (int32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
+        WaveRun w;
+        wave_run_load(T, height, runs, ri, w, chl);
+        uint16_t x[kWPer];
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) x[j] = w.sk[j] >= 0 ? pin_w[w.sk[j]] : 0;
+        __syncthreads();
+        for (int32_t h = 0; h <= w.maxh; ++h) {
+#pragma unroll
+            for (int j = 0; j < kWPer; ++j) {
+                if (w.hgt[j] != h) continue;
+                uint16_t m = x[j];
+                for (int32_t q = w.c0[j]; q < w.c1[j]; ++q) m = max(m, wl[chl[q]]);
+                wl[lane + 64 * j] = x[j] = m;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j)
+            if (lane + 64 * j < w.nn) seg_w[w.n0 + lane + 64 * j] = x[j];
     }
 }
 
@@ -635,6 +875,7 @@ TreeDev tree_view(const la_batch *b)
     t.dir = b->dir;
     t.flags = b->flags;
     t.cpin = b->cpin;
+    t.cpin_ff = b->cpin_ff;
     t.sink_id = b->sink_id;
     t.sink_node = b->sink_node;
     t.net_sink_ptr = b->net_sink_ptr;
@@ -719,11 +960,17 @@ static LevelList untiled_levels(const la_batch *b) { return LevelList{&b->h_ebig
 
 // workgroups of the tile kernels: 8 per CU of a 256-CU part (the loop over tiles strides by it)
 static int tile_grid(const la_batch *b) { return std::max(1, std::min<int>(b->e_ntiles, 2048)); }
+// one-wavefront workgroups of the wavefront-run kernels: up to 32 per CU (the loop strides by it)
+static int wave_grid(const la_batch *b) { return std::max(1, std::min<int>(b->e_nwtiles, 8192)); }
 
 la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay)
 {
     const TreeDev T = tree_view(b);
-    // nets in tiles: one launch; the others level by level
+    // small nets in wavefront runs, the larger ones in workgroup tiles, the others level by level
+    if (b->e_nwtiles > 0)
+        LA_TIMED(b, "k_elmore_wave", b->stream,
+                 hipLaunchKernelGGL(k_elmore_wave, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, b->e_wtile,
+                                    b->e_nwtiles, b->height, R, C, b->el_S, b->el_Slo, delay));
     if (b->e_ntiles > 0)
         LA_TIMED(b, "k_elmore_tiles", b->stream,
                  hipLaunchKernelGGL(k_elmore_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T, b->e_tile,
@@ -758,6 +1005,11 @@ la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *
         gbar = b->scratch_f;
     }
     float *Glo = b->el_Glo, *Siglo = b->el_Siglo;
+    if (b->e_nwtiles > 0)
+        LA_TIMED(b, "k_adj_wave", b->stream,
+                 hipLaunchKernelGGL(k_adj_wave, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, b->e_wtile,
+                                    b->e_nwtiles, b->height, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, gbar, b->el_G,
+                                    Glo, b->el_Sig, Siglo, dR, dC));
     if (b->e_ntiles > 0)
         LA_TIMED(b, "k_adj_tiles", b->stream,
                  hipLaunchKernelGGL(k_adj_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T, b->e_tile,
@@ -793,6 +1045,10 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
              hipLaunchKernelGGL(k_tiers, dim3(grid_for(b->nets)), dim3(kBlock), 0, b->stream, T, b->slack,
                                 b->wns_bits, tier));
     if (mode == LA_WEIGHTS_PLAIN) {
+        if (b->e_nwtiles > 0)
+            LA_TIMED(b, "k_edge_w_wave", b->stream,
+                     hipLaunchKernelGGL(k_edge_w_wave, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, b->e_wtile,
+                                        b->e_nwtiles, b->height, pin_w, seg_w));
         if (b->e_ntiles > 0)
             LA_TIMED(b, "k_edge_w_tiles", b->stream,
                      hipLaunchKernelGGL(k_edge_w_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T,

@@ -17,6 +17,7 @@ constexpr int kQPartials = 2048 * 5;   // quality report: workgroups x partial s
 constexpr int kQSpan = 64;             // quality report: e^{s x} tabulated for integer x in [-kQSpan, kQSpan]
 constexpr int kETile = 1024;        // nodes of one Elmore tile (whole nets, swept in one workgroup)
 constexpr int kEMaxH = 128;         // tree heights an Elmore tile handles
+constexpr int kWTile = 256;         // nodes of one wavefront's Elmore run (nets of at most that many nodes)
 constexpr int kCap = 192;          // default nodes of one batched-form workgroup's LDS tile
 constexpr int kTileCaps[3] = {128, 192, 256};   // tile sizes the batched form is built for
 constexpr int kBigMin = 128;       // smallest tile: nets above it get their own level lists
@@ -110,6 +111,7 @@ struct TreeDev {
     const uint8_t *dir;             // 0 H, 1 V (root: 0)
     const uint8_t *flags;
     const int32_t *cpin;            // aF, sinks only
+    const float *cpin_ff;           // the same in fF, single precision (rounded once)
     const int32_t *sink_id;         // node -> sink or -1
     const int32_t *sink_node;       // [sinks]
     const int32_t *net_sink_ptr;    // [nets+1] sinks of a net are contiguous
@@ -139,6 +141,9 @@ struct la_batch {
     // the nets no tile takes
     int32_t *e_tile = nullptr, *e_big_nodes = nullptr, *e_big_ptr = nullptr;
     int32_t e_ntiles = 0;
+    int32_t *e_wtile = nullptr;         // wavefront runs ([start, end) pairs) of the nets of <= kWTile nodes
+    int32_t e_nwtiles = 0;
+    float *cpin_ff = nullptr;           // [nodes] pin load in fF (float)
     std::vector<int32_t> h_ebig_ptr;    // [levels+1]
     std::vector<int32_t> h_net_ptr;
     std::vector<int16_t> h_bbox;        // [nets][4] x min, x max, y min, y max of the net's nodes

@@ -202,23 +202,27 @@ def _heights(T):
     return h
 
 
-def test_untiled_nets_elmore_adjoint_and_eq5():
-    # nets of more than 1024 layer-assignment nodes, or of height 128 or more, do not fit an
-    # Elmore tile: their sweeps run in the per-level kernels (one launch per dense level, one
-    # workgroup over the sparse top levels).  Forward, reverse sweep and Eq. 5 weights of those
-    # nets against the FP64 oracle.
-    inst = gen.generate(240, 256, 256, 10, 23, pin_law=1, pin_max=16, placement=2, fanout_every=40,
-                        fanout_min=1000, fanout_max=1600, cap_min=4, cap_max=10, budget_min_fs=-400000,
-                        budget_max_fs=-100000)
+@pytest.mark.parametrize("kind", ["untiled", "tiles"])
+def test_large_nets_elmore_adjoint_and_eq5(kind):
+    # Nets of at most 256 layer-assignment nodes take the one-wavefront runs; nets of up to 1024
+    # nodes and height below 128 the workgroup tiles; the others (more than 1024 nodes or height
+    # 128 or more) the per-level kernels (one launch per dense level, one workgroup over the sparse
+    # top levels).  Each instance mixes wavefront-run nets with nets of one of the other two
+    # classes.  Forward, reverse sweep and Eq. 5 weights against the FP64 oracle.
+    fan = dict(untiled=dict(fanout_every=40, fanout_min=1000, fanout_max=1600),
+               tiles=dict(fanout_every=12, fanout_min=120, fanout_max=400))[kind]
+    inst = gen.generate(240, 256, 256, 10, 23, pin_law=1, pin_max=16, placement=2, cap_min=4, cap_max=10,
+                        budget_min_fs=-400000, budget_max_fs=-100000, **fan)
     T = oracle.Tree(inst)
     sizes = np.diff(T.net_ptr)
     h = _heights(T)
     net_h = np.zeros(T.nets, np.int64)
     np.maximum.at(net_h, np.searchsorted(T.net_ptr, np.arange(T.nodes), side="right") - 1, h)
     untiled = (sizes > 1024) | (net_h >= 128)
-    say("untiled nets: %d of %d (largest %d nodes, tallest %d levels)" % (untiled.sum(), T.nets, sizes.max(),
-                                                                          net_h.max() + 1))
-    assert untiled.sum() >= 3
+    tiled = ~untiled & (sizes > 256)
+    say("%s: %d untiled, %d tile, %d wavefront-run nets (largest %d nodes, tallest %d levels)" % (
+        kind, untiled.sum(), tiled.sum(), T.nets - untiled.sum() - tiled.sum(), sizes.max(), net_h.max() + 1))
+    assert (untiled if kind == "untiled" else tiled).sum() >= 3 and (sizes <= 256).sum() >= 100
     P = oracle.Params(T)
     R, C = oracle.rc(T, P, None)
     S, t, d = oracle.elmore(T, R, C)
@@ -236,7 +240,8 @@ def test_untiled_nets_elmore_adjoint_and_eq5():
     net_of = _net_of(T)
     for name, gpu, ref in (("dR", host(dRg), dR), ("dC", host(dCg), dC)):
         ok = _adjoint_tol(gpu, ref, net_of)
-        assert ok.all(), "%s: %d bad (%d in untiled nets)" % (name, (~ok).sum(), (~ok & untiled[net_of]).sum())
+        assert ok.all(), "%s: %d bad (%d in untiled nets, %d in tile nets)" % (
+            name, (~ok).sum(), (~ok & untiled[net_of]).sum(), (~ok & tiled[net_of]).sum())
     # plain weights: Eq. 5 over the untiled nets' levels
     w = oracle.plain_weights(T, P)
     d2 = g.elmore()
@@ -256,7 +261,7 @@ def test_untiled_nets_elmore_adjoint_and_eq5():
     bad_net[sink_net[pwg != w["pin_w"]]] = True
     exact = ~bad_net[net_of[:T.nodes]]
     assert (swg[exact] == w["seg_w"][exact]).all() and (lg[exact] == w["lam"][exact]).all()
-    say("untiled Eq. 5: %d of %d nodes in nets with identical pin weights" % (exact.sum(), T.nodes))
+    say("%s Eq. 5: %d of %d nodes in nets with identical pin weights" % (kind, exact.sum(), T.nodes))
 
 
 def test_backward_after_reassignment_is_state_error(c1):
