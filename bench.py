@@ -165,6 +165,8 @@ def main():
             ablations[vname] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in q.items()}
             ablations[vname]["wall_s"] = round(time.time() - t0, 3)
             log("ablation %-12s %s" % (vname, ablations[vname]))
+        ablations["alg1_order"] = alg1_step(la, b, inst, delay, sw, pw, lam, tier, H, layers)
+        log("ablation alg1_order   %s" % ablations["alg1_order"])
 
     main_form = "batched" if "batched" in results else "plain"
     cpu = None
@@ -211,6 +213,48 @@ def main():
         out["batched_over_plain_same_weights"] = (results["batched_plainw"]["nets_per_s"] /
                                                   results["plain"]["nets_per_s"])
     print(json.dumps(out), flush=True)
+
+
+def alg1_step(la, b, inst, delay, sw, pw, lam, tier, H, layers):
+    """The paper's whole ordering flow (Alg. 1) in place of the slack bins and net-id batches:
+    per iteration, static timing of a synthetic gate graph over the nets with the current sink
+    delays, top-1 critical-path counts, the ordered subsets and their classical batches, then
+    R rounds on those batches (adjoint-form weights); quality terms of the result and the time
+    of the ordering calls (STA + subsets + batching) beside the whole step."""
+    import gen
+    import torch
+
+    tg = gen.timing_graph(inst)
+    la.la_timing_graph(b, tg["sink_next"], tg["gate_delay_fs"], tg["clock_fs"])
+    slack = torch.empty(b.sinks, dtype=torch.float32, device="cuda")
+    crit = torch.empty(b.nets, dtype=torch.int32, device="cuda")
+    sub = torch.empty(b.nets, dtype=torch.int32, device="cuda")
+    bat = torch.empty(b.nets, dtype=torch.int32, device="cuda")
+    t0 = time.time()
+    t_order = 0.0
+    batches = []
+    la.la_reset(b)
+    H.zero_()
+    for _ in range(I_ITERS):
+        la.la_elmore(b, delay)
+        la.la_timing_weights(b, delay, la.LA_WEIGHTS_ADJOINT, sw, pw, lam, tier)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        wns = la.la_sta(b, delay, slack, crit)
+        nsub = la.la_alg1_subsets(b, slack, crit, wns, sub)
+        nb = la.la_get_batches(b, sub, nsub, bat)
+        torch.cuda.synchronize()
+        t_order += time.time() - t1
+        batches.append(nb)
+        la.la_assign(b, sw, pw, lam, H, layers, num_tiers=nb, rounds=R_ROUNDS, form=la.LA_FORM_BATCHED,
+                     net_batch=bat)
+    la.la_elmore(b, delay)
+    q = la.la_quality_report(b, delay=delay, weights=SCORE_WEIGHTS)
+    torch.cuda.synchronize()
+    out = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in q.items()}
+    out.update(wall_s=round(time.time() - t0, 3), ordering_s=round(t_order, 3), batches=batches,
+               critical_nets=int((crit > 3).sum().item()))
+    return out
 
 
 KERNEL_SOURCES = ("batched.hip", "dp_device.h", "la_internal.h")
@@ -287,7 +331,7 @@ def quality_rate(b, inst, q, kernels):
 
 def elmore_rate(b, kernels):
     """Algorithmic HBM rate of the Elmore forward sweeps (28 B per RC edge per sweep)."""
-    names = ("k_elmore_tiles", "k_elmore_up", "k_elmore_down")   # tiles, and untiled nets by level
+    names = ("k_elmore_wave", "k_elmore_tiles", "k_elmore_up", "k_elmore_down")   # runs, tiles, untiled nets
     if not any(k in kernels for k in names):
         return None
     sweeps = I_ITERS + 1

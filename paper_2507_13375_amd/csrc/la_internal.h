@@ -17,7 +17,7 @@ constexpr int kQPartials = 2048 * 5;   // quality report: workgroups x partial s
 constexpr int kQSpan = 64;             // quality report: e^{s x} tabulated for integer x in [-kQSpan, kQSpan]
 constexpr int kETile = 1024;        // nodes of one Elmore tile (whole nets, swept in one workgroup)
 constexpr int kEMaxH = 128;         // tree heights an Elmore tile handles
-constexpr int kWTile = 256;         // nodes of one wavefront's Elmore run (nets of at most that many nodes)
+constexpr int kWTile = 128;         // nodes of one wavefront's Elmore run (nets of at most that many nodes)
 constexpr int kCap = 192;          // default nodes of one batched-form workgroup's LDS tile
 constexpr int kTileCaps[3] = {128, 192, 256};   // tile sizes the batched form is built for
 constexpr int kBigMin = 128;       // smallest tile: nets above it get their own level lists
