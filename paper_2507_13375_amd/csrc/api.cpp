@@ -451,6 +451,9 @@ void la_free_batch(la_batch *b)
         if (p) (void)hipFree(p);
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     delete b;
 }
 

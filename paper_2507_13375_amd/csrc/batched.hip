@@ -822,10 +822,20 @@ la_status launch_tiles(la_batch *b, const DPArgs &a, const BArgs &ba, hipStream_
 la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t nbig, int32_t nsmall, hipStream_t s)
 {
     const int NA = b->NAmax, cap = b->tune.tile_nodes;
+    // The big nets (a workgroup each, walking tall trees level by level) run beside the tile
+    // kernel on a second stream, joined before the batch's commit: both read the demand map as
+    // it was before the batch and append to one change list.
+    const bool fork = nbig > 0 && nsmall > 0;
+    hipStream_t sb = s;
+    if (fork) {
+        LA_HIP(hipEventRecord(b->ev_fork, s));
+        LA_HIP(hipStreamWaitEvent(b->side_stream, b->ev_fork, 0));
+        sb = b->side_stream;
+    }
     if (nbig > 0) {
         auto big = NA <= 4 ? k_batched_big<4> : (NA <= 6 ? k_batched_big<6> : k_batched_big<8>);
-        LA_TIMED(b, "k_batched_big", s,
-                 hipLaunchKernelGGL(big, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, s, a, ba));
+        LA_TIMED(b, "k_batched_big", sb,
+                 hipLaunchKernelGGL(big, dim3(std::min(nbig, 4096)), dim3(kThreads), 0, sb, a, ba));
     }
     if (nsmall > 0) {
         la_status st = LA_OK;
@@ -835,6 +845,10 @@ la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t 
                             : (cap == 256 ? launch_tiles<6, 256>(b, a, ba, s) : launch_tiles<6, kCap>(b, a, ba, s));
         else st = launch_tiles<8, kCap>(b, a, ba, s);
         if (st != LA_OK) return st;
+    }
+    if (fork) {
+        LA_HIP(hipEventRecord(b->ev_join, sb));
+        LA_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
     }
     LA_HIP(hipGetLastError());
     return LA_OK;
@@ -1054,6 +1068,9 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
         }
     }
 
+    if (!b->side_stream) LA_HIP(hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking));
+    if (!b->ev_fork) LA_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    if (!b->ev_join) LA_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
     // the rounds, as one graph: per batch the persistent DP, then the commit; history per round.
     // While kernels are being timed the same launches go straight to the batch's stream.
     if (b->prof_on || direct) {

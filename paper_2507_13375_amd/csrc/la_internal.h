@@ -212,6 +212,9 @@ struct la_batch {
     bool sta_ready = false;
     std::vector<int32_t> h_net_sink_ptr;   // [nets+1] host copy
     hipStream_t cap_stream = nullptr;
+    // the big nets' DP kernel runs on its own stream beside the tile kernel, forked and joined by events
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // instantiated round graphs of the batched form by call key, most recently used first
     std::vector<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
     int64_t graph_instantiations = 0;
