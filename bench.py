@@ -195,7 +195,7 @@ def main():
                    "nets": inst.num_nets, "la_nodes": b.nodes, "rounds": R_ROUNDS, "iterations": I_ITERS,
                    "form": main_form, "tuning": tuning},
         "forms": {k: {"nets_per_s": v["nets_per_s"], "ms_per_step": v["ms"], "tns_ps": v["tns"], "wns_ps": v["wns"],
-                      "roofline": roof[k], "elmore": elmore_rate(b, v["kernels"]),
+                      "roofline": roof[k], "elmore": elmore_rate(b, v["kernels"], digest),
                       "graph_instantiations_in_timed_steps": v["graphs_timed"],
                       "kernel_ms_per_step": {n: round(t, 4) for n, (c, t) in v["kernels"].items()}}
                   for k, v in results.items()},
@@ -257,32 +257,40 @@ def alg1_step(la, b, inst, delay, sw, pw, lam, tier, H, layers):
     return out
 
 
-KERNEL_SOURCES = ("batched.hip", "dp_device.h", "la_internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batched_dp_c4_2M_traffic.md")
+# the sources each measured kernel is built from (its traffic figure holds for these only)
+KERNEL_SOURCES = {
+    "k_batched_dp": ("batched.hip", "dp_device.h", "la_internal.h"),
+    "k_elmore_wave": ("elmore.hip", "la_internal.h"),
+    "k_adj_wave": ("elmore.hip", "la_internal.h"),
+}
 
 
-def kernel_sources_sha256():
-    """Hash of the sources of the batched DP kernel (the traffic figures hold for these only)."""
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", "%s_c4_2M_traffic.md" % kernel)
+
+
+def kernel_sources_sha256(kernel="k_batched_dp"):
+    """Hash of the sources of a kernel (the traffic figures hold for these only)."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2507_13375_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload_digest):
-    """HBM bytes per k_batched_dp launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
+def measured_traffic(workload_digest, kernel="k_batched_dp"):
+    """HBM bytes per launch of `kernel` from its committed FETCH_SIZE/WRITE_SIZE summary, or None
     when it is missing, was taken on other kernel sources, or on another workload (the figure is
     per launch of one instance: its digest must match)."""
     try:
         vals = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(kernel)) as fh:
             for line in fh:
                 if ":" in line and not line.startswith(("|", "#", "`")):
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
-        if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        if vals.get("kernel_sources_sha256") != kernel_sources_sha256(kernel):
             return None
         if vals.get("workload_digest") != workload_digest:
             return None
@@ -307,9 +315,14 @@ def roofline(b, form, kernels, workload_digest):
     ops_round = b.dp_ops_per_round - (b.dp_ops_big_per_round if batched else 0.0)
     ops = ops_round * R_ROUNDS * I_ITERS
     achieved = ops / (ms * 1e-3) / 1e12
+    # the same launches against HBM: the algorithmic bytes (per node and per GCell edge and
+    # layer of its segment) over the launch time
+    alg_bytes = b.dp_bytes_per_round * R_ROUNDS * I_ITERS / n
+    hbm_gbs = alg_bytes / (ms / n * 1e-3) / 1e9
     return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
             "frac": achieved / ALU_PEAK_TOPS, "traffic": measured_traffic(workload_digest) if form == "batched" else None,
-            "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": b.dp_bytes_per_round * R_ROUNDS * I_ITERS / n,
+            "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": alg_bytes,
+            "hbm": {"achieved": hbm_gbs, "peak": 8000.0, "unit": "GB/s", "frac": hbm_gbs / 8000.0},
             "launches": n, "avg_launch_us": 1e3 * ms / n, "ops_per_launch": ops / n}
 
 
@@ -329,16 +342,28 @@ def quality_rate(b, inst, q, kernels):
     return out
 
 
-def elmore_rate(b, kernels):
-    """Algorithmic HBM rate of the Elmore forward sweeps (28 B per RC edge per sweep)."""
+def elmore_rate(b, kernels, workload_digest=None):
+    """Algorithmic HBM rate of the Elmore forward sweeps (28 B per RC edge per sweep) and of the
+    reverse sweeps of the adjoint weights (40 B per RC edge), with the measured traffic of the
+    wavefront-run kernels that take the small nets, where a summary for these sources exists."""
     names = ("k_elmore_wave", "k_elmore_tiles", "k_elmore_up", "k_elmore_down")   # runs, tiles, untiled nets
     if not any(k in kernels for k in names):
         return None
     sweeps = I_ITERS + 1
     ms = sum(kernels[k][1] for k in names if k in kernels)
     gbs = b.elmore_fwd_bytes * sweeps / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
-            "ms_per_sweep": ms / sweeps}
+    out = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+           "ms_per_sweep": ms / sweeps,
+           "traffic_k_elmore_wave": measured_traffic(workload_digest, "k_elmore_wave") if workload_digest else None}
+    back = ("k_adj_wave", "k_adj_tiles", "k_adj_up", "k_adj_down")
+    nb = kernels["k_adj_wave"][0] if "k_adj_wave" in kernels else 0
+    if nb:
+        bms = sum(kernels[k][1] for k in back if k in kernels)
+        bgbs = b.elmore_bwd_bytes * nb / (bms * 1e-3) / 1e9
+        out["reverse"] = {"achieved": bgbs, "frac": bgbs / 8000.0, "ms_per_sweep": bms / nb,
+                          "traffic_k_adj_wave": (measured_traffic(workload_digest, "k_adj_wave")
+                                                 if workload_digest else None)}
+    return out
 
 
 def _oracle_schedule(T, adjoint):

@@ -23,24 +23,30 @@ def _write(path, sha, digest, value="1.5e+09"):
                     "workload_digest: %s\n" % (value, sha, digest))
 
 
-def test_traffic_needs_matching_sources_and_instance(tmp_path, monkeypatch):
-    f = tmp_path / "traffic.md"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    sha = bench.kernel_sources_sha256()
+@pytest.mark.parametrize("kernel", sorted(bench.KERNEL_SOURCES))
+def test_traffic_needs_matching_sources_and_instance(tmp_path, monkeypatch, kernel):
+    monkeypatch.setattr(bench, "traffic_file", lambda k: str(tmp_path / ("%s.md" % k)))
+    f = tmp_path / ("%s.md" % kernel)
+    sha = bench.kernel_sources_sha256(kernel)
     _write(f, sha, "abc")
-    assert bench.measured_traffic("abc") == pytest.approx(1.5e9)
-    assert bench.measured_traffic("abd") is None          # another instance
+    assert bench.measured_traffic("abc", kernel) == pytest.approx(1.5e9)
+    assert bench.measured_traffic("abd", kernel) is None          # another instance
     _write(f, "0" * 64, "abc")
-    assert bench.measured_traffic("abc") is None          # other kernel sources
+    assert bench.measured_traffic("abc", kernel) is None          # other kernel sources
     _write(f, sha, "abc", value="n/a")
-    assert bench.measured_traffic("abc") is None          # unreadable figure
+    assert bench.measured_traffic("abc", kernel) is None          # unreadable figure
     f.unlink()
-    assert bench.measured_traffic("abc") is None          # no summary
+    assert bench.measured_traffic("abc", kernel) is None          # no summary
 
 
-def test_committed_traffic_summary_names_sources_and_instance():
+def test_elmore_and_dp_sources_differ():
+    assert bench.kernel_sources_sha256("k_batched_dp") != bench.kernel_sources_sha256("k_elmore_wave")
+
+
+@pytest.mark.parametrize("kernel", sorted(bench.KERNEL_SOURCES))
+def test_committed_traffic_summary_names_sources_and_instance(kernel):
     vals = {}
-    with open(bench.TRAFFIC_FILE) as fh:
+    with open(bench.traffic_file(kernel)) as fh:
         for line in fh:
             if ":" in line and not line.startswith(("|", "#", "`")):
                 k, v = line.split(":", 1)
