@@ -544,6 +544,16 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->rest, rest));
     chk(upload(&b->budget_fs, budget));
     chk(upload(&b->rdrv, rdrv));
+    {
+        // the budgets (ps) and driver resistances (kOhm) in single precision, each rounded once
+        std::vector<float> bp(std::max<int32_t>(N, 1), 0.f), rk(std::max<int32_t>(N, 1), 0.f);
+        for (int32_t i = 0; i < N; ++i) {
+            bp[i] = (float)((double)budget[i] * 1e-3);
+            rk[i] = (float)((double)rdrv[i] * 1e-6);
+        }
+        chk(upload(&b->budget_ps, bp));
+        chk(upload(&b->rdrv_k, rk));
+    }
     chk(upload(&b->dir, dir));
     chk(upload(&b->flags, flags));
     chk(upload(&b->level_nodes, level_nodes));

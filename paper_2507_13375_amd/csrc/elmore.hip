@@ -97,7 +97,7 @@ __global__ void k_rc(TreeDev T, LayerTab targ, const uint8_t *lay, float *R, flo
         if (i < T.nodes) {
             const int32_t v = (int32_t)i, p = T.parent[v];
             if (p < 0) {
-                R[v] = (float)((double)T.rdrv[T.net[v]] * 1e-6);
+                R[v] = T.rdrv_k[T.net[v]];
                 C[v] = 0.f;
                 continue;
             }
@@ -718,7 +718,7 @@ __global__ void k_slack(TreeDev T, const float *delay, float *slack, uint32_t *w
     uint32_t m = 0xffffffffu;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = T.sink_node[k];
-        const float s = (float)((double)T.budget_fs[T.net[v]] * 1e-3) - delay[k];
+        const float s = T.budget_ps[T.net[v]] - delay[k];
         slack[k] = s;
         m = min(m, f2ord(s));
     }
@@ -812,7 +812,7 @@ __global__ void k_tns_partial(TreeDev T, const float *delay, double *part)
     double s = 0.0, m = INFINITY;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = T.sink_node[k];
-        const double sl = (double)((float)((double)T.budget_fs[T.net[v]] * 1e-3) - delay[k]);
+        const double sl = (double)(T.budget_ps[T.net[v]] - delay[k]);
         if (sl < 0.0) s += sl;
         m = fmin(m, sl);
     }
@@ -882,6 +882,8 @@ TreeDev tree_view(const la_batch *b)
     t.rest = b->rest;
     t.budget_fs = b->budget_fs;
     t.rdrv = b->rdrv;
+    t.budget_ps = b->budget_ps;
+    t.rdrv_k = b->rdrv_k;
     return t;
 }
 

@@ -118,6 +118,8 @@ struct TreeDev {
     const int32_t *rest;            // average-R estimate (mOhm) from the driver to the segment's upper end
     const int32_t *budget_fs;       // per net
     const int32_t *rdrv;            // per net, mOhm
+    const float *budget_ps;         // per net, ps (single precision, rounded once)
+    const float *rdrv_k;            // per net, kOhm (single precision, rounded once)
 };
 
 }  // namespace gapla
@@ -144,6 +146,7 @@ struct la_batch {
     int32_t *e_wtile = nullptr;         // wavefront runs ([start, end) pairs) of the nets of <= kWTile nodes
     int32_t e_nwtiles = 0;
     float *cpin_ff = nullptr;           // [nodes] pin load in fF (float)
+    float *budget_ps = nullptr, *rdrv_k = nullptr;   // [nets] budget in ps, driver resistance in kOhm (float)
     std::vector<int32_t> h_ebig_ptr;    // [levels+1]
     std::vector<int32_t> h_net_ptr;
     std::vector<int16_t> h_bbox;        // [nets][4] x min, x max, y min, y max of the net's nodes
