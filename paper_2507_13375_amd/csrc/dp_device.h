@@ -130,6 +130,8 @@ __device__ __forceinline__ int64_t kappa_seg(const DPArgs &a, const LayerTab &tb
     const int32_t self = (a.w.self_excl && a.prev[n] == l) ? 1 : 0;
     const int32_t *lut = a.w.lut + l * 2 * kNDelta;
     int64_t s = 0;
+    // unrolled so that several edges' loads are in flight at once
+#pragma unroll 4
     for (int32_t k = first; k < len; k += stride, g += stride * step) {
         const int32_t cap = a.caps[g];
         int32_t d = a.D[g] - self - cap;
