@@ -503,6 +503,58 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 || CAP > 192 ? 3 : 4) k_ba
     }
 }
 
+// Congestion costs kappa_n(l) of every node and candidate layer of the batch's nets larger
+// than one LDS tile, into their slots of the HBM state array F (each DP item of k_batched_big
+// reads its slot before it overwrites it with f): the level walk then does no gather.  Workgroup
+// row y takes big net y; a wavefront takes a node, its lanes the segment's GCell edges (every
+// candidate layer at once: a record holds them side by side), summed across the wavefront.
+template <int NAMAX>
+__global__ void __launch_bounds__(256) k_kappa_big(DPArgs a, BArgs ba)
+{
+    __shared__ LayerTab tb;
+    load_tab(a.tab, tb);
+    const int lane = threadIdx.x & 63;
+    const int32_t wv = blockIdx.x * 4 + (threadIdx.x >> 6), nwv = gridDim.x * 4;
+    const int32_t off0 = ba.tier_off[ba.tier * kNB], cnt = ba.tier_off[ba.tier * kNB + 1] - off0;
+    for (int32_t i = blockIdx.y; i < cnt; i += gridDim.y) {
+        const int32_t net = ba.tier_nets[off0 + i];
+        const int32_t n0 = a.T.net_ptr[net], n1 = a.T.net_ptr[net + 1];
+        for (int32_t n = n0 + wv; n < n1; n += nwv) {
+            const int d = a.T.dir[n];
+            const int na = tb.nA[d];
+            const bool root = a.T.parent[n] < 0;
+            const int32_t len = root ? 0 : a.T.len[n];
+            const int self = a.w.self_excl ? a.prev[n] : 255;
+            const int32_t step = tb.nAp[d];
+            const int32_t g0 = route_index(tb, d, 0, a.T.g0[n]);
+            int64_t acc[NAMAX];
+#pragma unroll
+            for (int j = 0; j < NAMAX; ++j) acc[j] = 0;
+            for (int32_t k = lane; k < len; k += 64) {
+                const int32_t g = g0 + k * step;
+#pragma unroll
+                for (int j = 0; j < NAMAX; ++j) {
+                    if (j < na) {
+                        const int l = tb.lay[d][j];
+                        const int32_t cap = a.caps[g + j];
+                        int32_t dd = a.D[g + j] - (self == l ? 1 : 0) - cap;
+                        dd = dd < kDeltaMin ? kDeltaMin : (dd > kDeltaMin + kNDelta - 1 ? kDeltaMin + kNDelta - 1 : dd);
+                        acc[j] += a.w.lut[(l * 2 + (cap > 0 ? 0 : 1)) * kNDelta + dd - kDeltaMin] + (int64_t)a.H[g + j];
+                    }
+                }
+            }
+            int64_t mine = 0;
+#pragma unroll
+            for (int j = 0; j < NAMAX; ++j) {
+                int64_t v = acc[j];
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+                if (lane == j) mine = v;
+            }
+            if (lane < a.NA) a.F[(int64_t)n * a.NA + lane] = lane < na ? mine : 0;
+        }
+    }
+}
+
 // Nets larger than one LDS tile: one workgroup per net, DP state in HBM, the net's own
 // height levels walked with workgroup barriers.
 template <int NAMAX>
@@ -537,15 +589,8 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
                     if (j >= tb.nA[d]) continue;
                     l = tb.lay[d][j];
                 }
-                int64_t kp = 0;
-                if (!root && grp) {
-                    // the group's lanes take every kGroup-th GCell step of the segment
-                    kp = kappa_seg(a, tb, n, l, sub, kGroup);
-#pragma unroll
-                    for (int m = 1; m < kGroup; m <<= 1) kp += __shfl_xor(kp, m, kGroup);
-                } else if (!root) {
-                    kp = kappa_seg(a, tb, n, l);
-                }
+                // the congestion cost, from k_kappa_big
+                const int64_t kp = root ? 0 : a.F[(int64_t)n * a.NA + j];
                 if (!grp) {
                     dp_node<GlobalState, NAMAX>(a, tb, gst, n, l, j, root, kp);
                 } else {
@@ -827,6 +872,14 @@ la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t 
     // it was before the batch and append to one change list.
     const bool fork = nbig > 0 && nsmall > 0;
     hipStream_t sb = s;
+    if (nbig > 0) {
+        // the big nets' congestion costs first, on the whole GPU: launched beside the tile
+        // kernel, whose persistent workgroups hold every slot, they would wait for it
+        const int kx = (int)std::max<int64_t>(1, std::min<int64_t>((b->max_net_nodes + 3) / 4, 512));
+        auto kbig = NA <= 4 ? k_kappa_big<4> : (NA <= 6 ? k_kappa_big<6> : k_kappa_big<8>);
+        LA_TIMED(b, "k_kappa_big", s,
+                 hipLaunchKernelGGL(kbig, dim3(kx, std::min(nbig, 4096)), dim3(256), 0, s, a, ba));
+    }
     if (fork) {
         LA_HIP(hipEventRecord(b->ev_fork, s));
         LA_HIP(hipStreamWaitEvent(b->side_stream, b->ev_fork, 0));
