@@ -36,6 +36,18 @@ def test_batches_equal_the_oracle(nets, nsub):
     assert bad.size == 0, (bad[:5], gb[bad[:5]], ob[bad[:5]])
 
 
+def test_grid_not_a_multiple_of_the_bin_size():
+    # 37 x 29 GCells: the blocking bins (4 x 4 GCells) of the last row and column are partial
+    inst = gen.generate(3000, 37, 29, 8, 4242, pin_law=1, pin_max=24, placement=1, n_hot=4, hot_sigma=6.0)
+    T = oracle.Tree(inst)
+    rng = np.random.default_rng(37)
+    subset = rng.integers(0, 3, T.nets).astype(np.int32)
+    ob, on = oracle.get_batches(T, inst.X, inst.Y, subset, 3)
+    gb, gn = _gpu_batches(DeviceRun(inst), subset, 3)
+    say("37x29 grid, 3000 nets: %d batches (oracle %d)" % (gn, on))
+    assert gn == on and np.array_equal(gb, ob)
+
+
 def test_single_net_and_identical_boxes():
     # every net of c1 in one subset, then the same nets twice over (identical boxes stack up)
     inst = gen.config(1, num_nets=300)
