@@ -573,15 +573,38 @@ __global__ void __launch_bounds__(64) k_elmore_wave(TreeDev T, const int32_t *ru
     }
 }
 
+// Adjoint-form weights (Q10 segment and pin weights, look-ahead lambda in mOhm) from the
+// reverse sweep's G (a segment) and Sigma (its parent), each product and sum rounded as
+// written, so every kernel that forms them gets the same bits.
+__device__ __forceinline__ uint16_t adj_q10(float g_hi, float g_lo)
+{
+    const float q = rintf(__fmul_rn(-1024.0f, __fadd_rn(g_hi, g_lo)));
+    return (uint16_t)(q < 0.f ? 0.f : (q > 1024.f ? 1024.f : q));
+}
+
+__device__ __forceinline__ int32_t adj_lambda(float sig_hi, float sig_lo)
+{
+    // -Sigma * 1e6 as a float-float product, then rounded
+    const float sh = -sig_hi, sl = -sig_lo;
+    const float ph = __fmul_rn(sh, 1e6f);
+    const float pl = __fadd_rn(__fmaf_rn(sh, 1e6f, -ph), __fmul_rn(sl, 1e6f));
+    const float x = rintf(__fadd_rn(ph, pl));
+    return x <= 0.f ? 0 : (x >= 2147483520.f ? 2147483647 : (int32_t)x);
+}
+
+// GRADS: the R / C gradients are written (la_elmore_backward); without them (the adjoint
+// weights) the kernel keeps fewer registers live and runs more waves per SIMD, and, given
+// seg_w, writes the weights of its nodes and sinks itself.
+template <bool GRADS>
 __global__ void __launch_bounds__(64) k_adj_wave(TreeDev T, const int32_t *runs, int32_t nruns,
                                                  const int32_t *height, const float *R, const float *C,
                                                  const float *S, const float *Slo, const float *gbar, float *G,
-                                                 float *Glo, float *Sig, float *Siglo, float *dR, float *dC)
+                                                 float *Glo, float *Sig, float *Siglo, float *dR, float *dC,
+                                                 uint16_t *seg_w, uint16_t *pin_w, int32_t *lam)
 {
     __shared__ float gh[kWTile], gl[kWTile], qh[kWTile], ql[kWTile];
     __shared__ int16_t chl[kWTile];
     const int lane = threadIdx.x;
-    const bool grads = dR != nullptr || dC != nullptr;
     for (int32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
         WaveRun w;
         wave_run_load(T, height, runs, ri, w, chl);
@@ -635,7 +658,12 @@ __global__ void __launch_bounds__(64) k_adj_wave(TreeDev T, const int32_t *runs,
                 ql[u] = sv.lo;
                 Sig[v] = sv.hi;
                 Siglo[v] = sv.lo;
-                if (grads) {
+                if (!GRADS && seg_w) {
+                    seg_w[v] = adj_q10(xh[j], xl[j]);
+                    lam[v] = p < 0 ? 0 : adj_lambda(up.hi, up.lo);
+                    if (w.sk[j] >= 0) pin_w[w.sk[j]] = adj_q10(gk[j], 0.f);
+                }
+                if (GRADS) {
                     const float cv = C[v];
                     if (dR) dR[v] = ff_val(ff_mul(ff_val(g), ff_add(ff{S[v], Slo[v]}, 0.5f * cv)));
                     if (dC) dC[v] = ff_val(ff_add(up, 0.5f * r[j] * ff_val(g)));
@@ -782,24 +810,12 @@ __global__ void k_adj_weights(TreeDev T, const float *G, const float *Glo, const
                               const float *gbar, uint16_t *seg_w, uint16_t *pin_w, int32_t *lam)
 {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T.nodes; v += (int64_t)gridDim.x * blockDim.x) {
-        const float q = rintf(-1024.0f * (G[v] + Glo[v]));
-        seg_w[v] = (uint16_t)(q < 0.f ? 0.f : (q > 1024.f ? 1024.f : q));
+        seg_w[v] = adj_q10(G[v], Glo[v]);
         const int32_t p = T.parent[v];
-        if (p < 0) {
-            lam[v] = 0;
-        } else {
-            // -Sig * 1e6 as a float-float product, then rounded
-            const float sh = -Sig[p], sl = -Siglo[p];
-            const float ph = sh * 1e6f;
-            const float pl = fmaf(sh, 1e6f, -ph) + sl * 1e6f;
-            const float x = rintf(ph + pl);
-            lam[v] = x <= 0.f ? 0 : (x >= 2147483520.f ? 2147483647 : (int32_t)x);
-        }
+        lam[v] = p < 0 ? 0 : adj_lambda(Sig[p], Siglo[p]);
     }
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x) {
-        const float q = rintf(-1024.0f * gbar[k]);
-        pin_w[k] = (uint16_t)(q < 0.f ? 0.f : (q > 1024.f ? 1024.f : q));
-    }
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < T.sinks; k += (int64_t)gridDim.x * blockDim.x)
+        pin_w[k] = adj_q10(gbar[k], 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -995,7 +1011,8 @@ la_status elmore_forward(la_batch *b, const float *R, const float *C, float *del
 }
 
 // gbar: dJ/d delay per sink (from_dslack: the array holds dJ/dslack and is negated first)
-la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *dR, float *dC)
+la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *dR, float *dC, uint16_t *seg_w,
+                          uint16_t *pin_w, int32_t *lam)
 {
     if (!b->fwd_done) return set_error(LA_ERR_STATE, "la_elmore_backward needs a forward on this batch first");
     const TreeDev T = tree_view(b);
@@ -1008,10 +1025,12 @@ la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *
     }
     float *Glo = b->el_Glo, *Siglo = b->el_Siglo;
     if (b->e_nwtiles > 0)
-        LA_TIMED(b, "k_adj_wave", b->stream,
-                 hipLaunchKernelGGL(k_adj_wave, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, b->e_wtile,
-                                    b->e_nwtiles, b->height, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, gbar, b->el_G,
-                                    Glo, b->el_Sig, Siglo, dR, dC));
+        LA_TIMED(b, "k_adj_wave", b->stream, {
+            auto kern = (dR || dC) ? k_adj_wave<true> : k_adj_wave<false>;
+            hipLaunchKernelGGL(kern, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, b->e_wtile, b->e_nwtiles,
+                               b->height, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, gbar, b->el_G, Glo, b->el_Sig,
+                               Siglo, dR, dC, (dR || dC) ? nullptr : seg_w, pin_w, lam);
+        });
     if (b->e_ntiles > 0)
         LA_TIMED(b, "k_adj_tiles", b->stream,
                  hipLaunchKernelGGL(k_adj_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T, b->e_tile,
@@ -1069,9 +1088,13 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
     LA_TIMED(b, "k_adj_seed", b->stream,
              hipLaunchKernelGGL(k_adj_seed, dim3(grid_for(b->sinks)), dim3(kBlock), 0, b->stream, T, b->slack, pin_w,
                                 b->scratch_f));
-    la_status s = elmore_backward(b, b->scratch_f, false, nullptr, nullptr);
+    la_status s = elmore_backward(b, b->scratch_f, false, nullptr, nullptr, seg_w, pin_w, lam);
     if (s != LA_OK) return s;
-    LA_TIMED(b, "k_adj_weights", b->stream,
+    // the wavefront runs wrote their nets' weights; the other nets' (workgroup tiles, per-level
+    // walks) from the stored G and Sigma -- over every node, the runs' ones with the same bits
+    const bool others = b->e_ntiles > 0 || (!b->h_ebig_ptr.empty() && b->h_ebig_ptr.back() > 0);
+    if (others || b->e_nwtiles == 0)
+        LA_TIMED(b, "k_adj_weights", b->stream,
              hipLaunchKernelGGL(k_adj_weights, dim3(grid_for(b->nodes)), dim3(kBlock), 0, b->stream, T, b->el_G,
                                 b->el_Glo, b->el_Sig, b->el_Siglo, b->scratch_f, seg_w, pin_w, lam));
     LA_HIP(hipGetLastError());

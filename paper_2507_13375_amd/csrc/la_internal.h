@@ -288,7 +288,9 @@ private:
 la_status launch_rc_from_layers(la_batch *b);
 la_status launch_rc_pre(la_batch *b);
 la_status elmore_forward(la_batch *b, const float *R, const float *C, float *delay);
-la_status elmore_backward(la_batch *b, const float *gbar_neg_dslack, bool from_dslack, float *dR, float *dC);
+// with seg_w (and no dR, dC) the wavefront runs also write the adjoint-form weights of their nodes
+la_status elmore_backward(la_batch *b, const float *gbar_neg_dslack, bool from_dslack, float *dR, float *dC,
+                          uint16_t *seg_w = nullptr, uint16_t *pin_w = nullptr, int32_t *lam = nullptr);
 la_status commit_changed(la_batch *b, int32_t *D);
 // conversions between the API's grid order (E int32) and the library's layout (Eg int32)
 la_status grid_to_planes(la_batch *b, const int32_t *api, int32_t *planes);
