@@ -91,17 +91,48 @@ __global__ void k_zero_i32(int32_t *p, int64_t n)
 }
 
 // demand moves of the segments whose layer changed (HBM atomics; integer, so order-free)
+// One lane per GCell edge of the changed segments: a wavefront takes 64 changes, scans their
+// lengths and walks the concatenated edges, so consecutive lanes move consecutive edges of a
+// segment (adjacent records) rather than one lane walking a whole segment.
 __global__ void k_commit(TreeDev T, LayerTab tab, const int32_t *chg_node, const uint8_t *chg_old,
                          const uint8_t *chg_new, const int32_t *chg_count, int32_t *D)
 {
     const int32_t cnt = *chg_count;
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
-        const int32_t n = chg_node[i];
-        const int o = chg_old[i], nw = chg_new[i];
-        const int32_t q = T.g0[n];
-        for (int32_t k = 0; k < T.len[n]; ++k) {
-            if (o != 255) atomicAdd(&D[grid_index(tab, o, q + k)], -1);
-            atomicAdd(&D[grid_index(tab, nw, q + k)], 1);
+    const int lane = threadIdx.x & 63;
+    const int32_t w0 = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), nw = gridDim.x * (blockDim.x >> 6);
+    for (int32_t base = w0 * 64; base < cnt; base += nw * 64) {
+        const int32_t i = base + lane;
+        int32_t q = 0, len = 0, o = 255, nl = 255;
+        if (i < cnt) {
+            const int32_t n = chg_node[i];
+            o = chg_old[i];
+            nl = chg_new[i];
+            q = T.g0[n];
+            len = T.len[n];
+        }
+        int32_t pre = len;   // inclusive scan of the lengths
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t y = __shfl_up(pre, d);
+            if (lane >= d) pre += y;
+        }
+        const int32_t total = __shfl(pre, 63);
+        for (int32_t e0 = 0; e0 < total; e0 += 64) {
+            const int32_t e = e0 + lane;
+            // the change holding edge e: the first c with pre[c] > e
+            int32_t c = 0;
+#pragma unroll
+            for (int s = 32; s > 0; s >>= 1) {
+                const int32_t pc = __shfl(pre, c + s - 1);
+                if (pc <= e) c += s;
+            }
+            const int32_t pc0 = __shfl(pre, c) - __shfl(len, c);   // first edge of change c
+            const int32_t qc = __shfl(q, c), oc = __shfl(o, c), nc = __shfl(nl, c);
+            if (e < total) {
+                const int32_t k = e - pc0;
+                if (oc != 255) atomicAdd(&D[grid_index(tab, oc, qc + k)], -1);
+                atomicAdd(&D[grid_index(tab, nc, qc + k)], 1);
+            }
         }
     }
 }
