@@ -35,7 +35,7 @@ constexpr int kFT = 1024;           // threads per first-fit workgroup
 constexpr int kFitGroups = 64;      // first-fit workgroups (fewer where fewer fit at once)
 constexpr int kChunk = 8192;        // nets of a subset placed per chunk
 constexpr int kBatchWords = 16;     // 64-bit words of batch bits per GCell: at most 1024 batches
-static_assert(kBatchWords % 4 == 0, "the batch words are scanned four at a time");
+static_assert(kBatchWords % 8 == 0, "the batch words are scanned eight at a time");
 
 // ---- stable order of the nets by (subset, index) ---------------------------------------
 // per workgroup of kBT consecutive nets and subset s: cnt[s * nblk + blk]
@@ -292,23 +292,26 @@ __global__ void __launch_bounds__(kFT) k_first_fit(FitArgs a)
                         const int32_t net = a.ord[c0 + q];
                         const int16_t *b = a.box + 4 * (int64_t)net;
                         const int32_t bw = b[1] - b[0] + 1, area = bw * (b[3] - b[2] + 1);
-                        // four batch words (32 bytes of a GCell's 128-byte record) per pass over
+                        // eight batch words (64 bytes of a GCell's 128-byte record) per pass over
                         // the box; words below the subset's first batch count as taken
                         int32_t bt = -1;
                         const int wb = base >> 6;
-                        for (int w0 = wb & ~3; w0 < kBatchWords && bt < 0; w0 += 4) {
-                            unsigned long long u[4] = {0ull, 0ull, 0ull, 0ull};
+                        for (int w0 = wb & ~7; w0 < kBatchWords && bt < 0; w0 += 8) {
+                            unsigned long long u[8];
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) u[k] = 0ull;
                             for (int32_t i = lane; i < area; i += 64) {
                                 const ulonglong2 *p =
                                     (const ulonglong2 *)(a.bits + box_cell(b, bw, a.X, i) * kBatchWords + w0);
-                                const ulonglong2 x = p[0], y = p[1];
-                                u[0] |= x.x;
-                                u[1] |= x.y;
-                                u[2] |= y.x;
-                                u[3] |= y.y;
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) {
+                                    const ulonglong2 x = p[k];
+                                    u[2 * k] |= x.x;
+                                    u[2 * k + 1] |= x.y;
+                                }
                             }
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) {
+                            for (int k = 0; k < 8; ++k) {
                                 for (int o = 32; o > 0; o >>= 1) u[k] |= __shfl_xor(u[k], o);
                                 const int w = w0 + k;
                                 if (w < wb) u[k] = ~0ull;
