@@ -137,15 +137,33 @@ __global__ void k_commit(TreeDev T, LayerTab tab, const int32_t *chg_node, const
     }
 }
 
+__device__ __forceinline__ int32_t history_step(int32_t d, int32_t cap, int32_t h, int32_t inc)
+{
+    const int32_t over = d - cap;
+    if (over <= 0) return h;
+    const int64_t x = (int64_t)h + (int64_t)inc * over;
+    return (int32_t)(x > kHistSat ? kHistSat : x);
+}
+
+// Four GCell edges per lane (16-byte demand and history, 4-byte capacity accesses), the tail
+// one by one.
 __global__ void k_history(const int32_t *D, const uint8_t *caps, int32_t *H, int64_t E, int32_t inc)
 {
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < E; g += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t over = D[g] - (int32_t)caps[g];
-        if (over > 0) {
-            const int64_t h = (int64_t)H[g] + (int64_t)inc * over;
-            H[g] = (int32_t)(h > kHistSat ? kHistSat : h);
-        }
+    const int64_t E4 = E / 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < E4; g += stride) {
+        const int4 d = ((const int4 *)D)[g];
+        const uchar4 c = ((const uchar4 *)caps)[g];
+        int4 h = ((const int4 *)H)[g];
+        const int4 h0 = h;
+        h.x = history_step(d.x, c.x, h.x, inc);
+        h.y = history_step(d.y, c.y, h.y, inc);
+        h.z = history_step(d.z, c.z, h.z, inc);
+        h.w = history_step(d.w, c.w, h.w, inc);
+        if (h.x != h0.x || h.y != h0.y || h.z != h0.z || h.w != h0.w) ((int4 *)H)[g] = h;
     }
+    for (int64_t g = 4 * E4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < E; g += stride)
+        H[g] = history_step(D[g], caps[g], H[g], inc);
 }
 
 // Counting sort of nodes by (batch, height).  With few buckets each block keeps a
@@ -306,8 +324,8 @@ la_status zero_i32(la_batch *b, int32_t *p, int64_t n)
 la_status history_update(la_batch *b, const int32_t *D, int32_t *H, int32_t inc)
 {
     LA_TIMED(b, "k_history", b->stream,
-             hipLaunchKernelGGL(k_history, dim3(grid_for(b->Eg)), dim3(kBlock), 0, b->stream, D, b->caps, H, b->Eg,
-                                inc));
+             hipLaunchKernelGGL(k_history, dim3(grid_for(b->Eg / 4 + 1)), dim3(kBlock), 0, b->stream, D, b->caps, H,
+                                b->Eg, inc));
     LA_HIP(hipGetLastError());
     return LA_OK;
 }
