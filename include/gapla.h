@@ -197,7 +197,7 @@ la_status la_set_tuning(la_batch *b, const la_tuning *t);
 la_status la_get_tuning(const la_batch *b, la_tuning *out);
 
 /*
- * la_get_batches -- classical batching (Alg. 1, GetBatch, lines 6-8: the batching of the
+ * la_get_batches -- classical batching (Alg. 1, GetBatch: the batching of the
  * routers the paper cites for it).  A net's box is the GCell rectangle its tree spans.  Within
  * each subset, in increasing net order, a net joins the lowest batch in which no net's box
  * shares a GCell with its own (so the nets of a batch share no GCell edge); subsets are batched
@@ -214,7 +214,7 @@ la_status la_get_batches(la_batch *b, const int32_t *net_subset, int32_t num_sub
                          int32_t *num_batches);
 
 /*
- * Critical-path net ordering (Sec. III-A; Alg. 1 lines 1-5) on a gate-level graph over the nets.
+ * Critical-path net ordering (Sec. III-A; Alg. 1 ordering) on a gate-level graph over the nets.
  * la_timing_graph sets the graph: each net is driven by one gate (gate_delay_fs: HOST [nets]);
  * sink k (node order) feeds the gate of net sink_next[k] (HOST [sinks]), or is a primary output
  * (-1) whose required time is clock_fs.  Copied; ordered topologically on the host.
@@ -235,7 +235,7 @@ la_status la_timing_graph(la_batch *b, const int32_t *sink_next, const int32_t *
  */
 la_status la_sta(la_batch *b, const float *sink_delay, float *out_slack, int32_t *out_crit, float *wns);
 /*
- * la_alg1_subsets -- Alg. 1 lines 3-5: critical nets (more than three counted paths) by count
+ * la_alg1_subsets -- Alg. 1 division and partition: critical nets (more than three counted paths) by count
  * against the largest, C: subset k holds C / 2^k <= count < C / 2^(k-1); the other nets whose
  * net slack (least over its sinks) is below 0.7 WNS by rho = slack / WNS in the bins 1,
  * [0.99, 1), [0.96, 0.99), [0.91, 0.96), [0.84, 0.91), [0.75, 0.84), [0.7, 0.75); then the rest.

@@ -276,8 +276,8 @@ def get_batches(tree: Tree, X: int, Y: int, subset, nsub: int):
 
 
 def sta(tree: Tree, sink_next, gate_delay_fs, clock_fs: int, delay):
-    """Static timing of the gate graph over the nets (Alg. 1 line 1) in single precision, and the
-    critical-path counts of line 2.  delay: per-sink Elmore delay (ps, float32).  Returns
+    """Static timing of the gate graph over the nets (Alg. 1, its first step) in single precision, and
+    the critical-path counts that follow it.  delay: per-sink Elmore delay (ps, float32).  Returns
     (slack per sink, critical paths per net, WNS)."""
     sl = np.empty(max(tree.sinks, 1), np.float32)
     cr = np.empty(max(tree.nets, 1), np.int32)
@@ -291,7 +291,7 @@ def sta(tree: Tree, sink_next, gate_delay_fs, clock_fs: int, delay):
 
 
 def alg1_subsets(tree: Tree, slack, crit, wns: float):
-    """Alg. 1 lines 3-5: the ordered subsets (critical by path count, semi-critical by slack,
+    """Alg. 1 division and partition: the ordered subsets (critical by path count, semi-critical by slack,
     then the rest).  Returns (subset per net, number of subsets)."""
     out = np.empty(max(tree.nets, 1), np.int32)
     n = _load().oracle_alg1_subsets(tree.handle, _p(np.ascontiguousarray(slack, np.float32)),

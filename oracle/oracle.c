@@ -934,8 +934,8 @@ int64_t oracle_get_batches(const otree *T, int32_t X, int32_t Y, const int32_t *
 }
 
 /*
- * Static timing of a gate-level graph over the nets (Alg. 1 line 1) and the critical-path
- * count of line 2.  Each net is driven by one gate (delay gate_fs); each sink feeds the gate of
+ * Static timing of a gate-level graph over the nets (Alg. 1, its first step) and the
+ * critical-path count that follows it.  Each net is driven by one gate (delay gate_fs); each sink feeds the gate of
  * net sink_next (or is a primary output, -1).  Single precision, each value rounded once as
  * written (max and min are exact), so decisions taken from it (a gate's latest input, the bins
  * of Alg. 1) come out the same in any evaluation order:
@@ -1044,7 +1044,7 @@ done:
 }
 
 /*
- * Alg. 1 lines 3-5: divide the nets and partition the timing-critical ones into ordered
+ * Alg. 1 division and partition: divide the nets and partition the timing-critical ones into ordered
  * subsets.  Net slack = the minimum slack over the net's sinks.  Critical nets (N_c): more than
  * three counted critical paths; with C the largest count, subset k holds the counts c with
  * C / 2^k <= c < C / 2^(k-1) (subset 0: c = C).  Semi-critical nets (N_s): the other nets whose

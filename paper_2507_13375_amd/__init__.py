@@ -300,14 +300,14 @@ def la_timing_graph(b: Batch, sink_next, gate_delay_fs, clock_fs: int):
 
 
 def la_sta(b: Batch, sink_delay, out_slack, out_crit) -> float:
-    """Static timing of the gate graph and critical-path counts (Alg. 1 lines 1-2); returns WNS."""
+    """Static timing of the gate graph and critical-path counts (Alg. 1: static timing and critical-path counts); returns WNS."""
     w = ctypes.c_float()
     _chk(_load().la_sta(_on(b), _dev(sink_delay), _dev(out_slack), _dev(out_crit), ctypes.byref(w)), "la_sta")
     return w.value
 
 
 def la_alg1_subsets(b: Batch, slack, crit, wns: float, out_subset) -> int:
-    """Alg. 1 lines 3-5: ordered subsets of the nets; returns their number."""
+    """Alg. 1 division and partition: ordered subsets of the nets; returns their number."""
     n = I32()
     _chk(_load().la_alg1_subsets(_on(b), _dev(slack), _dev(crit), ctypes.c_float(wns), _dev(out_subset),
                                  ctypes.byref(n)), "la_alg1_subsets")

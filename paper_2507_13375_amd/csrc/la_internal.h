@@ -309,7 +309,7 @@ la_status tune_batched(la_batch *b, const la_weights *w, const int32_t *history,
                        const int32_t *batch, bool use_cache);
 // the batch indices the forms read: the caller's int32 array, a widened copy of its u8 tiers, or NULL
 la_status batch_indices(la_batch *b, const la_weights *w, const int32_t **out);
-// Alg. 1 lines 1-5 on a gate graph over the nets (sta.hip)
+// Alg. 1's ordering on a gate graph over the nets (sta.hip)
 la_status timing_graph(la_batch *b, const int32_t *sink_next, const int32_t *gate_fs, int32_t clock_fs);
 la_status sta(la_batch *b, const float *delay, float *slack, int32_t *crit, float *wns_out);
 la_status alg1_subsets(la_batch *b, const float *slack, const int32_t *crit, float wns, int32_t *subset,

@@ -1,4 +1,4 @@
-// Critical-path net ordering (Sec. III-A, Alg. 1 lines 1-5) on a gate-level graph over the
+// Critical-path net ordering (Sec. III-A, Alg. 1 ordering) on a gate-level graph over the
 // nets: static timing with the nets' sink delays, the top-1 critical path of every violating
 // primary output, the count of those paths through each net, and the division of the nets into
 // ordered subsets (critical by count, semi-critical by slack, the rest).

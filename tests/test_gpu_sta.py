@@ -1,4 +1,4 @@
-"""GPU critical-path net ordering (Sec. III-A; Alg. 1 lines 1-5) against the oracle: static
+"""GPU critical-path net ordering (Sec. III-A; Alg. 1 ordering) against the oracle: static
 timing of the synthetic gate graph, top-1 critical-path counts and the ordered subsets, bit for
 bit (single precision, each value rounded once, on identical sink delays: the oracle's FP64
 Elmore delays rounded to single precision feed both sides); then the whole Alg. 1 flow --
@@ -55,7 +55,7 @@ def test_sta_counts_and_subsets_equal_the_oracle(nets):
 
 
 def test_alg1_flow_assignment():
-    # lines 1-8 of Alg. 1 then the layer assignment (two rounds, batched form) on their batches
+    # Alg. 1's ordering and GetBatch, then the layer assignment (two rounds, batched form) on their batches
     inst, T, tg, d32, run = _setup(40000, clock_fs=800000)
     sl, cr, wns = _gpu_sta(run, d32)
     t_ = torch()

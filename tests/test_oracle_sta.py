@@ -1,5 +1,5 @@
 """Pins of the oracle's static timing of the gate graph, critical-path counts and Alg. 1
-division (Sec. III-A; Alg. 1 lines 1-5), and of the synthetic timing graph.
+division (Sec. III-A; Alg. 1 ordering), and of the synthetic timing graph.
 
 - closed forms on hand-built chains and fan-ins (delays exact in single precision): arrival,
   required time and slack along the path, the latest input on a gate, the lowest sink on a tie;
