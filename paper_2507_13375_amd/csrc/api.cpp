@@ -443,7 +443,7 @@ void la_free_batch(la_batch *b)
                     b->chg_node, b->chg_count, b->chg_old, b->chg_new, b->lut, b->R, b->C, b->el_S,
                     b->el_Slo, b->el_t, b->el_tlo, b->el_G, b->el_Glo, b->el_Sig, b->el_Siglo, b->slack,
                     b->scratch_f, b->wns_bits, b->red, b->net_big, b->net_zw, b->nrec, b->dynrec, b->cnet, b->bbox, b->batch_i32, b->sta_next, b->sta_fin_ptr, b->sta_fin,
-                    b->sta_order, b->sta_gd, b->sta_f, b->sta_i, b->bn_order, b->bn_lvl, b->bn_lvl_off,
+                    b->sta_order, b->sta_gd, b->sta_f, b->sta_i, b->bn_order, b->bn_rec, b->bn_lvl, b->bn_lvl_off,
                     b->bn_nlev, b->tier_nets, b->tier_off, b->tier_cur, b->tier_cnt, b->claim,
                     b->cl_pre, b->cl_blk, b->cl_start, b->cl_off, b->D_alt, b->Hi,
                     b->e_tile, b->e_wtile, b->cpin_ff, b->budget_ps, b->rdrv_k, b->e_big_nodes, b->e_big_ptr, b->qofw, b->qpart};

@@ -108,6 +108,7 @@ struct BArgs {
     const int32_t *cl_off;
     const int32_t *height;
     const int32_t *net_big, *bn_order, *bn_lvl, *bn_lvl_off, *bn_nlev;
+    int4 *bn_rec;               // per bn_order position: the node's record (k_big_records)
     const uint8_t *net_zw;      // per net: all timing weights zero
     const uint4 *nrec;          // static node records (see la_batch::nrec)
     const uint2 *dynrec;        // this call's node weights: look-ahead, segment | pin << 16
@@ -503,6 +504,53 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 || CAP > 192 ? 3 : 4) k_ba
     }
 }
 
+// Per position of a big net's level order, the node's record for the level walk: node id,
+// parent, child count | direction << 8 | flags << 16, length; its first three children and pin
+// load; this call's look-ahead coefficient and segment weight.  One read then gives a DP item
+// its node's inputs and children, which otherwise take three dependent reads per level.
+__global__ void __launch_bounds__(256) k_big_records(DPArgs a, BArgs ba)
+{
+    const int32_t off0 = ba.tier_off[ba.tier * kNB], cnt = ba.tier_off[ba.tier * kNB + 1] - off0;
+    for (int32_t i = blockIdx.y; i < cnt; i += gridDim.y) {
+        const int32_t q = ba.net_big[ba.tier_nets[off0 + i]];
+        const int32_t lo = ba.bn_lvl_off[q];
+        const int32_t p0 = ba.bn_lvl[lo], p1 = ba.bn_lvl[lo + ba.bn_nlev[q]];
+        for (int32_t p = p0 + blockIdx.x * blockDim.x + threadIdx.x; p < p1; p += gridDim.x * blockDim.x) {
+            const int32_t n = ba.bn_order[p];
+            const int32_t c0 = a.T.ch_ptr[n], k = a.T.ch_ptr[n + 1] - c0;
+            int4 *r = ba.bn_rec + 3 * (int64_t)p;
+            r[0] = make_int4(n, a.T.parent[n], k | (int32_t)a.T.dir[n] << 8 | (int32_t)a.T.flags[n] << 16, a.T.len[n]);
+            r[1] = make_int4(k > 0 ? a.T.ch[c0] : -1, k > 1 ? a.T.ch[c0 + 1] : -1, k > 2 ? a.T.ch[c0 + 2] : -1,
+                             a.T.cpin[n]);
+            r[2] = make_int4(a.w.lam[n], (int32_t)a.w.seg_w[n], 0, 0);
+        }
+    }
+}
+
+// HBM state of a big net with the current node's record in registers: its inputs, child count
+// and first three children come from the record, everything else from HBM as in GlobalState.
+struct BigState : GlobalState {
+    int32_t cur;
+    int4 r0, r1, r2;
+    __device__ BigState(const DPArgs &a_, const int4 *rec) : GlobalState(a_), r0(rec[0]), r1(rec[1]), r2(rec[2])
+    {
+        cur = r0.x;
+    }
+    __device__ int nch(int32_t s) const { return s == cur ? (r0.z & 0xff) : GlobalState::nch(s); }
+    __device__ int32_t ch_state(int32_t s, int q) const
+    {
+        if (s == cur && q < 3) return q == 0 ? r1.x : (q == 1 ? r1.y : r1.z);
+        return GlobalState::ch_state(s, q);
+    }
+    __device__ NodeIn in(int32_t s) const
+    {
+        if (s == cur)
+            return NodeIn{r0.w, (uint32_t)r2.x, (uint16_t)r2.y, (uint8_t)((r0.z >> 8) & 0xff),
+                          (uint8_t)((r0.z >> 16) & 0xff), r1.w};
+        return GlobalState::in(s);
+    }
+};
+
 // Congestion costs kappa_n(l) of every node and candidate layer of the batch's nets larger
 // than one LDS tile, into their slots of the HBM state array F (each DP item of k_batched_big
 // reads its slot before it overwrites it with f): the level walk then does no gather.  Workgroup
@@ -577,28 +625,30 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
             for (int32_t it = threadIdx.x; it < span; it += blockDim.x) {
                 const int32_t gi = grp ? it / kGroup : it;
                 const int sub = grp ? it % kGroup : 0;
-                const int32_t n = ba.bn_order[b0 + gi / NAMAX];
+                // the node's record (k_big_records): inputs and first children in one read
+                const BigState bst(a, ba.bn_rec + 3 * (int64_t)(b0 + gi / NAMAX));
+                const int32_t n = bst.cur;
                 const int j = gi % NAMAX;
-                const bool root = a.T.parent[n] < 0;
+                const bool root = bst.r0.y < 0;
                 int l;
                 if (root) {
                     if (j != 0) continue;
                     l = 0;
                 } else {
-                    const int d = a.T.dir[n];
+                    const int d = (bst.r0.z >> 8) & 0xff;
                     if (j >= tb.nA[d]) continue;
                     l = tb.lay[d][j];
                 }
                 // the congestion cost, from k_kappa_big
                 const int64_t kp = root ? 0 : a.F[(int64_t)n * a.NA + j];
                 if (!grp) {
-                    dp_node<GlobalState, NAMAX>(a, tb, gst, n, l, j, root, kp);
+                    dp_node<BigState, NAMAX>(a, tb, bst, n, l, j, root, kp);
                 } else {
-                    const int k = gst.nch(n);
+                    const int k = bst.nch(n);
                     if (k >= 1 && k <= 3)
-                        dp_group<GlobalState, NAMAX>(a, tb, gst, n, l, j, root, kp, sub);
+                        dp_group<BigState, NAMAX>(a, tb, bst, n, l, j, root, kp, sub);
                     else if (sub == 0)
-                        dp_node<GlobalState, NAMAX, false>(a, tb, gst, n, l, j, root, kp);
+                        dp_node<BigState, NAMAX, false>(a, tb, bst, n, l, j, root, kp);
                 }
             }
             __syncthreads();
@@ -612,8 +662,9 @@ __global__ void __launch_bounds__(kThreads) k_batched_big(DPArgs a, BArgs ba)
                 int ln = 0;
                 int32_t n = 0;
                 if (it < c) {
-                    n = ba.bn_order[b0 + it];
-                    const int32_t pp = a.T.parent[n];
+                    const int4 r0 = ba.bn_rec[3 * (int64_t)(b0 + it)];
+                    n = r0.x;
+                    const int32_t pp = r0.y;
                     const int jp = (pp < 0 || a.T.parent[pp] < 0) ? 0 : tb.jidx[ba.cur[pp] & (kMaxL - 1)];
                     trace_node(tb, gst, n, n, jp, pp < 0, ba.cur, ba.vlo, ba.vhi, ba.out_layers, ba.has_prev, &ln,
                                &changed, &old_l);
@@ -876,6 +927,8 @@ la_status launch_batched(la_batch *b, const DPArgs &a, const BArgs &ba, int32_t 
         // the big nets' congestion costs first, on the whole GPU: launched beside the tile
         // kernel, whose persistent workgroups hold every slot, they would wait for it
         const int kx = (int)std::max<int64_t>(1, std::min<int64_t>((b->max_net_nodes + 3) / 4, 512));
+        LA_TIMED(b, "k_big_records", s,
+                 hipLaunchKernelGGL(k_big_records, dim3(kx, std::min(nbig, 4096)), dim3(256), 0, s, a, ba));
         auto kbig = NA <= 4 ? k_kappa_big<4> : (NA <= 6 ? k_kappa_big<6> : k_kappa_big<8>);
         LA_TIMED(b, "k_kappa_big", s,
                  hipLaunchKernelGGL(kbig, dim3(kx, std::min(nbig, 4096)), dim3(256), 0, s, a, ba));
@@ -962,6 +1015,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             ba.bn_lvl = b->bn_lvl;
             ba.bn_lvl_off = b->bn_lvl_off;
             ba.bn_nlev = b->bn_nlev;
+            ba.bn_rec = (int4 *)b->bn_rec;
             ba.net_zw = b->net_zw;
             ba.nrec = (const uint4 *)b->nrec;
             ba.dynrec = (const uint2 *)b->dynrec;

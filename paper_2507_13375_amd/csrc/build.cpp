@@ -597,6 +597,7 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     b->n_big = (int32_t)bn_nlev.size();
     chk(upload(&b->net_big, net_big));
     chk(upload(&b->bn_order, bn_order));
+    chk(alloc(&b->bn_rec, 12 * std::max<size_t>(bn_order.size(), 1)));
     chk(upload(&b->bn_lvl, bn_lvl));
     chk(upload(&b->bn_lvl_off, bn_lvl_off));
     chk(upload(&b->bn_nlev, bn_nlev));

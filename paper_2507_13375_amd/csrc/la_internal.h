@@ -192,6 +192,7 @@ struct la_batch {
     uint32_t *nrec = nullptr, *dynrec = nullptr;
     int32_t *cnet = nullptr;
     int32_t *bn_order = nullptr, *bn_lvl = nullptr, *bn_lvl_off = nullptr, *bn_nlev = nullptr;
+    int32_t *bn_rec = nullptr;      // [bn_order positions][12]: the node's record for the level walk (per call)
     int32_t n_big = 0;
     int32_t *tier_nets = nullptr, *tier_off = nullptr, *tier_cur = nullptr, *tier_cnt = nullptr;
     int32_t *claim = nullptr;
