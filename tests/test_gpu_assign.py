@@ -184,6 +184,28 @@ def test_nets_larger_than_a_tile(form):
     assert_assign_equal(g, o, "big")
 
 
+@pytest.mark.parametrize("form", FORMS)
+def test_huge_nets_with_four_children(form):
+    # nets of 1,000-1,600 pins (up to thousands of layer-assignment nodes, one node with four
+    # children): the big-net walk reads a node's first three children from its record and the
+    # fourth from the child list
+    inst = gen.generate(240, 256, 256, 10, 23, pin_law=1, pin_max=16, placement=2, fanout_every=40,
+                        fanout_min=1000, fanout_max=1600, cap_min=4, cap_max=10)
+    T = oracle.Tree(inst)
+    par = np.asarray(T.parent)
+    kids = np.bincount(par[par >= 0], minlength=T.nodes)
+    sizes = np.diff(T.net_ptr)
+    big = sizes[np.repeat(np.arange(T.nets), sizes)] > 256
+    assert (kids[big] >= 4).any()
+    sw = gen.synthetic_weights(T.nodes, T.sinks, T.nets, seed=11, n_tiers=2)
+    o = oracle_assign(inst, sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], rounds=2)
+    g = DeviceRun(inst).assign(sw["seg_w_q10"], sw["pin_w_q10"], sw["lambda_mohm"], sw["net_tier"], num_tiers=2,
+                               rounds=2, form=form)
+    say("huge nets form=%d: %d big-net nodes, %d with four or more children" % (
+        form, big.sum(), (kids[big] >= 4).sum()))
+    assert_assign_equal(g, o, "huge")
+
+
 def test_graph_replays_match_eager_plain_form():
     # the batched rounds run as a captured hipGraph; every replay, with eager work and
     # synchronisation in between, must give the plain (eager) form's result
