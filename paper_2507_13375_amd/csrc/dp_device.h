@@ -648,20 +648,35 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
         });
         // child 1's layer, bounds and validity of every index, for the pairs of this lane
         const uint32_t pack1 = (uint32_t)l1 | (uint32_t)(lb1 + 1) << 4 | (uint32_t)(ub1 + 1) << 9 | (v1 ? 1u << 14 : 0u);
-        // each lane's own contributions; child 1's reach the pairs by broadcast
-        ChildVZ z0{0, 0}, z1o{0, 0};
-        if (v0) z0 = child_vz_j(tb, st, wd, c0, l, l0, sub);
-        if (v1) z1o = child_vz_j(tb, st, wd, c1, l, l1, sub);
+        // the pairs of this lane's choice with each of child 1's indices that pass (bit i)
+        uint32_t pm = 0;
         gx::each_lane<0>([&](auto I_) {
             constexpr int i = decltype(I_)::value;
             const uint32_t p = gx::bcast<i>(pack1, sub);
-            const ChildVZ z1{gx::bcast<i>(z1o.V, sub), gx::bcast<i>(z1o.Z, sub)};
-            if (!v0 || !((p >> 14) & 1u)) return;
             const int L2 = (int)(p & 15u), lb2 = (int)((p >> 4) & 31u) - 1, ub2 = (int)((p >> 9) & 31u) - 1;
             const int b = min(lo, min(l0, L2)), t = max(hi, max(l0, L2));
-            if (lb0 < b && t < ub0 && lb2 < b && t < ub2) {
+            if (v0 && ((p >> 14) & 1u) && lb0 < b && t < ub0 && lb2 < b && t < ub2) pm |= 1u << i;
+        });
+        // each lane's own contributions; child 1's reach the pairs by shuffles inside the group.
+        // Only the passing pairs are priced, in ascending i (the order of the tie rule): a pass
+        // per pair of the lane with the most, every lane of the branch taking part in each (the
+        // shuffles read other lanes), a lane with none left pricing nothing.
+        ChildVZ z0{0, 0}, z1o{0, 0};
+        if (v0) z0 = child_vz_j(tb, st, wd, c0, l, l0, sub);
+        if (v1) z1o = child_vz_j(tb, st, wd, c1, l, l1, sub);
+        const int gbase = __lane_id() & ~(kGroup - 1);
+        while (__any(pm != 0)) {
+            const bool have = pm != 0;
+            const int i = have ? __ffs(pm) - 1 : 0;
+            pm &= pm - 1;
+            const int src = gbase + i;
+            const int64_t V1 = __shfl((long long)z1o.V, src);
+            const uint32_t Z1 = (uint32_t)__shfl((int)z1o.Z, src);
+            const int L2 = (int)((uint32_t)__shfl((int)pack1, src) & 15u);
+            if (have) {
+                const int b = min(lo, min(l0, L2)), t = max(hi, max(l0, L2));
                 uint32_t Xc;
-                const int64_t f = value(b, t, z0.V + z1.V, (int64_t)z0.Z + z1.Z, Xc);
+                const int64_t f = value(b, t, z0.V + V1, (int64_t)z0.Z + Z1, Xc);
                 const uint32_t btc = (uint32_t)(b << 4 | t);
                 if (f < fp || (f == fp && btc < bt)) {
                     fp = f;
@@ -670,7 +685,7 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
                     sel = (uint32_t)l0 | (uint32_t)L2 << 4;
                 }
             }
-        });
+        }
     } else {
         // three children: every lane builds each child's key row from the group (one key per
         // lane), its block bounds and single-child candidates, as the serial hull order does;
