@@ -258,10 +258,10 @@ def alg1_step(la, b, inst, delay, sw, pw, lam, tier, H, layers):
 
 
 # the sources each measured kernel is built from (its traffic figure holds for these only)
-KERNEL_SOURCES = {
-    "k_batched_dp": ("batched.hip", "dp_device.h", "la_internal.h"),
-    "k_elmore_wave": ("elmore.hip", "la_internal.h"),
-    "k_adj_wave": ("elmore.hip", "la_internal.h"),
+KERNEL_SOURCES = {   # the kernel's code and the host code that lays out the records it reads
+    "k_batched_dp": ("batched.hip", "dp_device.h", "la_internal.h", "build.cpp"),
+    "k_elmore_wave": ("elmore.hip", "la_internal.h", "build.cpp"),
+    "k_adj_wave": ("elmore.hip", "la_internal.h", "build.cpp"),
 }
 
 

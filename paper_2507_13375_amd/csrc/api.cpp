@@ -446,7 +446,7 @@ void la_free_batch(la_batch *b)
                     b->sta_order, b->sta_gd, b->sta_f, b->sta_i, b->bn_order, b->bn_rec, b->bn_lvl, b->bn_lvl_off,
                     b->bn_nlev, b->tier_nets, b->tier_off, b->tier_cur, b->tier_cnt, b->claim,
                     b->cl_pre, b->cl_blk, b->cl_start, b->cl_off, b->D_alt, b->Hi,
-                    b->e_tile, b->e_wtile, b->cpin_ff, b->budget_ps, b->rdrv_k, b->e_big_nodes, b->e_big_ptr, b->qofw, b->qpart};
+                    b->e_tile, b->e_wrun, b->e_wpos, b->e_wchl, b->cpin_ff, b->budget_ps, b->rdrv_k, b->e_big_nodes, b->e_big_ptr, b->qofw, b->qpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);

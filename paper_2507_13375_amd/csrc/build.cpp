@@ -559,7 +559,46 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
     chk(upload(&b->level_nodes, level_nodes));
     chk(upload(&b->level_ptr, level_ptr));
     chk(upload(&b->e_tile, etile));
-    chk(upload(&b->e_wtile, wtile));
+    {
+        // wavefront runs: lane slot p of a run (p = lane + 64 j) takes the run's node of rank p by
+        // height (ties in node order), so each level's nodes fill as few slots as possible
+        const size_t nr = wtile.size() / 2;
+        std::vector<int32_t> wrun(std::max<size_t>(nr, 1) * 4, 0);
+        std::vector<int32_t> wpos((size_t)std::max<int64_t>(M, 1) * 4, 0);
+        std::vector<uint8_t> wchl((size_t)std::max<int64_t>(M, 1), 0);
+        std::vector<int32_t> rank;
+        for (size_t r = 0; r < nr; ++r) {
+            const int32_t n0 = wtile[2 * r], n1 = wtile[2 * r + 1], q0 = ch_ptr[n0], q1 = ch_ptr[n1];
+            const int32_t nn = n1 - n0;
+            rank.resize(nn);
+            for (int32_t u = 0; u < nn; ++u) rank[u] = u;
+            std::stable_sort(rank.begin(), rank.end(),
+                             [&](int32_t x, int32_t y) { return height[n0 + x] < height[n0 + y]; });
+            for (int32_t p = 0; p < nn; ++p) {
+                const int32_t v = n0 + rank[p];
+                const uint32_t pl = parent[v] < 0 ? 0u : (uint32_t)(parent[v] - n0 + 1);
+                int32_t *w = &wpos[(size_t)4 * (n0 + p)];
+                w[0] = (int32_t)((uint32_t)height[v] | pl << 8 | (uint32_t)(ch_ptr[v] - q0) << 16 |
+                                 (uint32_t)(ch_ptr[v + 1] - ch_ptr[v]) << 24);
+                w[1] = rank[p];
+                w[2] = sink_id[v];
+                const float cp = (float)((double)cpin[v] * 1e-3);
+                std::memcpy(&w[3], &cp, 4);
+            }
+            for (int32_t q = q0; q < q1; ++q) wchl[q] = (uint8_t)(chl[q] - n0);
+            const int32_t mh = height[n0 + rank[nn - 1]];
+            const int32_t s0max = height[n0 + rank[std::min(nn, 64) - 1]];
+            const int32_t s1min = nn > 64 ? height[n0 + rank[64]] : 255;
+            wrun[4 * r] = n0;
+            wrun[4 * r + 1] = (int32_t)((uint32_t)nn | (uint32_t)mh << 8 | (uint32_t)s0max << 16 | (uint32_t)s1min << 24);
+            wrun[4 * r + 2] = q0;
+            wrun[4 * r + 3] = q1 - q0;
+        }
+        static_assert(kWTile <= 128, "run-local ids, heights and child offsets fit a byte");
+        chk(upload(&b->e_wrun, wrun));
+        chk(upload(&b->e_wpos, wpos));
+        chk(upload(&b->e_wchl, wchl));
+    }
     {
         // pin loads in fF as single precision, rounded once from the exact product
         std::vector<float> cf(std::max<int64_t>(M, 1), 0.f);

@@ -444,96 +444,137 @@ __global__ void __launch_bounds__(kEThreads) k_edge_w_tiles(TreeDev T, const int
 
 // ---------------------------------------------------------------------------
 // Wavefront runs: the nets of at most kWTile nodes, a run of whole nets per one-wavefront
-// workgroup.  Lane i keeps nodes i, i + 64, i + 128 and i + 192 of the run in registers (their
-// records are read coalesced, once), the child lists as run-local ids and the sweep state sit in
-// LDS, and each level costs one barrier of a single wavefront.  Per node the operations are those
+// workgroup.  Lane slot p = lane + 64 j holds the run's node of rank p by height, from one packed
+// record read coalesced, so a level's nodes sit in as few slots as possible and a level skips the
+// slots that hold none of its heights.  The child list (run-local ids) and the sweep state sit in
+// LDS, and each level costs one barrier of a single wavefront.  A wavefront takes runs
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next run's records are read as the current run
+// starts and its inputs (which need the records) after the current run's first sweep, so a
+// run's loads are in flight during its predecessor's levels.  Per node the operations are those
 // of the per-level kernels, in the same order.
 // ---------------------------------------------------------------------------
 constexpr int kWPer = kWTile / 64;
 
-__device__ __forceinline__ int32_t wave_max(int32_t x)
-{
-    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
-    return x;
-}
-
-struct WaveRun {
-    int32_t n0, nn, maxh;
-    int32_t hgt[kWPer];   // height, -1 past the run's end
-    int32_t par[kWPer];   // run-local parent, -1 at the root
-    int32_t sk[kWPer];    // sink id or -1
-    int32_t c0[kWPer], c1[kWPer];   // child entries [c0, c1) of the run-local child list
+// One run: its descriptor and, per lane slot, its node's record, run-local id, sink id, pin load
+// and one child entry of the run
+struct RunIn {
+    int32_t n0, nn, maxh, s0max, s1min, nq;
+    uint32_t rec[kWPer];   // height | (run-local parent + 1) << 8 | first child entry << 16 | children << 24
+    int32_t u[kWPer];      // run-local node id
+    int32_t sk[kWPer];     // sink id, -1 if none
+    float cp[kWPer];       // pin load (fF)
+    uint32_t ch[kWPer];    // run-local node id of the run's child entry lane + 64 j
+    __device__ int hgt(int j) const { return (int)(rec[j] & 0xffu); }
+    __device__ int par(int j) const { return (int)((rec[j] >> 8) & 0xffu) - 1; }
+    __device__ int c0(int j) const { return (int)((rec[j] >> 16) & 0xffu); }
+    __device__ int c1(int j) const { return c0(j) + (int)(rec[j] >> 24); }
+    // slot j holds a node of height h at all (the same answer in every lane)
+    __device__ bool holds(int j, int32_t h) const { return j == 0 ? h <= s0max : h >= s1min; }
 };
 
-// The run's node records into lane slots, its child list into `chl` (run-local ids).
-__device__ __forceinline__ void wave_run_load(const TreeDev &T, const int32_t *height, const int32_t *runs,
-                                              int32_t ri, WaveRun &w, int16_t *chl)
+__device__ __forceinline__ void run_in(const int4 *runs, const int4 *wpos, const uint8_t *wchl, int32_t ri,
+                                       RunIn &a)
 {
     const int lane = threadIdx.x;
-    w.n0 = runs[2 * ri];
-    w.nn = runs[2 * ri + 1] - w.n0;
-    const int32_t q0 = T.ch_ptr[w.n0], nq = T.ch_ptr[w.n0 + w.nn] - q0;
-    int32_t mh = 0;
+    const int4 d = runs[ri];
+    a.n0 = d.x;
+    a.nn = d.y & 0xff;
+    a.maxh = (d.y >> 8) & 0xff;
+    a.s0max = (d.y >> 16) & 0xff;
+    a.s1min = (d.y >> 24) & 0xff;
+    a.nq = d.w;
 #pragma unroll
     for (int j = 0; j < kWPer; ++j) {
-        const int32_t u = lane + 64 * j, v = w.n0 + u;
-        w.hgt[j] = -1;
-        w.par[j] = -1;
-        w.sk[j] = -1;
-        w.c0[j] = w.c1[j] = 0;
-        if (u < w.nn) {
-            w.hgt[j] = height[v];
-            const int32_t p = T.parent[v];
-            w.par[j] = p < 0 ? -1 : p - w.n0;
-            w.sk[j] = T.sink_id[v];
-            w.c0[j] = T.ch_ptr[v] - q0;
-            w.c1[j] = T.ch_ptr[v + 1] - q0;
-            mh = max(mh, w.hgt[j]);
+        const int32_t p = lane + 64 * j;
+        a.rec[j] = 0xffu;   // height 255: in no level
+        a.u[j] = 0;
+        a.sk[j] = -1;
+        a.cp[j] = 0.f;
+        a.ch[j] = 0;
+        if (p < a.nn) {
+            const int4 w = wpos[a.n0 + p];
+            a.rec[j] = (uint32_t)w.x;
+            a.u[j] = w.y;
+            a.sk[j] = w.z;
+            a.cp[j] = __int_as_float(w.w);
         }
+        if (p < a.nq) a.ch[j] = wchl[d.z + p];
     }
-    for (int32_t i = lane; i < nq; i += 64) chl[i] = (int16_t)(T.ch[q0 + i] - w.n0);
-    w.maxh = wave_max(mh);
 }
 
-__global__ void __launch_bounds__(64) k_elmore_wave(TreeDev T, const int32_t *runs, int32_t nruns,
-                                                    const int32_t *height, const float *R, const float *C, float *S,
-                                                    float *Slo, float *delay)
+// the run's child list into LDS
+__device__ __forceinline__ void run_children(const RunIn &a, uint8_t *chl)
 {
-    __shared__ float cc[kWTile], sh[kWTile], sl[kWTile], th[kWTile], tl[kWTile];
-    __shared__ int16_t chl[kWTile];
-    const int lane = threadIdx.x;
-    for (int32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
-        WaveRun w;
-        wave_run_load(T, height, runs, ri, w, chl);
-        float r[kWPer], c[kWPer], ce[kWPer], re[kWPer], cp[kWPer], xh[kWPer], xl[kWPer];
 #pragma unroll
-        for (int j = 0; j < kWPer; ++j) {
-            const int32_t u = lane + 64 * j, v = w.n0 + u;
-            r[j] = c[j] = ce[j] = re[j] = cp[j] = xh[j] = xl[j] = 0.f;
-            if (u < w.nn) {
-                r[j] = R[v];
-                c[j] = C[v];
-                cc[u] = c[j];
-                if (w.sk[j] >= 0) {
-                    ce[j] = C[T.nodes + w.sk[j]];
-                    re[j] = R[T.nodes + w.sk[j]];
-                    cp[j] = T.cpin_ff[v];
-                }
-            }
+    for (int j = 0; j < kWPer; ++j)
+        if ((int32_t)threadIdx.x + 64 * j < a.nq) chl[threadIdx.x + 64 * j] = (uint8_t)a.ch[j];
+}
+
+// Inputs of the forward sweep per lane slot: the segment's R and C; at a sink pin its pin
+// edge's C and R
+struct FwdIn {
+    float r[kWPer], c[kWPer], ce[kWPer], re[kWPer];
+};
+
+__device__ __forceinline__ void fwd_in(const TreeDev &T, const RunIn &a, const float *R, const float *C, FwdIn &f)
+{
+#pragma unroll
+    for (int j = 0; j < kWPer; ++j) {
+        f.r[j] = f.c[j] = f.ce[j] = f.re[j] = 0.f;
+        if ((int32_t)threadIdx.x + 64 * j < a.nn) {
+            f.r[j] = R[a.n0 + a.u[j]];
+            f.c[j] = C[a.n0 + a.u[j]];
         }
+        if (a.sk[j] >= 0) {
+            f.ce[j] = C[T.nodes + a.sk[j]];
+            f.re[j] = R[T.nodes + a.sk[j]];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) k_elmore_wave(TreeDev T, const int4 *runs, const int4 *wpos,
+                                                    const uint8_t *wchl, int32_t nruns, const float *R, const float *C,
+                                                    float *S, float *Slo, float *delay)
+{
+    __shared__ float cc[kWTile], sh[kWTile], sl[kWTile], th[kWTile], tl[kWTile], dl[kWTile];
+    __shared__ int32_t skl[kWTile];
+    __shared__ uint8_t chl[kWTile];
+    const int lane = threadIdx.x;
+    int32_t ri = blockIdx.x;
+    if (ri >= nruns) return;
+    RunIn a;
+    FwdIn f;
+    run_in(runs, wpos, wchl, ri, a);
+    fwd_in(T, a, R, C, f);
+    for (;;) {
+        const int32_t rn = ri + (int32_t)gridDim.x;
+        const bool more = rn < nruns;
+        RunIn an;
+        FwdIn fn;
+        if (more) run_in(runs, wpos, wchl, rn, an);
+        run_children(a, chl);
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j)
+            if (lane + 64 * j < a.nn) {
+                cc[a.u[j]] = f.c[j];
+                skl[a.u[j]] = a.sk[j];
+            }
         __syncthreads();
         // S(v) = sum over RC children of (C + S), bottom-up
-        for (int32_t h = 0; h <= w.maxh; ++h) {
+        float xh[kWPer], xl[kWPer];
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) xh[j] = xl[j] = 0.f;
+        for (int32_t h = 0; h <= a.maxh; ++h) {
 #pragma unroll
             for (int j = 0; j < kWPer; ++j) {
-                if (w.hgt[j] != h) continue;
-                const int32_t u = lane + 64 * j;
+                if (!a.holds(j, h) || a.hgt(j) != h) continue;
+                const int32_t u = a.u[j];
                 ff x{0.f, 0.f};
-                if (w.sk[j] >= 0) {
-                    x = ff_add(x, ce[j]);
-                    x = ff_add(x, cp[j]);
+                if (a.sk[j] >= 0) {
+                    x = ff_add(x, f.ce[j]);
+                    x = ff_add(x, a.cp[j]);
                 }
-                for (int32_t q = w.c0[j]; q < w.c1[j]; ++q) {
+                for (int32_t q = a.c0(j); q < a.c1(j); ++q) {
                     const int32_t cu = chl[q];
                     x = ff_add(x, cc[cu]);
                     x = ff_add(x, ff{sh[cu], sl[cu]});
@@ -544,32 +585,44 @@ __global__ void __launch_bounds__(64) k_elmore_wave(TreeDev T, const int32_t *ru
             }
             __syncthreads();
         }
+        // the next run's inputs: its records have arrived during the sweep
+        if (more) fwd_in(T, an, R, C, fn);
+        // results leave in node order (coalesced), from LDS
 #pragma unroll
         for (int j = 0; j < kWPer; ++j) {
-            const int32_t u = lane + 64 * j;
-            if (u < w.nn) {
-                S[w.n0 + u] = xh[j];
-                Slo[w.n0 + u] = xl[j];
+            const int32_t p = lane + 64 * j;
+            if (p < a.nn) {
+                S[a.n0 + p] = sh[p];
+                Slo[a.n0 + p] = sl[p];
             }
         }
         // t(v) = t(parent) + R_v (C_v/2 + S_v), top-down; delay at sink pins
-        for (int32_t h = w.maxh; h >= 0; --h) {
+        for (int32_t h = a.maxh; h >= 0; --h) {
 #pragma unroll
             for (int j = 0; j < kWPer; ++j) {
-                if (w.hgt[j] != h) continue;
-                const int32_t u = lane + 64 * j, p = w.par[j];
+                if (!a.holds(j, h) || a.hgt(j) != h) continue;
+                const int32_t u = a.u[j], p = a.par(j);
                 const ff up = p < 0 ? ff{0.f, 0.f} : ff{th[p], tl[p]};
-                const ff load = ff_add(ff{xh[j], xl[j]}, 0.5f * c[j]);
-                const ff tv = ff_norm(ff_add(up, ff_mul(r[j], load)));
+                const ff load = ff_add(ff{xh[j], xl[j]}, 0.5f * f.c[j]);
+                const ff tv = ff_norm(ff_add(up, ff_mul(f.r[j], load)));
                 th[u] = tv.hi;
                 tl[u] = tv.lo;
-                if (w.sk[j] >= 0) {
-                    const ff pl = ff_add(ff{0.5f * ce[j], 0.f}, cp[j]);
-                    delay[w.sk[j]] = ff_val(ff_add(tv, ff_mul(re[j], pl)));
+                if (a.sk[j] >= 0) {
+                    const ff pl = ff_add(ff{0.5f * f.ce[j], 0.f}, a.cp[j]);
+                    dl[u] = ff_val(ff_add(tv, ff_mul(f.re[j], pl)));
                 }
             }
             __syncthreads();
         }
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) {
+            const int32_t p = lane + 64 * j;
+            if (p < a.nn && skl[p] >= 0) delay[skl[p]] = dl[p];
+        }
+        if (!more) break;
+        ri = rn;
+        a = an;
+        f = fn;
     }
 }
 
@@ -592,42 +645,65 @@ __device__ __forceinline__ int32_t adj_lambda(float sig_hi, float sig_lo)
     return x <= 0.f ? 0 : (x >= 2147483520.f ? 2147483647 : (int32_t)x);
 }
 
+// Inputs of the reverse sweep per lane slot: the segment's R and the sink's dJ/d delay
+struct AdjIn {
+    float r[kWPer], gk[kWPer];
+};
+
+__device__ __forceinline__ void adj_in(const RunIn &a, const float *R, const float *gbar, AdjIn &x)
+{
+#pragma unroll
+    for (int j = 0; j < kWPer; ++j) {
+        x.r[j] = (int32_t)threadIdx.x + 64 * j < a.nn ? R[a.n0 + a.u[j]] : 0.f;
+        x.gk[j] = a.sk[j] >= 0 ? gbar[a.sk[j]] : 0.f;
+    }
+}
+
 // GRADS: the R / C gradients are written (la_elmore_backward); without them (the adjoint
 // weights) the kernel keeps fewer registers live and runs more waves per SIMD, and, given
-// seg_w, writes the weights of its nodes and sinks itself.
+// seg_w, writes the weights of its nodes and sinks itself.  As in k_elmore_wave, the next run's
+// inputs are read during the current run's sweeps.
 template <bool GRADS>
-__global__ void __launch_bounds__(64) k_adj_wave(TreeDev T, const int32_t *runs, int32_t nruns,
-                                                 const int32_t *height, const float *R, const float *C,
+__global__ void __launch_bounds__(64, GRADS ? 1 : 8) k_adj_wave(TreeDev T, const int4 *runs, const int4 *wpos,
+                                                 const uint8_t *wchl, int32_t nruns, const float *R, const float *C,
                                                  const float *S, const float *Slo, const float *gbar, float *G,
                                                  float *Glo, float *Sig, float *Siglo, float *dR, float *dC,
                                                  uint16_t *seg_w, uint16_t *pin_w, int32_t *lam)
 {
     __shared__ float gh[kWTile], gl[kWTile], qh[kWTile], ql[kWTile];
-    __shared__ int16_t chl[kWTile];
+    __shared__ int32_t skl[kWTile], lml[kWTile];
+    __shared__ uint16_t pwl[kWTile];
+    __shared__ uint8_t chl[kWTile];
     const int lane = threadIdx.x;
-    for (int32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
-        WaveRun w;
-        wave_run_load(T, height, runs, ri, w, chl);
-        float r[kWPer], gk[kWPer], xh[kWPer], xl[kWPer];
+    int32_t ri = blockIdx.x;
+    if (ri >= nruns) return;
+    RunIn a;
+    AdjIn in;
+    run_in(runs, wpos, wchl, ri, a);
+    adj_in(a, R, gbar, in);
+    for (;;) {
+        const int32_t rn = ri + (int32_t)gridDim.x;
+        const bool more = rn < nruns;
+        RunIn an;
+        AdjIn inn;
+        if (more) run_in(runs, wpos, wchl, rn, an);
+        run_children(a, chl);
 #pragma unroll
-        for (int j = 0; j < kWPer; ++j) {
-            const int32_t u = lane + 64 * j;
-            r[j] = gk[j] = xh[j] = xl[j] = 0.f;
-            if (u < w.nn) {
-                r[j] = R[w.n0 + u];
-                if (w.sk[j] >= 0) gk[j] = gbar[w.sk[j]];
-            }
-        }
+        for (int j = 0; j < kWPer; ++j)
+            if (lane + 64 * j < a.nn) skl[a.u[j]] = a.sk[j];
         __syncthreads();
         // G(v) = sum of g below v, bottom-up
-        for (int32_t h = 0; h <= w.maxh; ++h) {
+        float xh[kWPer], xl[kWPer];
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) xh[j] = xl[j] = 0.f;
+        for (int32_t h = 0; h <= a.maxh; ++h) {
 #pragma unroll
             for (int j = 0; j < kWPer; ++j) {
-                if (w.hgt[j] != h) continue;
-                const int32_t u = lane + 64 * j;
+                if (!a.holds(j, h) || a.hgt(j) != h) continue;
+                const int32_t u = a.u[j];
                 ff g{0.f, 0.f};
-                if (w.sk[j] >= 0) g = ff_add(g, gk[j]);
-                for (int32_t q = w.c0[j]; q < w.c1[j]; ++q) {
+                if (a.sk[j] >= 0) g = ff_add(g, in.gk[j]);
+                for (int32_t q = a.c0(j); q < a.c1(j); ++q) {
                     const int32_t cu = chl[q];
                     g = ff_add(g, ff{gh[cu], gl[cu]});
                 }
@@ -637,76 +713,94 @@ __global__ void __launch_bounds__(64) k_adj_wave(TreeDev T, const int32_t *runs,
             }
             __syncthreads();
         }
+        if (more) adj_in(an, R, gbar, inn);
+        // results leave in node order (coalesced), from LDS
 #pragma unroll
         for (int j = 0; j < kWPer; ++j) {
-            const int32_t u = lane + 64 * j;
-            if (u < w.nn) {
-                G[w.n0 + u] = xh[j];
-                Glo[w.n0 + u] = xl[j];
+            const int32_t p = lane + 64 * j;
+            if (p < a.nn) {
+                G[a.n0 + p] = gh[p];
+                Glo[a.n0 + p] = gl[p];
             }
         }
         // Sig(v) = Sig(parent) + R_v G(v), top-down, and the R / C gradients
-        for (int32_t h = w.maxh; h >= 0; --h) {
+        for (int32_t h = a.maxh; h >= 0; --h) {
 #pragma unroll
             for (int j = 0; j < kWPer; ++j) {
-                if (w.hgt[j] != h) continue;
-                const int32_t u = lane + 64 * j, v = w.n0 + u, p = w.par[j];
+                if (!a.holds(j, h) || a.hgt(j) != h) continue;
+                const int32_t u = a.u[j], v = a.n0 + u, p = a.par(j);
                 const ff up = p < 0 ? ff{0.f, 0.f} : ff{qh[p], ql[p]};
                 const ff g{xh[j], xl[j]};
-                const ff sv = ff_norm(ff_add(up, ff_mul(r[j], g)));
+                const ff sv = ff_norm(ff_add(up, ff_mul(in.r[j], g)));
                 qh[u] = sv.hi;
                 ql[u] = sv.lo;
-                Sig[v] = sv.hi;
-                Siglo[v] = sv.lo;
                 if (!GRADS && seg_w) {
-                    seg_w[v] = adj_q10(xh[j], xl[j]);
-                    lam[v] = p < 0 ? 0 : adj_lambda(up.hi, up.lo);
-                    if (w.sk[j] >= 0) pin_w[w.sk[j]] = adj_q10(gk[j], 0.f);
+                    lml[u] = p < 0 ? 0 : adj_lambda(up.hi, up.lo);
+                    if (a.sk[j] >= 0) pwl[u] = adj_q10(in.gk[j], 0.f);
                 }
                 if (GRADS) {
                     const float cv = C[v];
                     if (dR) dR[v] = ff_val(ff_mul(ff_val(g), ff_add(ff{S[v], Slo[v]}, 0.5f * cv)));
-                    if (dC) dC[v] = ff_val(ff_add(up, 0.5f * r[j] * ff_val(g)));
-                    const int32_t k = w.sk[j];
+                    if (dC) dC[v] = ff_val(ff_add(up, 0.5f * in.r[j] * ff_val(g)));
+                    const int32_t k = a.sk[j];
                     if (k >= 0) {
                         const int64_t e = T.nodes + k;
-                        if (dR) dR[e] = gk[j] * (0.5f * C[e] + T.cpin_ff[v]);
-                        if (dC) dC[e] = ff_val(ff_add(sv, 0.5f * R[e] * gk[j]));
+                        if (dR) dR[e] = in.gk[j] * (0.5f * C[e] + T.cpin_ff[v]);
+                        if (dC) dC[e] = ff_val(ff_add(sv, 0.5f * R[e] * in.gk[j]));
                     }
                 }
             }
             __syncthreads();
         }
+#pragma unroll
+        for (int j = 0; j < kWPer; ++j) {
+            const int32_t p = lane + 64 * j, v = a.n0 + p;
+            if (p < a.nn) {
+                Sig[v] = qh[p];
+                Siglo[v] = ql[p];
+                if (!GRADS && seg_w) {
+                    seg_w[v] = adj_q10(gh[p], gl[p]);
+                    lam[v] = lml[p];
+                    if (skl[p] >= 0) pin_w[skl[p]] = pwl[p];
+                }
+            }
+        }
+        if (!more) break;
+        ri = rn;
+        a = an;
+        in = inn;
     }
 }
 
 // Eq. 5 on the wavefront runs: the largest pin weight below each segment, bottom-up in LDS
-__global__ void __launch_bounds__(64) k_edge_w_wave(TreeDev T, const int32_t *runs, int32_t nruns,
-                                                    const int32_t *height, const uint16_t *pin_w, uint16_t *seg_w)
+__global__ void __launch_bounds__(64) k_edge_w_wave(TreeDev T, const int4 *runs, const int4 *wpos,
+                                                    const uint8_t *wchl, int32_t nruns, const uint16_t *pin_w,
+                                                    uint16_t *seg_w)
 {
     __shared__ uint16_t wl[kWTile];
-    __shared__ int16_t chl[kWTile];
+    __shared__ uint8_t chl[kWTile];
     const int lane = threadIdx.x;
     for (int32_t ri = blockIdx.x; ri < nruns; ri += gridDim.x) {
-        WaveRun w;
-        wave_run_load(T, height, runs, ri, w, chl);
+        RunIn a;
+        run_in(runs, wpos, wchl, ri, a);
+        run_children(a, chl);
         uint16_t x[kWPer];
 #pragma unroll
-        for (int j = 0; j < kWPer; ++j) x[j] = w.sk[j] >= 0 ? pin_w[w.sk[j]] : 0;
+        for (int j = 0; j < kWPer; ++j) x[j] = a.sk[j] >= 0 ? pin_w[a.sk[j]] : 0;
         __syncthreads();
-        for (int32_t h = 0; h <= w.maxh; ++h) {
+        for (int32_t h = 0; h <= a.maxh; ++h) {
 #pragma unroll
             for (int j = 0; j < kWPer; ++j) {
-                if (w.hgt[j] != h) continue;
+                if (!a.holds(j, h) || a.hgt(j) != h) continue;
                 uint16_t m = x[j];
-                for (int32_t q = w.c0[j]; q < w.c1[j]; ++q) m = max(m, wl[chl[q]]);
-                wl[lane + 64 * j] = x[j] = m;
+                for (int32_t q = a.c0(j); q < a.c1(j); ++q) m = max(m, wl[chl[q]]);
+                wl[a.u[j]] = x[j] = m;
             }
             __syncthreads();
         }
 #pragma unroll
         for (int j = 0; j < kWPer; ++j)
-            if (lane + 64 * j < w.nn) seg_w[w.n0 + lane + 64 * j] = x[j];
+            if (lane + 64 * j < a.nn) seg_w[a.n0 + a.u[j]] = x[j];
     }
 }
 
@@ -987,8 +1081,9 @@ la_status elmore_forward(la_batch *b, const float *R, const float *C, float *del
     // small nets in wavefront runs, the larger ones in workgroup tiles, the others level by level
     if (b->e_nwtiles > 0)
         LA_TIMED(b, "k_elmore_wave", b->stream,
-                 hipLaunchKernelGGL(k_elmore_wave, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, b->e_wtile,
-                                    b->e_nwtiles, b->height, R, C, b->el_S, b->el_Slo, delay));
+                 hipLaunchKernelGGL(k_elmore_wave, dim3(wave_grid(b)), dim3(64), 0, b->stream, T,
+                                    (const int4 *)b->e_wrun, (const int4 *)b->e_wpos, b->e_wchl, b->e_nwtiles, R, C, b->el_S,
+                                    b->el_Slo, delay));
     if (b->e_ntiles > 0)
         LA_TIMED(b, "k_elmore_tiles", b->stream,
                  hipLaunchKernelGGL(k_elmore_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T, b->e_tile,
@@ -1027,8 +1122,8 @@ la_status elmore_backward(la_batch *b, const float *g, bool from_dslack, float *
     if (b->e_nwtiles > 0)
         LA_TIMED(b, "k_adj_wave", b->stream, {
             auto kern = (dR || dC) ? k_adj_wave<true> : k_adj_wave<false>;
-            hipLaunchKernelGGL(kern, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, b->e_wtile, b->e_nwtiles,
-                               b->height, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, gbar, b->el_G, Glo, b->el_Sig,
+            hipLaunchKernelGGL(kern, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, (const int4 *)b->e_wrun,
+                               (const int4 *)b->e_wpos, b->e_wchl, b->e_nwtiles, b->fwd_R, b->fwd_C, b->el_S, b->el_Slo, gbar, b->el_G, Glo, b->el_Sig,
                                Siglo, dR, dC, (dR || dC) ? nullptr : seg_w, pin_w, lam);
         });
     if (b->e_ntiles > 0)
@@ -1068,8 +1163,8 @@ la_status timing_weights(la_batch *b, const float *delay, int32_t mode, uint16_t
     if (mode == LA_WEIGHTS_PLAIN) {
         if (b->e_nwtiles > 0)
             LA_TIMED(b, "k_edge_w_wave", b->stream,
-                     hipLaunchKernelGGL(k_edge_w_wave, dim3(wave_grid(b)), dim3(64), 0, b->stream, T, b->e_wtile,
-                                        b->e_nwtiles, b->height, pin_w, seg_w));
+                     hipLaunchKernelGGL(k_edge_w_wave, dim3(wave_grid(b)), dim3(64), 0, b->stream, T,
+                                        (const int4 *)b->e_wrun, (const int4 *)b->e_wpos, b->e_wchl, b->e_nwtiles, pin_w, seg_w));
         if (b->e_ntiles > 0)
             LA_TIMED(b, "k_edge_w_tiles", b->stream,
                      hipLaunchKernelGGL(k_edge_w_tiles, dim3(tile_grid(b)), dim3(kEThreads), 0, b->stream, T,

@@ -143,7 +143,15 @@ struct la_batch {
     // the nets no tile takes
     int32_t *e_tile = nullptr, *e_big_nodes = nullptr, *e_big_ptr = nullptr;
     int32_t e_ntiles = 0;
-    int32_t *e_wtile = nullptr;         // wavefront runs ([start, end) pairs) of the nets of <= kWTile nodes
+    // wavefront runs of the nets of <= kWTile nodes: per run {first node, node count | max height
+    // << 8 | the highest height in lane slots 0-63 << 16 | the lowest in slots 64-127 << 24, first
+    // child entry, child entries}; per lane slot of a run (index first node + slot) {height |
+    // (run-local parent + 1) << 8 | first child entry inside the run's entries << 16 | child
+    // count << 24, run-local node id, sink id or -1, pin load in fF as float bits}; per child entry
+    // of a run its run-local node id
+    int32_t *e_wrun = nullptr;
+    int32_t *e_wpos = nullptr;
+    uint8_t *e_wchl = nullptr;
     int32_t e_nwtiles = 0;
     float *cpin_ff = nullptr;           // [nodes] pin load in fF (float)
     float *budget_ps = nullptr, *rdrv_k = nullptr;   // [nets] budget in ps, driver resistance in kOhm (float)
