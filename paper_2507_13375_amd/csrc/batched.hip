@@ -68,6 +68,26 @@ struct LdsState {
     __device__ uint32_t pinw(int32_t s) const { return ZW ? 0u : (uint32_t)pinw_[s]; }
 };
 
+// The tile state with the current DP item's node header in registers: its child count and first
+// child, and the first child's direction, so that the child's state can be read before its record.
+template <class Base>
+struct ItemState : Base {
+    int32_t cur, c0, k, cdir;
+    __device__ ItemState(const Base &b, int32_t u, uint32_t hd)
+        : Base(b), cur(u), c0((int32_t)((hd >> 8) & 0xffu)), k((int32_t)((hd >> 16) & 0xffu)),
+          cdir((int32_t)((hd >> 26) & 1u))
+    {
+    }
+    __device__ int nch(int32_t s) const { return s == cur ? k : Base::nch(s); }
+    __device__ int32_t ch_state(int32_t s, int q) const { return (s == cur && q == 0) ? c0 : Base::ch_state(s, q); }
+    __device__ NodeIn in(int32_t s) const
+    {
+        NodeIn r = Base::in(s);
+        if (k > 0 && s == c0) r.dir = cdir;
+        return r;
+    }
+};
+
 // LDS layout of one tile (byte offsets), shared by the host launch and the kernel.  The
 // congestion table (L x 2 x 64 int32) follows at LUT; the launch sizes it by L.
 template <int NAMAX, int CAP>
@@ -85,8 +105,8 @@ struct Tile {
     static constexpr size_t PAR = BOOK + (size_t)kBook * 4;         // int16 [CAP]
     static constexpr size_t CHP = PAR + (size_t)CAP * 2;           // int16 [CAP+2]
     static constexpr size_t CHL = CHP + (size_t)(CAP + 2) * 2;     // int16 [CAP]
-    static constexpr size_t ORD = CHL + (size_t)CAP * 2;           // int16 [CAP]
-    static constexpr size_t KEY = ORD + (size_t)CAP * 2;           // int16 [CAP] bucket of each node
+    static constexpr size_t ORD = CHL + (size_t)CAP * 2;           // uint32 [CAP] item header by order position
+    static constexpr size_t KEY = ORD + (size_t)CAP * 4;           // int16 [CAP] bucket of each node
     static constexpr size_t PINW = KEY + (size_t)CAP * 2;          // uint16 [CAP]
     static constexpr size_t BT = PINW + (size_t)CAP * 2;           // uint8 [CAP][NAMAX] b << 4 | t
     static constexpr size_t SEL = BT + (size_t)CAP * NAMAX;        // uint8 [CAP][NAMAX]
@@ -168,7 +188,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 || CAP > 192 ? 3 : 4) k_ba
     int16_t *par = (int16_t *)(smem + TL::PAR);
     int16_t *chp = (int16_t *)(smem + TL::CHP);
     int16_t *chl = (int16_t *)(smem + TL::CHL);
-    int16_t *order = (int16_t *)(smem + TL::ORD);
+    uint32_t *hdr = (uint32_t *)(smem + TL::ORD);
     int16_t *key = (int16_t *)(smem + TL::KEY);
     uint16_t *pinw = (uint16_t *)(smem + TL::PINW);
     uint8_t *bt = smem + TL::BT;
@@ -335,7 +355,15 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 || CAP > 192 ? 3 : 4) k_ba
                 return lo_;
             };
             for (int32_t u = threadIdx.x; u < nn; u += blockDim.x) {
-                order[atomicAdd(&kst[key[u]], 1)] = (int16_t)u;
+                {
+                    // the item header of u at its (height, class) position: node, first child,
+                    // child count, root flag, direction, the first child's direction
+                    const int32_t kq = chp[u + 1] - chp[u];
+                    const int32_t c0 = kq > 0 ? chl[chp[u]] : 0;
+                    hdr[atomicAdd(&kst[key[u]], 1)] =
+                        (uint32_t)u | (uint32_t)c0 << 8 | (uint32_t)min(kq, 255) << 16 | (par[u] < 0 ? 1u << 24 : 0u) |
+                        (uint32_t)(fld[u] >> 4) << 25 | (kq > 0 ? (uint32_t)(fld[c0] >> 4) << 26 : 0u);
+                }
                 if (mapped)
                     for (int32_t q = lenp[u]; q < lenp[u + 1]; ++q) smap[q] = (uint8_t)u;
             }
@@ -423,31 +451,35 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 || CAP > 192 ? 3 : 4) k_ba
                         pos = c2b + gi / NAMAX;
                         j = gi % NAMAX;
                     }
-                    const int32_t u = order[pos];
-                    const bool root = par[u] < 0;
+                    const uint32_t hd = hdr[pos];
+                    const int32_t u = (int32_t)(hd & 0xffu);
+                    const bool root = (hd >> 24) & 1u;
                     int l;
                     if (root) {
                         if (j != 0) continue;
                         l = 0;
                     } else {
-                        const int d = fld[u] >> 4;
+                        const int d = (hd >> 25) & 1u;
                         if (j >= tb.nA[d]) continue;
                         l = tb.lay[d][j];
                     }
                     const int64_t kp = root ? 0 : kap[u * NAMAX + j];
-                    const int k = st.nch(u);
+                    const int k = (int)((hd >> 16) & 0xffu);
+                    const ItemState<LdsState<NAMAX>> ist(st, u, hd);
+                    const ItemState<LdsState<NAMAX, true>> istz(stz, u, hd);
                     // group items with one to three children are lane-parallel; the others run
                     // on one lane (the group's first)
                     if (sub >= 0 && a.w.w_via > 0 && k >= 1 && k <= 3) {
                         if (zt)
-                            dp_group<LdsState<NAMAX, true>, NAMAX>(a, tb, stz, u, l, j, root, kp, sub);
+                            dp_group<ItemState<LdsState<NAMAX, true>>, NAMAX>(a, tb, istz, u, l, j, root, kp, sub);
                         else
-                            dp_group<LdsState<NAMAX>, NAMAX>(a, tb, st, u, l, j, root, kp, sub);
+                            dp_group<ItemState<LdsState<NAMAX>>, NAMAX>(a, tb, ist, u, l, j, root, kp, sub);
                     } else if (sub <= 0) {   // no child count 2..3 here while the via weight is positive
                         if (zt)
-                            dp_node<LdsState<NAMAX, true>, NAMAX, true, false>(a, tb, stz, u, l, j, root, kp);
+                            dp_node<ItemState<LdsState<NAMAX, true>>, NAMAX, true, false>(a, tb, istz, u, l, j, root,
+                                                                                          kp);
                         else
-                            dp_node<LdsState<NAMAX>, NAMAX, true, false>(a, tb, st, u, l, j, root, kp);
+                            dp_node<ItemState<LdsState<NAMAX>>, NAMAX, true, false>(a, tb, ist, u, l, j, root, kp);
                     }
                 }
                 __syncthreads();
@@ -456,7 +488,7 @@ __global__ void __launch_bounds__(kThreads, NAMAX > 6 || CAP > 192 ? 3 : 4) k_ba
             for (int32_t h = maxlev; h >= 0; --h) {
                 const int32_t lb = h == 0 ? 0 : kst[4 * h - 1], le = kst[4 * h + 3];
                 for (int32_t it = lb + threadIdx.x; it < le; it += blockDim.x) {
-                    const int32_t u = order[it];
+                    const int32_t u = (int32_t)(hdr[it] & 0xffu);
                     const int32_t pu = par[u];
                     int ln;
                     ent[u] = (uint8_t)trace_choice(tb, st, u, (pu < 0 || par[pu] < 0) ? 0 : ent[pu], pu < 0, &ln);

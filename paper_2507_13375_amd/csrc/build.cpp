@@ -590,7 +590,8 @@ la_status build_batch(const la_nets *nets, const la_grid *grid, const la_layer_r
             const int32_t s0max = height[n0 + rank[std::min(nn, 64) - 1]];
             const int32_t s1min = nn > 64 ? height[n0 + rank[64]] : 255;
             wrun[4 * r] = n0;
-            wrun[4 * r + 1] = (int32_t)((uint32_t)nn | (uint32_t)mh << 8 | (uint32_t)s0max << 16 | (uint32_t)s1min << 24);
+            wrun[4 * r + 1] =
+                (int32_t)((uint32_t)nn | (uint32_t)mh << 8 | (uint32_t)s0max << 16 | (uint32_t)s1min << 24);
             wrun[4 * r + 2] = q0;
             wrun[4 * r + 3] = q1 - q0;
         }
