@@ -687,34 +687,49 @@ __device__ __forceinline__ void dp_group(const DPArgs &a, const LayerTab &tb, co
             }
         }
     } else {
-        // three children: every lane builds each child's key row from the group (one key per
-        // lane), its block bounds and single-child candidates, as the serial hull order does;
-        // lane sub then takes the combinations whose first choice is index sub
+        // three children: per child, lane sub finds the block bounds of the child's index sub
+        // (from the group's keys, one broadcast at a time) and whether that index is a
+        // single-child candidate (prefix / suffix minima across the group, as for one child);
+        // the group then shares both, so every lane holds each child's bounds and candidate
+        // mask -- the values the serial hull order computes -- and lane sub takes the
+        // combinations whose first choice is index sub
         uint32_t lyp[3], cand[3];
         uint64_t bnd[3];
         ChildIn cq[3];
         int nq[3];
         cq[0] = c0;
+        const int gbase = __lane_id() & ~(kGroup - 1);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             if (q > 0) cq[q] = child_in(st, s, q);
-            nq[q] = tb.nA[cq[q].dir];
+            const int dq = cq[q].dir;
+            nq[q] = tb.nA[dq];
             const bool vq = sub < nq[q];
-            const int lq = tb.lay[cq[q].dir][vq ? sub : 0];
+            const int lq = tb.lay[dq][vq ? sub : 0];
             const int64_t kq = q == 0 ? k0 : (vq ? child_key_j(tb, st, wd, cq[q], l, lq, sub) : INT64_MAX);
-            int64_t ky[NAMAX];
-            int ly[NAMAX];
+            // the highest lower index with a key <= this one (its layer + 1, else 0) and the lowest
+            // higher index with a smaller key (its layer - 1, else 15)
+            int lbq = 0, ubq = 15;
             lyp[q] = 0;
             gx::each_lane<0>([&](auto I_) {
                 constexpr int i = decltype(I_)::value;
-                if constexpr (i < NAMAX) {
-                    ky[i] = gx::bcast<i>(kq, sub);
-                    ly[i] = tb.lay[cq[q].dir][i];
-                    lyp[q] |= (uint32_t)ly[i] << (4 * i);
-                }
+                const int64_t ki = gx::bcast<i>(kq, sub);
+                const int li = tb.lay[dq][i < kMaxA ? i : 0];
+                if (i < nq[q] && i < sub && ki <= kq) lbq = li + 1;
+                if (i < nq[q] && i > sub && ki < kq && ubq == 15) ubq = li - 1;
+                if constexpr (i < NAMAX) lyp[q] |= (uint32_t)li << (4 * i);
             });
-            bnd[q] = block_bounds<NAMAX>(ky, ly, nq[q]);
-            cand[q] = hull_min_mask<NAMAX>(ky, ly, nq[q], lo, hi);
+            const int64_t below = gx::mov<gx::kRowShr + 1>(grp_min_up(vq && lq >= lo ? kq : INT64_MAX, sub));
+            const int64_t above = gx::mov<gx::kRowShl + 1>(grp_min_down(vq && lq <= hi ? kq : INT64_MAX, sub));
+            const bool okq =
+                vq && (lq < lo || sub == 0 || kq < below) && (lq > hi || sub == kGroup - 1 || kq <= above);
+            cand[q] = (uint32_t)((__ballot(okq) >> gbase) & 0xffu);
+            const uint32_t myb = (uint32_t)(lbq | ubq << 4);
+            bnd[q] = 0;
+            gx::each_lane<0>([&](auto I_) {
+                constexpr int i = decltype(I_)::value;
+                if constexpr (i < NAMAX) bnd[q] |= (uint64_t)gx::bcast<i>(myb, sub) << (8 * i);
+            });
         }
         auto lay_of = [&](int q, int jj) { return (int)((lyp[q] >> (4 * jj)) & 15u); };
         auto inside = [&](int q, int jj, int b, int t) {
