@@ -7,6 +7,7 @@ import gen
 import oracle
 import paper_2507_13375_amd as la
 from gpu_util import DeviceRun, dev, host, say, tier_flips_at_bin_edges, torch
+from helpers import make_instance
 
 pytestmark = pytest.mark.gpu
 
@@ -204,7 +205,7 @@ def _heights(T):
 
 @pytest.mark.parametrize("kind", ["untiled", "tiles"])
 def test_large_nets_elmore_adjoint_and_eq5(kind):
-    # Nets of at most 256 layer-assignment nodes take the one-wavefront runs; nets of up to 1024
+    # Nets of at most 128 layer-assignment nodes take the one-wavefront runs; nets of up to 1024
     # nodes and height below 128 the workgroup tiles; the others (more than 1024 nodes or height
     # 128 or more) the per-level kernels (one launch per dense level, one workgroup over the sparse
     # top levels).  Each instance mixes wavefront-run nets with nets of one of the other two
@@ -219,10 +220,10 @@ def test_large_nets_elmore_adjoint_and_eq5(kind):
     net_h = np.zeros(T.nets, np.int64)
     np.maximum.at(net_h, np.searchsorted(T.net_ptr, np.arange(T.nodes), side="right") - 1, h)
     untiled = (sizes > 1024) | (net_h >= 128)
-    tiled = ~untiled & (sizes > 256)
+    tiled = ~untiled & (sizes > 128)
     say("%s: %d untiled, %d tile, %d wavefront-run nets (largest %d nodes, tallest %d levels)" % (
         kind, untiled.sum(), tiled.sum(), T.nets - untiled.sum() - tiled.sum(), sizes.max(), net_h.max() + 1))
-    assert (untiled if kind == "untiled" else tiled).sum() >= 3 and (sizes <= 256).sum() >= 100
+    assert (untiled if kind == "untiled" else tiled).sum() >= 3 and (sizes <= 128).sum() >= 100
     P = oracle.Params(T)
     R, C = oracle.rc(T, P, None)
     S, t, d = oracle.elmore(T, R, C)
@@ -262,6 +263,47 @@ def test_large_nets_elmore_adjoint_and_eq5(kind):
     exact = ~bad_net[net_of[:T.nodes]]
     assert (swg[exact] == w["seg_w"][exact]).all() and (lg[exact] == w["lam"][exact]).all()
     say("%s Eq. 5: %d of %d nodes in nets with identical pin weights" % (kind, exact.sum(), T.nodes))
+
+
+def test_wavefront_run_limits():
+    # chains of 128 nodes (heights 0-127: one full run, both lane slots), 65 and 64 nodes and two
+    # small nets: runs of 128, 65 and 69 nodes, at the largest height a run holds and at the
+    # boundary of its two lane slots; forward, reverse sweep and adjoint-form weights
+    nets = []
+    for i, n in enumerate((128, 65, 64, 2, 3)):
+        nodes = [(0, 2 * i, -1, "driver")] + [(k, 2 * i, k - 1, "sink") for k in range(1, n)]
+        nets.append((nodes, None))
+    inst = make_instance(nets, X=160, Y=16, L=8, budget_fs=[-20000] * len(nets))
+    T = oracle.Tree(inst)
+    assert np.diff(T.net_ptr).tolist() == [128, 65, 64, 2, 3] and _heights(T).max() == 127
+    P = oracle.Params(T)
+    R, C = oracle.rc(T, P, None)
+    S, t, d = oracle.elmore(T, R, C)
+    g = DeviceRun(inst)
+    dg = g.elmore()
+    _rel_close(host(dg)[:T.sinks], d, REL, "delay")
+    rng = np.random.default_rng(31)
+    dslack = rng.uniform(0, 1, T.sinks).astype(np.float32)
+    G, Sig, dR, dC = oracle.elmore_adjoint(T, R, C, S, -dslack.astype(np.float64))
+    t_ = torch()
+    dRg = t_.empty(T.nodes + T.sinks, dtype=t_.float32, device="cuda")
+    dCg = t_.empty_like(dRg)
+    la.la_elmore_backward(g.b, dev(dslack), dRg, dCg)
+    net_of = _net_of(T)
+    for name, gpu, ref in (("dR", host(dRg), dR), ("dC", host(dCg), dC)):
+        assert _adjoint_tol(gpu, ref, net_of).all(), name
+    w = oracle.adjoint_form_weights(T, P, None)
+    d2 = g.elmore()
+    sw = t_.empty(T.nodes, dtype=t_.uint16, device="cuda")
+    pw = t_.empty(T.sinks, dtype=t_.uint16, device="cuda")
+    lam = t_.empty(T.nodes, dtype=t_.int32, device="cuda")
+    tier = t_.empty(T.nets, dtype=t_.uint8, device="cuda")
+    la.la_timing_weights(g.b, d2, la.LA_WEIGHTS_ADJOINT, sw, pw, lam, tier)
+    swg, pwg, lg = host(sw).astype(np.int64), host(pw).astype(np.int64), host(lam).astype(np.int64)
+    assert np.abs(pwg - w["pin_w"]).max() <= 1
+    assert np.abs(swg - w["seg_w"]).max() <= 1
+    assert (np.abs(lg - w["lam"]) <= 1 + 1e-5 * np.abs(w["lam"])).all()
+    say("run limits: %d nodes, %d sinks, %d nonzero segment weights" % (T.nodes, T.sinks, (swg > 0).sum()))
 
 
 def test_backward_after_reassignment_is_state_error(c1):
