@@ -742,6 +742,7 @@ __global__ void k_net_zero_weights(TreeDev T, const uint16_t *seg_w, const uint1
 }
 
 constexpr int kLdsNB = 2048;   // buckets counted in LDS; more go straight to HBM counters
+constexpr int kPartGroups = 512;   // workgroups of the partition: each adds its bucket counts to HBM once
 
 __global__ void k_tier_count(const int32_t *tier, int32_t ntier, int64_t nets, int32_t cap,
                              const uint8_t *zw, const int32_t *net_ptr, const int32_t *height, int32_t *cnt,
@@ -797,25 +798,29 @@ __global__ void k_tier_scatter(const int32_t *tier, int32_t ntier, int64_t nets,
         }
         return;
     }
-    // one tile of blockDim nets at a time: rank inside the tile, then reserve per bucket
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < nets; i0 += (int64_t)gridDim.x * blockDim.x) {
-        for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
-        __syncthreads();
-        const int64_t i = i0 + threadIdx.x;
-        int32_t q = -1, r = 0;
-        if (i < nets) {
-            const int t = tier ? tier[i] : 0;
-            if (t >= 0 && t < ntier) {
-                q = net_bucket(t, net_ptr[i + 1] - net_ptr[i] > cap, zw[i] != 0, height[net_ptr[i]]);
-                r = atomicAdd(&hist[q], 1);
-            }
-        }
-        __syncthreads();
-        for (int k = threadIdx.x; k < nb; k += blockDim.x)
-            if (hist[k]) base[k] = atomicAdd(&cur[k], hist[k]);
-        __syncthreads();
-        if (q >= 0) out[base[q] + r] = (int32_t)i;
-        __syncthreads();
+    // a workgroup takes a contiguous range of nets: counts them per bucket, reserves each bucket's
+    // span once (one global atomic per bucket and workgroup), then places them, in any order
+    // inside a bucket
+    const int64_t per = (nets + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < nets ? r0 + per : nets;
+    auto bucket = [&](int64_t i) -> int32_t {
+        const int t = tier ? tier[i] : 0;
+        if (t < 0 || t >= ntier) return -1;
+        return net_bucket(t, net_ptr[i + 1] - net_ptr[i] > cap, zw[i] != 0, height[net_ptr[i]]);
+    };
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const int32_t q = bucket(i);
+        if (q >= 0) atomicAdd(&hist[q], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += blockDim.x)
+        if (hist[k]) base[k] = atomicAdd(&cur[k], hist[k]);
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const int32_t q = bucket(i);
+        if (q >= 0) out[atomicAdd(&base[q], 1)] = (int32_t)i;
     }
 }
 
@@ -1119,9 +1124,9 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     });
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb + 1);
     LA_TIMED(b, "k_tier_count", b->stream,
-             hipLaunchKernelGGL(k_tier_count, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, batch, ntier,
-                                b->nets, b->tune.tile_nodes, b->net_zw, b->net_ptr, b->height, b->tier_cnt,
-                                b->tier_cnt + nb));
+             hipLaunchKernelGGL(k_tier_count, dim3(std::min(grid1d(b->nets), kPartGroups)), dim3(256), 0, b->stream,
+                                batch, ntier, b->nets, b->tune.tile_nodes, b->net_zw, b->net_ptr, b->height,
+                                b->tier_cnt, b->tier_cnt + nb));
     // the counts (and the count of nets whose batch index is out of range) before anything reads
     // the partition: the net list holds only the nets of valid batches
     LA_HIP(hipGetLastError());
@@ -1132,9 +1137,9 @@ la_status assign_batched(la_batch *b, const la_weights *w, int32_t *H, const int
     hipLaunchKernelGGL(k_tier_offsets, dim3(1), dim3(1024), 0, b->stream, b->tier_cnt, nb, b->tier_off, b->tier_cur,
                        b->claim, R * ntier);
     LA_TIMED(b, "k_tier_scatter", b->stream,
-             hipLaunchKernelGGL(k_tier_scatter, dim3(grid1d(b->nets)), dim3(256), 0, b->stream, batch, ntier,
-                                b->nets, b->tune.tile_nodes, b->net_zw, b->net_ptr, b->height, b->tier_cur,
-                                b->tier_nets));
+             hipLaunchKernelGGL(k_tier_scatter, dim3(std::min(grid1d(b->nets), kPartGroups)), dim3(256), 0,
+                                b->stream, batch, ntier, b->nets, b->tune.tile_nodes, b->net_zw, b->net_ptr,
+                                b->height, b->tier_cur, b->tier_nets));
     // work-queue claims of each batch's small nets
     {
         const int64_t n = b->nets + 1;
