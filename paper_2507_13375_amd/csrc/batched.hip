@@ -1033,11 +1033,13 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             }
             if (nbig + nsmall == 0) continue;
             const bool fused = nsmall >= b->tune.fuse_nets;
+            // the change list holds the big nets' moves and, unfused, the small nets'
+            const bool listed = !fused || nbig > 0;
             a.D = dcur;
             if (fused)
                 LA_TIMED(b, "k_copy_i32", s,
                          hipLaunchKernelGGL(k_copy_i32, dim3(cgrid), dim3(256), 0, s, dalt, dcur, b->Eg));
-            hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, b->chg_count, 1);
+            if (listed) hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, s, b->chg_count, 1);
             BArgs ba;
             ba.tier_nets = b->tier_nets;
             ba.tier_off = b->tier_off;
@@ -1066,8 +1068,7 @@ la_status enqueue_rounds(la_batch *b, const la_weights *w, int32_t *H, const int
             ba.cl = ChangeList{b->chg_node, b->chg_old, b->chg_new, b->chg_count};
             ba.Dw = fused ? dalt : nullptr;
             st = launch_batched(b, a, ba, nbig, nsmall, s);
-            // the change list holds the big nets' moves (and, unfused, the small nets')
-            if (st == LA_OK) st = commit_changed(b, fused ? dalt : dcur);
+            if (st == LA_OK && listed) st = commit_changed(b, fused ? dalt : dcur);
             if (fused) std::swap(dcur, dalt);
         }
         if (st == LA_OK) st = history_update(b, dcur, H, w->hist_inc);
